@@ -1,0 +1,219 @@
+/*
+ * sfgmres.h -- C ABI of the MI355X (gfx950) sketched-FGMRES solver.
+ *
+ * Solves A x = b for a square sparse nonsymmetric A in CSR form by flexible
+ * GMRES (Guettel & Pearson, "Stabilizing randomized GMRES through flexible
+ * GMRES", arXiv 2506.18408, Algorithm 1) whose variable preconditioner is one
+ * cycle of sketched GMRES (eq. (1.2) and Section 3): a truncated-Arnoldi
+ * Krylov basis B_k of K_k(A, v_j), the sparse sign sketch S, and the sketched
+ * least-squares solve z_j = B_k (S A B_k)^+ (S v_j), with the inner dimension
+ * k limited by the rules C1 (k <= m), C2 (cond(S A B_k) <= threshold) and C3
+ * (the FGMRES residual predicted by the bound of eq. (2.2) is below tol).
+ *
+ * Conventions for every entry point
+ *  - All n- and nnz-sized arrays are DEVICE pointers (HIP device memory on
+ *    the current device), owned by the caller, which must keep them alive
+ *    and unmodified until the call returns.  Host arrays are marked "host".
+ *  - Every call enqueues its GPU work on the caller's HIP stream `stream`
+ *    (NULL = the default stream) and returns after that work is complete.
+ *  - The library allocates no device memory: the caller provides one
+ *    workspace of at least the size returned by sfgmres_workspace_bytes,
+ *    256-byte aligned.  It allocates only a small pinned host status block
+ *    per handle (in sfgmres_create).
+ *  - Return codes: 0 = success; > 0 = success with a warning (the result is
+ *    valid); < 0 = error, in which case output arrays may be partially
+ *    written and sfgmres_last_error(h) describes the problem.  No C++
+ *    exception crosses this interface.
+ *  - A handle serialises its calls: one call at a time per handle; distinct
+ *    handles may be used from distinct host threads.
+ */
+#ifndef SFGMRES_H
+#define SFGMRES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- return codes ---------------------------------------------------- */
+#define SFGMRES_OK               0   /* converged to tol                                  */
+#define SFGMRES_NOT_CONVERGED    1   /* max_outer reached; x holds the best (last) iterate */
+#define SFGMRES_ERR_INVALID     -1   /* invalid argument                                   */
+#define SFGMRES_ERR_HIP         -2   /* a HIP runtime call failed                          */
+#define SFGMRES_ERR_WORKSPACE   -3   /* workspace missing, too small or misaligned         */
+#define SFGMRES_ERR_NONFINITE   -4   /* NaN/Inf met in a norm or in the outer recurrence   */
+#define SFGMRES_ERR_BREAKDOWN   -5   /* S A v_j = 0: the inner problem is singular          */
+#define SFGMRES_ERR_TIMEOUT     -6   /* the device made no progress for 60 s                */
+
+/* ---- precision modes ------------------------------------------------- */
+#define SFGMRES_FP64   0  /* everything in float64                                           */
+#define SFGMRES_MIXED  1  /* float32 A values, inner SpMV inputs/outputs and inner basis B;
+                             float64 sketch accumulation, sketched QR/least squares,
+                             z = B y accumulation, outer SpMV, Gram-Schmidt and Givens       */
+
+/* ---- inner stop reasons (sfgmres_info.stop_reason) ------------------- */
+#define SFGMRES_STOP_C1         1  /* k reached m                                  */
+#define SFGMRES_STOP_C2         2  /* cond estimate of S A B_i exceeded threshold: k = i-1 */
+#define SFGMRES_STOP_C3         3  /* predicted outer residual <= tol * ||b||     */
+#define SFGMRES_STOP_BREAKDOWN  4  /* truncated Arnoldi produced an exact zero     */
+#define SFGMRES_STOP_FORCED     5  /* k replayed from sfgmres_info.forced_k        */
+
+/* Limits checked by every entry point. */
+#define SFGMRES_MAX_ZETA   16     /* nonzeros per sketch column                   */
+#define SFGMRES_MAX_S      2048   /* sketch rows                                  */
+#define SFGMRES_MAX_M      512    /* inner basis dimension                        */
+#define SFGMRES_MAX_T      8      /* Arnoldi truncation window                    */
+#define SFGMRES_MAX_OUTER  2000   /* outer FGMRES steps                           */
+
+/* A in CSR: int32 row_ptr[n+1] (row_ptr[0] = 0, non-decreasing,
+ * row_ptr[n] = nnz), int32 col_idx[nnz] in [0, n), float64 val[nnz].
+ * Columns need not be sorted; duplicates are summed by the SpMV. */
+typedef struct sfgmres_csr {
+  int64_t n;
+  int64_t nnz;
+  const int32_t* row_ptr;
+  const int32_t* col_idx;
+  const double* val;
+} sfgmres_csr;
+
+typedef struct sfgmres_options {
+  int32_t precision;            /* SFGMRES_FP64 (default) or SFGMRES_MIXED                       */
+  int32_t max_outer;            /* outer FGMRES steps, default 100                               */
+  double  cond_threshold;       /* C2 threshold on the condition estimate, default 1e15 (Sec. 3) */
+  int32_t record_true_residual; /* 1: also compute ||b - A x_j|| after every outer step (+1 SpMV
+                                   and one n x j combination per step), default 0                */
+  int32_t profile;              /* 1: time every inner SpMV+sketch launch with HIP events,
+                                   default 0                                                     */
+  int32_t lookahead;            /* inner steps enqueued ahead of the last one the device has
+                                   finished deciding; 0 = default (4)                            */
+  int32_t reserved[4];
+} sfgmres_options;
+
+/* Solve diagnostics.  Scalars are always written; each per-step array is a
+ * HOST array of the stated length, or NULL to skip it. */
+typedef struct sfgmres_info {
+  int32_t outer_iters;              /* J, outer steps taken                          */
+  int32_t converged;                /* 1 if the implicit residual reached tol        */
+  int32_t total_inner;              /* sum of the inner dimensions k_j               */
+  int32_t status;                   /* return code of the call                       */
+  double  rel_residual;             /* |g_{J+1}| / ||b||, the minimised residual     */
+  double  true_rel_residual;        /* ||b - A x|| / ||b|| of the returned x (float64) */
+  double* residual_history;         /* [max_outer+1]: |g_{j+1}| / ||b||, entry 0 = ||r0||/||b|| */
+  double* true_residual_history;    /* [max_outer]: ||b - A x_j||/||b|| (record_true_residual) */
+  int32_t* inner_k;                 /* [max_outer]: k_j                              */
+  int32_t* stop_reason;             /* [max_outer]: SFGMRES_STOP_*                   */
+  double* cond_at_stop;             /* [max_outer]: condition estimate of S A B_{k_j} */
+  double* inner_sketched_residual;  /* [max_outer]: ||S(v_j - A z_j)|| at k_j        */
+  double* inner_true_residual;      /* [max_outer]: ||v_j - A z_j||                  */
+  double* ffom_residual;            /* [max_outer]: FFOM residual norm, eq. (2.1), absolute */
+  const int32_t* forced_k;          /* input [max_outer] or NULL: replay these inner
+                                       dimensions (k_j steps, no C1-C3 tests)         */
+  double  spmv_ms;                  /* profile: summed duration of the inner SpMV+sketch
+                                       launches that did work                          */
+  int64_t spmv_launches;            /* profile: number of those launches              */
+  double  solve_ms;                 /* host wall time of the call                      */
+  double  reserved[6];
+} sfgmres_info;
+
+typedef struct sfgmres_ctx* sfgmres_handle;
+
+/* Fill *opt with the defaults listed above.  Returns SFGMRES_OK. */
+int sfgmres_default_options(sfgmres_options* opt);
+
+/* Workspace bytes needed by sfgmres_solve (adjoint = 0) or
+ * sfgmres_solve_adjoint (adjoint = 1) for a problem with n unknowns, nnz
+ * nonzeros, inner dimension m, window t, sketch rows s under *opt (NULL =
+ * defaults).  Writes the size to *bytes. */
+int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s,
+                            const sfgmres_options* opt, int32_t adjoint, size_t* bytes);
+
+/* Create a handle bound to the current HIP device. */
+int sfgmres_create(sfgmres_handle* h);
+
+/* Release a handle (NULL is ignored). */
+void sfgmres_destroy(sfgmres_handle h);
+
+/* Text of the last error on h (never NULL; "" if none).  Valid until the
+ * next call on h. */
+const char* sfgmres_last_error(sfgmres_handle h);
+
+/* Solve A x = b (Algorithm 1 with an sGMRES inner cycle, Section 3).
+ *   A      : CSR as above (device arrays).
+ *   b      : [n] right-hand side.
+ *   x0     : [n] initial guess or NULL for zero.
+ *   x      : [n] output solution (may alias x0).
+ *   m      : inner basis dimension cap k_max (rule C1), 1 <= m < s.
+ *   t      : Arnoldi truncation window (Section 4.1), 0 <= t <= min(m, SFGMRES_MAX_T);
+ *            t = 0 builds a normalised power basis.
+ *   s      : sketch rows, m < s <= SFGMRES_MAX_S.
+ *   zeta   : nonzeros per sketch column, 1 <= zeta <= min(s, SFGMRES_MAX_ZETA).
+ *   tol    : relative tolerance on ||b - A x|| / ||b||, > 0.
+ *   seed   : 64-bit seed of the sketch (Philox4x32-10 key).
+ *   opt    : options or NULL for defaults.
+ *   info   : diagnostics (host struct) or NULL.
+ *   ws, ws_bytes : device workspace (see above).
+ *   stream : hipStream_t of the caller, as void*.
+ * Returns SFGMRES_OK or SFGMRES_NOT_CONVERGED with x written, or an error.
+ * ||b|| = 0 returns x = 0 and OK; ||b - A x0|| <= tol ||b|| returns x = x0. */
+int sfgmres_solve(sfgmres_handle h, const sfgmres_csr* A, const double* b, const double* x0,
+                  double* x, int32_t m, int32_t t, int32_t s, int32_t zeta, double tol,
+                  uint64_t seed, const sfgmres_options* opt, sfgmres_info* info,
+                  void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint solve for reverse-mode differentiation of x = A^{-1} b: builds
+ * CSR(A^T) in the workspace, solves A^T lambda = g with the same method and
+ * parameters (same sketch seed), and, if x and grad_val are non-NULL, writes
+ * grad_val[p] = -lambda[row(p)] * x[col(p)] for every nonzero p of A (the
+ * gradient of L with respect to A's values when g = dL/dx); dL/db = lambda.
+ *   g       : [n] input, lambda : [n] output, x : [n] forward solution or NULL,
+ *   grad_val: [nnz] output or NULL.
+ * Other arguments and return codes as sfgmres_solve; info describes the
+ * transposed solve. */
+int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* g,
+                          double* lambda, const double* x, double* grad_val, int32_t m,
+                          int32_t t, int32_t s, int32_t zeta, double tol, uint64_t seed,
+                          const sfgmres_options* opt, sfgmres_info* info, void* ws,
+                          size_t ws_bytes, void* stream);
+
+/* Write CSR(A^T) and the value map perm (val_T[q] = val[perm[q]]): row_ptr_t
+ * [n+1], col_idx_t [nnz], val_t [nnz] (may be NULL), perm [nnz] -- device
+ * arrays.  Rows of A^T list their columns in ascending order.  Needs
+ * sfgmres_transpose_workspace_bytes of workspace. */
+int sfgmres_transpose_workspace_bytes(int64_t n, int64_t nnz, size_t* bytes);
+int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t,
+                      int32_t* col_idx_t, double* val_t, int32_t* perm, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* The sketch S (s x n) defined by (seed, s, zeta): for every column r,
+ * rows[r*zeta + d] in [0, s) (distinct over d) and signs[r*zeta + d] in
+ * {-1, +1}; the nonzero value is signs/sqrt(zeta).  Column r's entries come
+ * from Philox4x32-10 with key (seed mod 2^32, seed div 2^32) and counter
+ * (r, block, 0, 0) by Floyd's sampling.  rows [n*zeta] int32, signs [n*zeta]
+ * int8, device arrays. */
+int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta,
+                               uint64_t seed, int32_t* rows, int8_t* signs, void* stream);
+
+/* out[s] = S w for w [n] (float64), with the same kernel family the solver
+ * uses for its sketches.  Needs sfgmres_sketch_workspace_bytes(s). */
+int sfgmres_sketch_workspace_bytes(int32_t s, size_t* bytes);
+int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, uint64_t seed,
+                         const double* w, double* out, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* One inner step's fused kernel on its own: w = scale * A u, c = S w (s
+ * entries), dots[l] = <w, U_l> for the `nwin` vectors U_l (columns of the
+ * n x nwin column-major array U, leading dimension ldu), norm2 = ||w||^2.
+ * u, w, U: float64 [n].  c: [s], dots: [nwin] (nwin <= SFGMRES_MAX_T),
+ * norm2: [1] device outputs.  Needs sfgmres_spmv_workspace_bytes. */
+int sfgmres_spmv_workspace_bytes(int64_t n, int64_t nnz, int32_t s, size_t* bytes);
+int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u, double scale,
+                        double* w, int32_t s, int32_t zeta, uint64_t seed, const double* U,
+                        int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2,
+                        void* ws, size_t ws_bytes, void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SFGMRES_H */

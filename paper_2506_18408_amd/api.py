@@ -1,0 +1,297 @@
+"""PyTorch-facing binding of the sketched-FGMRES HIP library.
+
+Tensors live on the current HIP device; PyTorch provides the device memory
+(inputs, outputs and the one workspace blob) and the stream
+(``torch.cuda.current_stream()``).  Every function marshals arguments into
+the C ABI of include/sfgmres.h and raises ``SFGMRESError`` on a negative
+return code.  There is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import warnings
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+class SFGMRESError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"sfgmres error {code}: {msg}")
+        self.code = code
+
+
+@dataclasses.dataclass
+class SolveParams:
+    """Method parameters (names follow the paper's notation where it has one).
+
+    m: inner sGMRES basis cap k_max (rule C1); t: Arnoldi truncation window;
+    s: sketch rows; zeta: nonzeros per sketch column; tol: relative
+    tolerance on ||b - A x|| / ||b||; seed: sketch seed; cond_threshold: C2
+    threshold; precision: "fp64" or "mixed".
+    """
+    m: int = 30
+    t: int = 2
+    s: int = 60
+    zeta: int = 8
+    tol: float = 1e-8
+    seed: int = 0
+    max_outer: int = 100
+    cond_threshold: float = 1e15
+    precision: str = "fp64"
+    lookahead: int = 0
+
+
+_HANDLES = {}
+
+
+def _handle(device: torch.device) -> C.c_void_p:
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _HANDLES.get(idx)
+    if h is None:
+        lib = L.load()
+        h = C.c_void_p()
+        with torch.cuda.device(idx):
+            rc = lib.sfgmres_create(C.byref(h))
+        if rc != 0:
+            raise SFGMRESError(rc, "sfgmres_create failed")
+        _HANDLES[idx] = h
+    return h
+
+
+def _check(rc: int, h) -> int:
+    if rc < 0:
+        raise SFGMRESError(rc, L.load().sfgmres_last_error(h).decode())
+    return rc
+
+
+def _ptr(t) -> int | None:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _csr(row_ptr, col_idx, val) -> L.Csr:
+    n = row_ptr.numel() - 1
+    for name, tns, dt in (("row_ptr", row_ptr, torch.int32), ("col_idx", col_idx, torch.int32),
+                          ("val", val, torch.float64)):
+        if tns.dtype != dt or not tns.is_cuda or not tns.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} tensor on the GPU")
+    if col_idx.numel() != val.numel():
+        raise ValueError("col_idx and val differ in length")
+    return L.Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr())
+
+
+def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Options:
+    o = L.Options()
+    L.load().sfgmres_default_options(C.byref(o))
+    o.precision = {"fp64": L.FP64, "mixed": L.MIXED}[p.precision]
+    o.max_outer = p.max_outer
+    o.cond_threshold = p.cond_threshold
+    o.record_true_residual = 1 if record_true_residual else 0
+    o.profile = 1 if profile else 0
+    o.lookahead = p.lookahead
+    return o
+
+
+class _InfoBuffers:
+    def __init__(self, J: int, forced_k=None):
+        self.residual_history = np.full(J + 1, np.nan)
+        self.true_residual_history = np.full(J, np.nan)
+        self.inner_k = np.zeros(J, dtype=np.int32)
+        self.stop_reason = np.zeros(J, dtype=np.int32)
+        self.cond_at_stop = np.full(J, np.nan)
+        self.inner_sketched_residual = np.full(J, np.nan)
+        self.inner_true_residual = np.full(J, np.nan)
+        self.ffom_residual = np.full(J, np.nan)
+        self.forced = None
+        if forced_k is not None:
+            fk = np.zeros(J, dtype=np.int32)
+            fk[:min(J, len(forced_k))] = np.asarray(forced_k, dtype=np.int32)[:J]
+            self.forced = fk
+        self.info = L.Info()
+        dp = C.POINTER(C.c_double)
+        ip = C.POINTER(C.c_int32)
+        self.info.residual_history = self.residual_history.ctypes.data_as(dp)
+        self.info.true_residual_history = self.true_residual_history.ctypes.data_as(dp)
+        self.info.inner_k = self.inner_k.ctypes.data_as(ip)
+        self.info.stop_reason = self.stop_reason.ctypes.data_as(ip)
+        self.info.cond_at_stop = self.cond_at_stop.ctypes.data_as(dp)
+        self.info.inner_sketched_residual = self.inner_sketched_residual.ctypes.data_as(dp)
+        self.info.inner_true_residual = self.inner_true_residual.ctypes.data_as(dp)
+        self.info.ffom_residual = self.ffom_residual.ctypes.data_as(dp)
+        self.info.forced_k = self.forced.ctypes.data_as(ip) if self.forced is not None else None
+
+    def to_dict(self, rc: int) -> dict:
+        J = self.info.outer_iters
+        return dict(
+            status=rc,
+            outer_iters=J,
+            converged=bool(self.info.converged),
+            total_inner=self.info.total_inner,
+            rel_residual=self.info.rel_residual,
+            true_rel_residual=self.info.true_rel_residual,
+            residual_history=self.residual_history[:J + 1].copy(),
+            true_residual_history=self.true_residual_history[:J].copy(),
+            inner_k=self.inner_k[:J].copy(),
+            stop_reason=[L.STOP_REASONS.get(int(r), "?") for r in self.stop_reason[:J]],
+            cond_at_stop=self.cond_at_stop[:J].copy(),
+            inner_sketched_residual=self.inner_sketched_residual[:J].copy(),
+            inner_true_residual=self.inner_true_residual[:J].copy(),
+            ffom_residual=self.ffom_residual[:J].copy(),
+            spmv_ms=self.info.spmv_ms,
+            spmv_launches=self.info.spmv_launches,
+            solve_ms=self.info.solve_ms,
+        )
+
+
+_WS = {}
+
+
+def _workspace(nbytes: int, device, key: str) -> torch.Tensor:
+    buf = _WS.get((key, device))
+    if buf is None or buf.numel() < nbytes:
+        _WS.pop((key, device), None)
+        buf = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+        _WS[(key, device)] = buf
+    return buf
+
+
+def release_workspaces() -> None:
+    _WS.clear()
+
+
+def workspace_bytes(n, nnz, p: SolveParams, adjoint=False) -> int:
+    out = C.c_size_t()
+    o = _options(p)
+    rc = L.load().sfgmres_workspace_bytes(n, nnz, p.m, p.t, p.s, C.byref(o), 1 if adjoint else 0,
+                                          C.byref(out))
+    if rc != 0:
+        raise SFGMRESError(rc, "invalid sizes for the workspace query")
+    return out.value
+
+
+def solve(row_ptr, col_idx, val, b, x0=None, params: SolveParams | None = None, *, out=None,
+          forced_k=None, record_true_residual=False, profile=False, **kw):
+    """Solve A x = b; returns (x, info dict).  ``kw`` overrides fields of params."""
+    p = dataclasses.replace(params or SolveParams(), **kw)
+    A = _csr(row_ptr, col_idx, val)
+    dev = b.device
+    if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != A.n:
+        raise ValueError("b must be a contiguous float64 tensor of length n")
+    if x0 is not None and (x0.dtype != torch.float64 or x0.numel() != A.n):
+        raise ValueError("x0 must be a float64 tensor of length n")
+    x = out if out is not None else torch.empty_like(b)
+    nbytes = workspace_bytes(A.n, A.nnz, p)
+    ws = _workspace(nbytes, dev, "solve")
+    h = _handle(dev)
+    opt = _options(p, record_true_residual, profile)
+    ib = _InfoBuffers(p.max_outer, forced_k)
+    rc = L.load().sfgmres_solve(h, C.byref(A), b.data_ptr(), _ptr(x0), x.data_ptr(), p.m, p.t, p.s,
+                                p.zeta, p.tol, p.seed & (2**64 - 1), C.byref(opt), C.byref(ib.info),
+                                ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, h)
+    if rc == L.NOT_CONVERGED:
+        warnings.warn("sfgmres: max_outer reached before tol", RuntimeWarning)
+    return x, ib.to_dict(rc)
+
+
+def solve_adjoint(row_ptr, col_idx, val, g, x=None, params: SolveParams | None = None, *,
+                  want_grad_val=True, forced_k=None, **kw):
+    """Solve A^T lam = g; returns (lam, grad_val or None, info dict) with
+    grad_val[p] = -lam[row(p)] x[col(p)] when x is given."""
+    p = dataclasses.replace(params or SolveParams(), **kw)
+    A = _csr(row_ptr, col_idx, val)
+    dev = g.device
+    lam = torch.empty_like(g)
+    gv = torch.empty_like(val) if (want_grad_val and x is not None) else None
+    nbytes = workspace_bytes(A.n, A.nnz, p, adjoint=True)
+    ws = _workspace(nbytes, dev, "adjoint")
+    h = _handle(dev)
+    opt = _options(p)
+    ib = _InfoBuffers(p.max_outer, forced_k)
+    rc = L.load().sfgmres_solve_adjoint(h, C.byref(A), g.contiguous().data_ptr(), lam.data_ptr(),
+                                        _ptr(x) if gv is not None else None, _ptr(gv), p.m, p.t,
+                                        p.s, p.zeta, p.tol, p.seed & (2**64 - 1), C.byref(opt),
+                                        C.byref(ib.info), ws.data_ptr(), ws.numel(), _stream())
+    _check(rc, h)
+    if rc == L.NOT_CONVERGED:
+        warnings.warn("sfgmres adjoint: max_outer reached before tol", RuntimeWarning)
+    return lam, gv, ib.to_dict(rc)
+
+
+def transpose(row_ptr, col_idx, val=None):
+    """CSR of A^T and the value permutation (val_t = val[perm])."""
+    if val is None:
+        val = torch.zeros(col_idx.numel(), dtype=torch.float64, device=col_idx.device)
+        want_val = False
+    else:
+        want_val = True
+    A = _csr(row_ptr, col_idx, val)
+    dev = row_ptr.device
+    rp_t = torch.empty(A.n + 1, dtype=torch.int32, device=dev)
+    col_t = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    perm = torch.empty(max(A.nnz, 1), dtype=torch.int32, device=dev)
+    val_t = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev) if want_val else None
+    need = C.c_size_t()
+    _check(L.load().sfgmres_transpose_workspace_bytes(A.n, A.nnz, C.byref(need)), None)
+    ws = _workspace(need.value, dev, "transpose")
+    h = _handle(dev)
+    _check(L.load().sfgmres_transpose(h, C.byref(A), rp_t.data_ptr(), col_t.data_ptr(),
+                                      _ptr(val_t), perm.data_ptr(), ws.data_ptr(), ws.numel(),
+                                      _stream()), h)
+    nnz = A.nnz
+    return rp_t, col_t[:nnz], (val_t[:nnz] if val_t is not None else None), perm[:nnz]
+
+
+def sketch_materialize(n: int, s: int, zeta: int, seed: int, device="cuda"):
+    """(rows [n, zeta] int32, signs [n, zeta] int8) of the sketch S."""
+    dev = torch.device(device)
+    rows = torch.empty(n * zeta, dtype=torch.int32, device=dev)
+    signs = torch.empty(n * zeta, dtype=torch.int8, device=dev)
+    h = _handle(dev)
+    _check(L.load().sfgmres_sketch_materialize(h, n, s, zeta, seed & (2**64 - 1), rows.data_ptr(),
+                                               signs.data_ptr(), _stream()), h)
+    return rows.view(n, zeta), signs.view(n, zeta)
+
+
+def sketch_apply(w: torch.Tensor, s: int, zeta: int, seed: int) -> torch.Tensor:
+    """S w for a float64 vector w."""
+    n = w.numel()
+    out = torch.empty(s, dtype=torch.float64, device=w.device)
+    need = C.c_size_t()
+    _check(L.load().sfgmres_sketch_workspace_bytes(s, C.byref(need)), None)
+    ws = _workspace(need.value, w.device, "sketch")
+    h = _handle(w.device)
+    _check(L.load().sfgmres_sketch_apply(h, n, s, zeta, seed & (2**64 - 1),
+                                         w.contiguous().data_ptr(), out.data_ptr(), ws.data_ptr(),
+                                         ws.numel(), _stream()), h)
+    return out
+
+
+def spmv_sketch(row_ptr, col_idx, val, u, s, zeta, seed, scale=1.0, U=None):
+    """One fused inner-step kernel: (w = scale A u, S w, <w, U[:, l]>, ||w||^2)."""
+    A = _csr(row_ptr, col_idx, val)
+    dev = u.device
+    w = torch.empty(A.n, dtype=torch.float64, device=dev)
+    c = torch.empty(s, dtype=torch.float64, device=dev)
+    nrm = torch.empty(1, dtype=torch.float64, device=dev)
+    nwin = 0 if U is None else U.shape[1]
+    dots = torch.empty(max(nwin, 1), dtype=torch.float64, device=dev)
+    Ucm = None
+    if U is not None:
+        Ucm = U.t().contiguous()  # column-major storage: column l contiguous
+    need = C.c_size_t()
+    _check(L.load().sfgmres_spmv_workspace_bytes(A.n, A.nnz, s, C.byref(need)), None)
+    ws = _workspace(need.value, dev, "spmv")
+    h = _handle(dev)
+    _check(L.load().sfgmres_spmv_sketch(h, C.byref(A), u.contiguous().data_ptr(), scale,
+                                        w.data_ptr(), s, zeta, seed & (2**64 - 1), _ptr(Ucm),
+                                        A.n, nwin, c.data_ptr(), dots.data_ptr(), nrm.data_ptr(),
+                                        ws.data_ptr(), ws.numel(), _stream()), h)
+    return w, c, dots[:nwin], nrm[0]

@@ -1,0 +1,230 @@
+// Internal definitions shared by the sketched-FGMRES HIP kernels and the host
+// driver: device control block, host-visible status block, workspace layout,
+// the Philox4x32-10 generator, the sketch column definition and block
+// reductions.  gfx950 only (64-lane wavefronts).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/sfgmres.h"
+
+namespace sfg {
+
+constexpr int kWave = 64;
+constexpr int kMaxT = SFGMRES_MAX_T;
+constexpr int kMaxZeta = SFGMRES_MAX_ZETA;
+constexpr int kMaxS = SFGMRES_MAX_S;
+constexpr int kMaxM = SFGMRES_MAX_M;
+
+// Fused SpMV: threads per workgroup, LDS product capacity (nonzeros per tile)
+// and the persistent-grid cap.
+constexpr int kSpmvThreads = 256;
+constexpr int kTileCap = 4096;
+constexpr int kMaxGrid = 1024;
+// Partial-sum row layout written by every persistent kernel:
+//   [0, s)              sketch accumulators
+//   [s, s + kMaxT)      dot products
+//   s + kMaxT           squared norm
+//   s + kMaxT + 1       second squared norm / extra scalar
+constexpr int kPartExtra = kMaxT + 2;
+
+// Device control block (lives in the workspace).
+struct DevCtl {
+  // inner cycle
+  int32_t stop_k;        // 0 while the cycle runs, else the chosen dimension k_j
+  int32_t stop_step;     // inner step at which the stop was decided
+  int32_t stop_reason;   // SFGMRES_STOP_*
+  int32_t qr_k;          // columns in the sketched QR
+  int32_t forced_k;      // >0: replay this dimension
+  int32_t m, t, s;
+  int32_t error;         // 0, or a negative SFGMRES_ERR_* raised on the device
+  int32_t pad0;
+  double tol_abs;        // tol * ||b||
+  double cond_threshold;
+  double factor;         // C3 factor: FFOM residual of the previous outer step (beta at j = 1)
+  double ice_smax;       // incremental condition estimate state
+  double ice_znorm;
+  double cond_cur, cond_prev;
+  double rho_cur, rho_prev;   // sketched inner residuals at steps i and i-1
+  double d0norm;
+  // outer
+  double beta, nb;
+  double rhat2;          // ||v_j - A z_j||^2
+  double rho;            // |g_{j+1}|
+  double ffom;
+  double hnext;          // h_{j+1,j}
+  double cs_last;
+  // tickets for last-workgroup reductions (reset by the last workgroup)
+  uint32_t ticket[8];
+};
+
+// Host-visible status block (pinned, device-mapped).
+struct HostStatus {
+  int32_t inner_step_done;   // last inner step whose decision kernel finished
+  int32_t stop_k;            // mirror of DevCtl::stop_k
+  int32_t stop_step;
+  int32_t stop_reason;
+  int32_t outer_j;           // outer step recorded below (1-based)
+  int32_t k;
+  int32_t error;
+  int32_t pad;
+  double rho, ffom, hnext, cond, rho_hat, rhat_true, beta, nb;
+};
+
+// Offsets (bytes) of every workspace region.
+struct Layout {
+  size_t ctl, tiles, part, red, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z, sigma,
+      hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, at_rowptr, at_col, at_val,
+      at_perm, at_cursor, scan_tmp, total;
+  int64_t ld;        // leading dimension (elements) of the n-vectors
+  int64_t ntiles_max;
+  int32_t grid;      // persistent grid size used for the partial buffer
+};
+
+Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t max_outer,
+                   int32_t precision, int32_t adjoint);
+
+// ---------------------------------------------------------------- Philox
+// Philox4x32-10 (Salmon et al., SC'11): four 32-bit counter words, two key
+// words, ten rounds of two 32x32->64 multiplies, Weyl key bumps.
+__device__ __forceinline__ void philox4x32_10(uint32_t& c0, uint32_t& c1, uint32_t& c2,
+                                              uint32_t& c3, uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint32_t lo0 = 0xD2511F53u * c0;
+    const uint32_t hi0 = __umulhi(0xD2511F53u, c0);
+    const uint32_t lo1 = 0xCD9E8D57u * c2;
+    const uint32_t hi1 = __umulhi(0xCD9E8D57u, c2);
+    const uint32_t n0 = hi1 ^ c1 ^ k0;
+    const uint32_t n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+// Column `col` of the sparse sign sketch: rows[d] (distinct, in [0, s)) and
+// negative-sign flags for d < zeta.  ZB = number of Philox blocks generated
+// (zeta <= 4 ZB).  Random word d comes from block d/4, output d%4, counter
+// (col, block, 0, 0); Floyd's sampling: i = s - zeta + d,
+// t = ((w >> 1) * (i + 1)) >> 31, take i if t is already chosen; the sign
+// is negative when w is odd.
+template <int ZB>
+__device__ __forceinline__ void sketch_column(uint32_t col, int s, int zeta, uint32_t k0,
+                                              uint32_t k1, int (&rows)[4 * ZB],
+                                              uint32_t& negmask) {
+  uint32_t w[4 * ZB];
+#pragma unroll
+  for (int b = 0; b < ZB; ++b) {
+    uint32_t c0 = col, c1 = (uint32_t)b, c2 = 0u, c3 = 0u;
+    philox4x32_10(c0, c1, c2, c3, k0, k1);
+    w[4 * b + 0] = c0;
+    w[4 * b + 1] = c1;
+    w[4 * b + 2] = c2;
+    w[4 * b + 3] = c3;
+  }
+  negmask = 0u;
+#pragma unroll
+  for (int d = 0; d < 4 * ZB; ++d) {
+    if (d < zeta) {
+      const uint32_t i = (uint32_t)(s - zeta + d);
+      const uint64_t u = (uint64_t)(w[d] >> 1);
+      int t = (int)((u * (uint64_t)(i + 1u)) >> 31);
+      bool taken = false;
+#pragma unroll
+      for (int e = 0; e < d; ++e) taken |= (rows[e] == t);
+      rows[d] = taken ? (int)i : t;
+      negmask |= (w[d] & 1u) << d;
+    } else {
+      rows[d] = -1;
+    }
+  }
+}
+
+// Scatter +-v into the LDS accumulators of column `col` of S.
+template <int ZB>
+__device__ __forceinline__ void sketch_scatter(double* lds_sk, uint32_t col, double v, int s,
+                                               int zeta, uint32_t k0, uint32_t k1) {
+  int rows[4 * ZB];
+  uint32_t neg;
+  sketch_column<ZB>(col, s, zeta, k0, k1, rows, neg);
+#pragma unroll
+  for (int d = 0; d < 4 * ZB; ++d) {
+    if (d < zeta) {
+      const double a = ((neg >> d) & 1u) ? -v : v;
+      __hip_atomic_fetch_add(&lds_sk[rows[d]], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+  }
+}
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
+  return v;
+}
+
+// Sum of v over the workgroup (fixed order: waves combined in wave order).
+// `scratch` holds blockDim.x/64 doubles.  Every thread gets the result.
+__device__ __forceinline__ double block_sum(double v, double* scratch) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+  v = wave_sum(v);
+  __syncthreads();
+  if (lane == 0) scratch[wid] = v;
+  __syncthreads();
+  double r = 0.0;
+  for (int i = 0; i < nw; ++i) r += scratch[i];
+  __syncthreads();
+  return r;
+}
+
+// Persistent-grid logical block id: consecutive hardware workgroup ids are
+// dealt round-robin to the 8 XCDs, so give each XCD a contiguous range of
+// logical ids (and hence of rows / tiles) to keep gathers inside one L2.
+__device__ __forceinline__ int xcd_logical_block(int b, int nb) {
+  constexpr int kXcd = 8;
+  if (nb % kXcd != 0) return b;
+  return (b % kXcd) * (nb / kXcd) + b / kXcd;
+}
+
+// Last-workgroup detection: every workgroup calls this once after writing
+// its partial results; returns true in exactly one workgroup (the last to
+// arrive), which may then read all partials.  The counter is reset there.
+__device__ __forceinline__ bool last_block_arrival(uint32_t* counter, int nblocks,
+                                                   int* lds_flag) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const uint32_t prev =
+        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    *lds_flag = (prev == (uint32_t)(nblocks - 1)) ? 1 : 0;
+  }
+  __syncthreads();
+  const bool last = *lds_flag != 0;
+  if (last) {
+    __threadfence();
+    if (threadIdx.x == 0)
+      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  return last;
+}
+
+// Stores into the pinned host status block (system scope).
+__device__ __forceinline__ void host_store_i32(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+__device__ __forceinline__ void host_store_f64(double* p, double v) {
+  __hip_atomic_store(reinterpret_cast<unsigned long long*>(p),
+                     (unsigned long long)__double_as_longlong(v), __ATOMIC_RELAXED,
+                     __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
+}  // namespace sfg

@@ -1,0 +1,807 @@
+// Host driver and C ABI of the sketched-FGMRES solver (include/sfgmres.h).
+//
+// One call runs Algorithm 1 of Guettel & Pearson (arXiv 2506.18408) on the
+// caller's stream: the initial residual, then per outer step one sGMRES
+// cycle (Section 3) built from the fused SpMV+sketch kernel, the
+// reduce-and-decide kernel and, for t > 0, the truncated-Arnoldi update, then
+// z_j = B_k y, the outer SpMV, modified Gram-Schmidt, the Givens update and
+// the normalised v_{j+1} with its sketch.  The host stays a few inner steps
+// ahead of the device: every inner kernel is predicated on the device's stop
+// flag, and the host polls a pinned status block (written by the decision
+// kernel) to stop enqueuing once the cycle has ended.  The host synchronises
+// once per outer step to read the minimised residual.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "kernels.hpp"
+
+struct sfgmres_ctx {
+  int device = 0;
+  sfg::HostStatus* hs_host = nullptr;
+  sfg::HostStatus* hs_dev = nullptr;
+  std::string err;
+  std::vector<hipEvent_t> ev;
+};
+
+namespace sfg {
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t J,
+                   int32_t precision, int32_t adjoint) {
+  (void)t;
+  Layout L{};
+  const bool f32 = precision == SFGMRES_MIXED;
+  L.ld = (n + 63) / 64 * 64;
+  L.ntiles_max = nnz / 128 + 2;
+  L.grid = kMaxGrid;
+  const int64_t E = s + kPartExtra;
+  const size_t vt = f32 ? 4 : 8;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.ctl = take(sizeof(DevCtl));
+  L.tiles = take((size_t)(L.ntiles_max + 1) * 4);
+  L.part = take((size_t)kMaxGrid * E * 8);
+  L.red = take((size_t)E * 8);
+  L.qr_V = take((size_t)s * m * 8);
+  L.qr_T = take((size_t)m * m * 8);
+  L.qr_R = take((size_t)m * m * 8);
+  L.qr_d = take((size_t)s * 8);
+  L.qr_c = take(64 * 8);  // small device scalars
+  L.qr_tau = take((size_t)m * 8);
+  L.ice_x = take((size_t)(m + 1) * 8);
+  L.ice_z = take((size_t)(m + 1) * 8);
+  L.sigma = take((size_t)(m + 2) * 8);
+  L.hwin = take((size_t)kMaxT * 8);
+  L.yin = take((size_t)(m + 1) * 8);
+  L.H = take((size_t)(J + 1) * J * 8);
+  L.HR = take((size_t)(J + 1) * J * 8);
+  L.cs = take((size_t)J * 8);
+  L.sn = take((size_t)J * 8);
+  L.g = take((size_t)(J + 1) * 8);
+  L.yout = take((size_t)(J + 1) * 8);
+  L.V = take((size_t)(J + 1) * L.ld * 8);
+  L.Z = take((size_t)J * L.ld * 8);
+  L.B = take((size_t)(m + 1) * L.ld * vt);
+  L.W32 = take(f32 ? (size_t)L.ld * 4 : 0);
+  L.W64 = take((size_t)L.ld * 8);
+  L.X = take((size_t)L.ld * 8);
+  L.val32 = take(f32 ? (size_t)nnz * 4 : 0);
+  if (adjoint) {
+    L.at_rowptr = take((size_t)(n + 1) * 4);
+    L.at_col = take((size_t)nnz * 4);
+    L.at_val = take((size_t)nnz * 8);
+    L.at_perm = take((size_t)nnz * 4);
+    L.at_cursor = take((size_t)(n + 1) * 4);
+    L.scan_tmp = take(transpose_scan_tmp_ints(n) * 4);
+  }
+  L.total = off;
+  return L;
+}
+
+}  // namespace sfg
+
+using namespace sfg;
+
+namespace {
+
+#define SFG_HIP(call)                                                           \
+  do {                                                                          \
+    hipError_t e_ = (call);                                                     \
+    if (e_ != hipSuccess) {                                                     \
+      h->err = std::string(#call) + " failed: " + hipGetErrorString(e_);       \
+      return SFGMRES_ERR_HIP;                                                   \
+    }                                                                           \
+  } while (0)
+
+int fail(sfgmres_handle h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+sfgmres_options defaults() {
+  sfgmres_options o;
+  memset(&o, 0, sizeof(o));
+  o.precision = SFGMRES_FP64;
+  o.max_outer = 100;
+  o.cond_threshold = 1e15;
+  o.record_true_residual = 0;
+  o.profile = 0;
+  o.lookahead = 0;
+  return o;
+}
+
+int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s,
+                 int32_t zeta, double tol, const sfgmres_options& o) {
+  if (n < 1) return fail(h, SFGMRES_ERR_INVALID, "n must be >= 1");
+  if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(h, SFGMRES_ERR_INVALID, "nnz out of range");
+  if (n >= (int64_t)1 << 31) return fail(h, SFGMRES_ERR_INVALID, "n must be < 2^31");
+  if (m < 1 || m > SFGMRES_MAX_M) return fail(h, SFGMRES_ERR_INVALID, "need 1 <= m <= 512");
+  if (s <= m || s > SFGMRES_MAX_S) return fail(h, SFGMRES_ERR_INVALID, "need m < s <= 2048");
+  if (t < 0 || t > m || t > SFGMRES_MAX_T)
+    return fail(h, SFGMRES_ERR_INVALID, "need 0 <= t <= min(m, 8)");
+  if (zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA)
+    return fail(h, SFGMRES_ERR_INVALID, "need 1 <= zeta <= min(s, 16)");
+  if (!(tol > 0.0) || !isfinite(tol)) return fail(h, SFGMRES_ERR_INVALID, "tol must be > 0");
+  if (o.precision != SFGMRES_FP64 && o.precision != SFGMRES_MIXED)
+    return fail(h, SFGMRES_ERR_INVALID, "unknown precision");
+  if (o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
+    return fail(h, SFGMRES_ERR_INVALID, "need 1 <= max_outer <= 2000");
+  if (!(o.cond_threshold > 0.0)) return fail(h, SFGMRES_ERR_INVALID, "cond_threshold must be > 0");
+  return SFGMRES_OK;
+}
+
+int spmv_grid(int64_t ntiles) {
+  int64_t g = std::min<int64_t>(ntiles, kMaxGrid);
+  if (g >= 8) g -= g % 8;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+int rows_grid(int64_t n) {
+  int64_t g = std::min<int64_t>((n + 1023) / 1024, kMaxGrid);
+  if (g >= 8) g -= g % 8;
+  return (int)std::max<int64_t>(g, 1);
+}
+
+int stream_grid(int64_t n) {
+  int64_t g = std::min<int64_t>((n + 1023) / 1024, 2048);
+  return (int)std::max<int64_t>(g, 1);
+}
+
+int32_t tile_width(int64_t nnz) {
+  int64_t w = 128;
+  while (w < 2048 && w * 2 * 1024 <= nnz) w *= 2;
+  return (int32_t)w;
+}
+
+struct Ptrs {
+  DevCtl* ctl;
+  int32_t* tiles;
+  double *part, *red, *V, *T, *R, *d, *scal, *tau, *ice_x, *ice_z, *sigma, *coef, *yin, *H, *HR,
+      *cs, *sn, *g, *yout, *Vb, *Zb, *W64, *X;
+  void* Bb;
+  float *W32, *val32;
+};
+
+Ptrs make_ptrs(char* base, const Layout& L) {
+  Ptrs p;
+  p.ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
+  p.tiles = reinterpret_cast<int32_t*>(base + L.tiles);
+  p.part = reinterpret_cast<double*>(base + L.part);
+  p.red = reinterpret_cast<double*>(base + L.red);
+  p.V = reinterpret_cast<double*>(base + L.qr_V);
+  p.T = reinterpret_cast<double*>(base + L.qr_T);
+  p.R = reinterpret_cast<double*>(base + L.qr_R);
+  p.d = reinterpret_cast<double*>(base + L.qr_d);
+  p.scal = reinterpret_cast<double*>(base + L.qr_c);
+  p.tau = reinterpret_cast<double*>(base + L.qr_tau);
+  p.ice_x = reinterpret_cast<double*>(base + L.ice_x);
+  p.ice_z = reinterpret_cast<double*>(base + L.ice_z);
+  p.sigma = reinterpret_cast<double*>(base + L.sigma);
+  p.coef = reinterpret_cast<double*>(base + L.hwin);
+  p.yin = reinterpret_cast<double*>(base + L.yin);
+  p.H = reinterpret_cast<double*>(base + L.H);
+  p.HR = reinterpret_cast<double*>(base + L.HR);
+  p.cs = reinterpret_cast<double*>(base + L.cs);
+  p.sn = reinterpret_cast<double*>(base + L.sn);
+  p.g = reinterpret_cast<double*>(base + L.g);
+  p.yout = reinterpret_cast<double*>(base + L.yout);
+  p.Vb = reinterpret_cast<double*>(base + L.V);
+  p.Zb = reinterpret_cast<double*>(base + L.Z);
+  p.Bb = base + L.B;
+  p.W32 = reinterpret_cast<float*>(base + L.W32);
+  p.W64 = reinterpret_cast<double*>(base + L.W64);
+  p.X = reinterpret_cast<double*>(base + L.X);
+  p.val32 = reinterpret_cast<float*>(base + L.val32);
+  return p;
+}
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+// Host spin on the pinned status block until `pred` holds; fails after 60 s
+// without the device making progress.
+template <typename Pred>
+bool spin_until(sfgmres_ctx* h, Pred pred) {
+  volatile HostStatus* hs = h->hs_host;
+  int last = hs->inner_step_done;
+  double t0 = now_ms();
+  int spins = 0;
+  while (!pred()) {
+    const int cur = hs->inner_step_done;
+    if (cur != last) {
+      last = cur;
+      t0 = now_ms();
+    }
+    if (++spins > 64) {
+      std::this_thread::yield();
+      if (now_ms() - t0 > 60000.0) return false;
+    }
+  }
+  return true;
+}
+
+int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const double* x0,
+               double* x, int32_t m, int32_t t, int32_t s, int32_t zeta, double tol,
+               uint64_t seed, const sfgmres_options& o, sfgmres_info* info, void* ws,
+               size_t ws_bytes, hipStream_t st) {
+  const double t_start = now_ms();
+  const int64_t n = A->n, nnz = A->nnz;
+  int rc = check_params(h, n, nnz, m, t, s, zeta, tol, o);
+  if (rc) return rc;
+  if (!A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val)) || !b || !x)
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  const Layout L = make_layout(n, nnz, m, t, s, o.max_outer, o.precision, 0);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  char* base = static_cast<char*>(ws);
+  const Ptrs P = make_ptrs(base, L);
+  const bool f32 = o.precision == SFGMRES_MIXED;
+  const int J = o.max_outer;
+  const int ldh = J + 1;
+  const int64_t ld = L.ld;
+  const size_t vt = f32 ? 4 : 8;
+  const int E = s + kPartExtra;
+  const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  const uint32_t k1 = (uint32_t)(seed >> 32);
+  const double inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
+  const int lookahead = o.lookahead > 0 ? o.lookahead : 4;
+  HostStatus* hsd = h->hs_dev;
+  volatile HostStatus* hsh = h->hs_host;
+  auto Bcol = [&](int64_t l) -> void* { return static_cast<char*>(P.Bb) + l * ld * vt; };
+  auto Vcol = [&](int64_t l) { return P.Vb + l * ld; };
+  auto Zcol = [&](int64_t l) { return P.Zb + l * ld; };
+  const int32_t* forced = info ? info->forced_k : nullptr;
+
+  if (info) {
+    info->outer_iters = 0;
+    info->converged = 0;
+    info->total_inner = 0;
+    info->rel_residual = NAN;
+    info->true_rel_residual = NAN;
+    info->spmv_ms = 0.0;
+    info->spmv_launches = 0;
+  }
+  if (o.profile && (int)h->ev.size() < 2 * m) {
+    for (int i = (int)h->ev.size(); i < 2 * m; ++i) {
+      hipEvent_t e;
+      SFG_HIP(hipEventCreate(&e));
+      h->ev.push_back(e);
+    }
+  }
+
+  // ---- setup: control block, nnz-balanced tiles, float32 values ----------
+  const int32_t wt = tile_width(nnz);
+  const int32_t ntiles = (int32_t)(nnz / wt + 1);
+  const int Gp = spmv_grid(ntiles);
+  const int Gn = rows_grid(n);
+  const int G2 = stream_grid(n);
+  memset((void*)hsh, 0, sizeof(HostStatus));
+  SFG_HIP(launch_init_ctl(P.ctl, m, t, s, o.cond_threshold, tol, st));
+  SFG_HIP(launch_tiles(A->row_ptr, n, nnz, wt, P.tiles, ntiles, st));
+  if (f32) SFG_HIP(launch_cast_f32(A->val, P.val32, nnz, st));
+
+  SpmvArgs base_args{};
+  base_args.n = n;
+  base_args.row_ptr = A->row_ptr;
+  base_args.col_idx = A->col_idx;
+  base_args.val = A->val;
+  base_args.tiles = P.tiles;
+  base_args.ntiles = ntiles;
+  base_args.part = P.part;
+  base_args.E = E;
+  base_args.ctl = P.ctl;
+  base_args.hs = hsd;
+  base_args.scale_val = 1.0;
+
+  RqArgs rq{};
+  rq.part = P.part;
+  rq.E = E;
+  rq.s = s;
+  rq.m = m;
+  rq.t = t;
+  rq.inv_sqrt_zeta = inv_sqrt_zeta;
+  rq.ctl = P.ctl;
+  rq.hs = hsd;
+  rq.red = P.red;
+  rq.V = P.V;
+  rq.T = P.T;
+  rq.R = P.R;
+  rq.d = P.d;
+  rq.tau = P.tau;
+  rq.ice_x = P.ice_x;
+  rq.ice_z = P.ice_z;
+  rq.sigma = P.sigma;
+  rq.coef = P.coef;
+
+  // ---- r0 = b - A x0, beta, ||b||, v_1, S v_1 -----------------------------
+  {
+    SpmvArgs a = base_args;
+    a.has_x = x0 != nullptr;
+    a.x = x0;
+    a.w = P.W64;
+    a.b = b;
+    a.out0 = P.g;
+    SFG_HIP(launch_spmv(kModeResid, false, Gp, a, st));
+  }
+  SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, &P.ctl->beta, Vcol(0), Bcol(0), s, zeta, k0,
+                                  k1, P.part, E, st));
+  {
+    RqArgs r = rq;
+    r.G = Gn;
+    r.forced_k = forced ? forced[0] : 0;
+    SFG_HIP(launch_rq(kRqInit, r, st));
+  }
+  SFG_HIP(hipStreamSynchronize(st));
+  if (hsh->error) return fail(h, hsh->error, "non-finite initial residual or right-hand side");
+  const double beta = hsh->beta;
+  const double nb = hsh->nb;
+  if (!isfinite(beta) || !isfinite(nb))
+    return fail(h, SFGMRES_ERR_NONFINITE, "non-finite initial residual or right-hand side");
+
+  auto finish_info = [&](int status, int J_done, bool conv, double rel, double trel) {
+    if (info) {
+      info->outer_iters = J_done;
+      info->converged = conv ? 1 : 0;
+      info->rel_residual = rel;
+      info->true_rel_residual = trel;
+      info->status = status;
+      info->solve_ms = now_ms() - t_start;
+    }
+    return status;
+  };
+
+  if (nb == 0.0) {
+    SFG_HIP(launch_copy_or_zero(nullptr, x, n, st));
+    SFG_HIP(hipStreamSynchronize(st));
+    return finish_info(SFGMRES_OK, 0, true, 0.0, 0.0);
+  }
+  if (info && info->residual_history) info->residual_history[0] = beta / nb;
+  if (beta <= tol * nb) {
+    SFG_HIP(launch_copy_or_zero(x0, x, n, st));
+    SFG_HIP(hipStreamSynchronize(st));
+    return finish_info(SFGMRES_OK, 0, true, beta / nb, beta / nb);
+  }
+
+  // ---- outer FGMRES loop ---------------------------------------------------
+  int J_done = 0;
+  bool conv = false;
+  double rho_last = beta;
+  int total_inner = 0;
+  for (int j = 0; j < J; ++j) {
+    // inner sGMRES cycle, predicated steps with a bounded lookahead
+    hsh->stop_k = 0;
+    hsh->inner_step_done = 0;
+    hsh->stop_step = 0;
+    int enq = 0;
+    for (int i = 0; i < m; ++i) {
+      if (i >= lookahead) {
+        const int need = i - lookahead + 1;
+        if (!spin_until(h, [&] { return hsh->stop_k != 0 || hsh->inner_step_done >= need ||
+                                        hsh->error != 0; })) {
+          return fail(h, SFGMRES_ERR_TIMEOUT, "device made no progress for 60 s");
+        }
+      }
+      if (hsh->stop_k != 0 || hsh->error != 0) break;
+      const int nwin = std::min(t, i + 1);
+      const int l0 = i + 1 - nwin;
+      SpmvArgs a = base_args;
+      a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
+      a.x = Bcol(i);
+      a.scale_ptr = P.sigma + i;
+      a.w = (t == 0) ? Bcol(i + 1) : (f32 ? static_cast<void*>(P.W32) : static_cast<void*>(P.W64));
+      a.s = s;
+      a.zeta = zeta;
+      a.k0 = k0;
+      a.k1 = k1;
+      a.U = P.Bb;
+      a.ldu = ld;
+      a.l0 = l0;
+      a.nwin = nwin;
+      if (o.profile) SFG_HIP(hipEventRecord(h->ev[2 * i], st));
+      SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, st));
+      if (o.profile) SFG_HIP(hipEventRecord(h->ev[2 * i + 1], st));
+      RqArgs r = rq;
+      r.G = Gp;
+      r.step = i;
+      r.nwin = nwin;
+      r.l0 = l0;
+      SFG_HIP(launch_rq(kRqStep, r, st));
+      if (t > 0) {
+        const void* Wv = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
+        SFG_HIP(launch_arnoldi_update(f32, G2, n, Wv, P.Bb, ld, l0, nwin, i + 1, P.coef, P.sigma,
+                                      P.part, P.ctl, hsd, i, st));
+      }
+      enq = i + 1;
+    }
+    // z_j = B_k y_k
+    SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
+    SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
+    // w = A z_j with h_{1,j}; modified Gram-Schmidt; Givens
+    {
+      SpmvArgs a = base_args;
+      a.x = Zcol(j);
+      a.w = P.W64;
+      a.v0 = Vcol(0);
+      a.vj = Vcol(j);
+      a.out0 = P.H + (int64_t)j * ldh;
+      SFG_HIP(launch_spmv(kModeOuter, false, Gp, a, st));
+    }
+    for (int l = 0; l <= j; ++l) {
+      const bool last = l == j;
+      SFG_HIP(launch_mgs(G2, n, P.W64, Vcol(l), last ? Vcol(l) : Vcol(l + 1),
+                         P.H + (int64_t)j * ldh + l, P.H + (int64_t)j * ldh + l + 1, P.part,
+                         P.ctl, last ? 1 : 0, P.H, P.HR, P.cs, P.sn, P.g, j, ldh, hsd, st));
+    }
+    // v_{j+1}, its copy as the next cycle's b_1, and S v_{j+1}
+    SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, P.H + (int64_t)j * ldh + j + 1,
+                                    Vcol(j + 1), Bcol(0), s, zeta, k0, k1, P.part, E, st));
+    {
+      RqArgs r = rq;
+      r.G = Gn;
+      r.forced_k = (forced && j + 1 < J) ? forced[j + 1] : 0;
+      SFG_HIP(launch_rq(kRqInit, r, st));
+    }
+    SFG_HIP(hipStreamSynchronize(st));
+    (void)enq;
+    const int err = hsh->error;
+    const int kj = hsh->k;
+    const double rho = hsh->rho;
+    J_done = j + 1;
+    total_inner += kj;
+    if (o.profile) {
+      const int stop_step = hsh->stop_step;
+      const int worked = std::min(stop_step, m);
+      for (int i = 0; i < worked; ++i) {
+        float ms = 0.f;
+        SFG_HIP(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+        if (info) {
+          info->spmv_ms += ms;
+          info->spmv_launches += 1;
+        }
+      }
+    }
+    if (info) {
+      info->total_inner = total_inner;
+      if (info->residual_history) info->residual_history[j + 1] = rho / nb;
+      if (info->inner_k) info->inner_k[j] = kj;
+      if (info->stop_reason) info->stop_reason[j] = hsh->stop_reason;
+      if (info->cond_at_stop) info->cond_at_stop[j] = hsh->cond;
+      if (info->inner_sketched_residual) info->inner_sketched_residual[j] = hsh->rho_hat;
+      if (info->inner_true_residual) info->inner_true_residual[j] = hsh->rhat_true;
+      if (info->ffom_residual) info->ffom_residual[j] = hsh->ffom;
+    }
+    if (err) {
+      finish_info(err, J_done, false, rho / nb, NAN);
+      return fail(h, err,
+                  err == SFGMRES_ERR_BREAKDOWN ? "sketch of A v_j is zero (singular inner problem)"
+                                               : "non-finite value in the outer recurrence");
+    }
+    rho_last = rho;
+    if (o.record_true_residual) {
+      SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st));
+      SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, P.X, st));
+      SpmvArgs a = base_args;
+      a.x = P.X;
+      a.b = b;
+      a.out0 = P.scal;
+      SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, st));
+      double r2 = 0.0;
+      SFG_HIP(hipMemcpyAsync(&r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+      SFG_HIP(hipStreamSynchronize(st));
+      if (info && info->true_residual_history) info->true_residual_history[j] = sqrt(r2) / nb;
+    }
+    if (hsh->hnext == 0.0 || rho <= tol * nb) {
+      conv = true;
+      break;
+    }
+  }
+
+  // ---- x = x0 + Z y, true residual ----------------------------------------
+  SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st));
+  SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, x, st));
+  {
+    SpmvArgs a = base_args;
+    a.x = x;
+    a.b = b;
+    a.out0 = P.scal;
+    SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, st));
+  }
+  double r2 = 0.0;
+  SFG_HIP(hipMemcpyAsync(&r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  const int status = conv ? SFGMRES_OK : SFGMRES_NOT_CONVERGED;
+  return finish_info(status, J_done, conv, rho_last / nb, sqrt(r2) / nb);
+}
+
+}  // namespace
+
+extern "C" {
+
+int sfgmres_default_options(sfgmres_options* opt) {
+  if (!opt) return SFGMRES_ERR_INVALID;
+  *opt = defaults();
+  return SFGMRES_OK;
+}
+
+int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s,
+                            const sfgmres_options* opt, int32_t adjoint, size_t* bytes) {
+  if (!bytes) return SFGMRES_ERR_INVALID;
+  const sfgmres_options o = opt ? *opt : defaults();
+  if (n < 1 || nnz < 0 || m < 1 || s <= m || s > SFGMRES_MAX_S || m > SFGMRES_MAX_M || t < 0 ||
+      o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
+    return SFGMRES_ERR_INVALID;
+  *bytes = make_layout(n, nnz, m, t, s, o.max_outer, o.precision, adjoint ? 1 : 0).total;
+  return SFGMRES_OK;
+}
+
+int sfgmres_create(sfgmres_handle* out) {
+  if (!out) return SFGMRES_ERR_INVALID;
+  *out = nullptr;
+  sfgmres_ctx* c = new (std::nothrow) sfgmres_ctx();
+  if (!c) return SFGMRES_ERR_INVALID;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return SFGMRES_ERR_HIP;
+  }
+  void* p = nullptr;
+  if (hipHostMalloc(&p, sizeof(HostStatus), hipHostMallocMapped | hipHostMallocCoherent) !=
+      hipSuccess) {
+    delete c;
+    return SFGMRES_ERR_HIP;
+  }
+  memset(p, 0, sizeof(HostStatus));
+  c->hs_host = static_cast<HostStatus*>(p);
+  void* dp = nullptr;
+  if (hipHostGetDevicePointer(&dp, p, 0) != hipSuccess) {
+    (void)hipHostFree(p);
+    delete c;
+    return SFGMRES_ERR_HIP;
+  }
+  c->hs_dev = static_cast<HostStatus*>(dp);
+  *out = c;
+  return SFGMRES_OK;
+}
+
+void sfgmres_destroy(sfgmres_handle h) {
+  if (!h) return;
+  for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  if (h->hs_host) (void)hipHostFree(h->hs_host);
+  delete h;
+}
+
+const char* sfgmres_last_error(sfgmres_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+int sfgmres_solve(sfgmres_handle h, const sfgmres_csr* A, const double* b, const double* x0,
+                  double* x, int32_t m, int32_t t, int32_t s, int32_t zeta, double tol,
+                  uint64_t seed, const sfgmres_options* opt, sfgmres_info* info, void* ws,
+                  size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!A) return fail(h, SFGMRES_ERR_INVALID, "null matrix");
+  h->err.clear();
+  const sfgmres_options o = opt ? *opt : defaults();
+  try {
+    return solve_impl(h, A, b, x0, x, m, t, s, zeta, tol, seed, o, info, ws, ws_bytes,
+                      static_cast<hipStream_t>(stream));
+  } catch (...) {
+    return fail(h, SFGMRES_ERR_INVALID, "internal exception");
+  }
+}
+
+int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* g,
+                          double* lambda, const double* x, double* grad_val, int32_t m,
+                          int32_t t, int32_t s, int32_t zeta, double tol, uint64_t seed,
+                          const sfgmres_options* opt, sfgmres_info* info, void* ws,
+                          size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!A || !A->row_ptr) return fail(h, SFGMRES_ERR_INVALID, "null matrix");
+  h->err.clear();
+  const sfgmres_options o = opt ? *opt : defaults();
+  int rc = check_params(h, A->n, A->nnz, m, t, s, zeta, tol, o);
+  if (rc) return rc;
+  const Layout L = make_layout(A->n, A->nnz, m, t, s, o.max_outer, o.precision, 1);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  int32_t* rp_t = reinterpret_cast<int32_t*>(base + L.at_rowptr);
+  int32_t* col_t = reinterpret_cast<int32_t*>(base + L.at_col);
+  double* val_t = reinterpret_cast<double*>(base + L.at_val);
+  int32_t* perm = reinterpret_cast<int32_t*>(base + L.at_perm);
+  int32_t* cursor = reinterpret_cast<int32_t*>(base + L.at_cursor);
+  int32_t* scan_tmp = reinterpret_cast<int32_t*>(base + L.scan_tmp);
+  SFG_HIP(launch_transpose(A->row_ptr, A->col_idx, A->val, A->n, A->nnz, rp_t, col_t, val_t, perm,
+                           cursor, scan_tmp, st));
+  sfgmres_csr AT{A->n, A->nnz, rp_t, col_t, val_t};
+  try {
+    rc = solve_impl(h, &AT, g, nullptr, lambda, m, t, s, zeta, tol, seed, o, info, ws, L.at_rowptr,
+                    st);
+  } catch (...) {
+    return fail(h, SFGMRES_ERR_INVALID, "internal exception");
+  }
+  if (rc < 0) return rc;
+  if (x && grad_val) {
+    SFG_HIP(launch_gradient(A->row_ptr, A->col_idx, A->n, lambda, x, grad_val, st));
+    SFG_HIP(hipStreamSynchronize(st));
+  }
+  return rc;
+}
+
+int sfgmres_transpose_workspace_bytes(int64_t n, int64_t nnz, size_t* bytes) {
+  if (!bytes || n < 1 || nnz < 0) return SFGMRES_ERR_INVALID;
+  *bytes = align256((size_t)(n + 1) * 4) + align256(transpose_scan_tmp_ints(n) * 4);
+  return SFGMRES_OK;
+}
+
+int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t,
+                      int32_t* col_idx_t, double* val_t, int32_t* perm, void* ws,
+                      size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!A || !A->row_ptr || !row_ptr_t || !perm || (A->nnz > 0 && (!A->col_idx || !col_idx_t)))
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  if (val_t && !A->val) return fail(h, SFGMRES_ERR_INVALID, "val_t needs A->val");
+  size_t need = 0;
+  if (sfgmres_transpose_workspace_bytes(A->n, A->nnz, &need) != SFGMRES_OK)
+    return fail(h, SFGMRES_ERR_INVALID, "invalid sizes");
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  int32_t* cursor = reinterpret_cast<int32_t*>(base);
+  int32_t* scan_tmp = reinterpret_cast<int32_t*>(base + align256((size_t)(A->n + 1) * 4));
+  SFG_HIP(launch_transpose(A->row_ptr, A->col_idx, A->val, A->n, A->nnz, row_ptr_t, col_idx_t,
+                           val_t, perm, cursor, scan_tmp, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
+int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta,
+                               uint64_t seed, int32_t* rows, int8_t* signs, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (n < 1 || s < 1 || s > SFGMRES_MAX_S || zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA)
+    return fail(h, SFGMRES_ERR_INVALID, "invalid (n, s, zeta)");
+  if (!rows || !signs) return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  SFG_HIP(launch_sketch_materialize(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu),
+                                    (uint32_t)(seed >> 32), rows, signs, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
+int sfgmres_sketch_workspace_bytes(int32_t s, size_t* bytes) {
+  if (!bytes || s < 1 || s > SFGMRES_MAX_S) return SFGMRES_ERR_INVALID;
+  const size_t E = (size_t)s + kPartExtra;
+  *bytes = align256(sizeof(DevCtl)) + align256((size_t)kMaxGrid * E * 8) + align256(E * 8);
+  return SFGMRES_OK;
+}
+
+int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, uint64_t seed,
+                         const double* w, double* out, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (n < 1 || s < 1 || s > SFGMRES_MAX_S || zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA)
+    return fail(h, SFGMRES_ERR_INVALID, "invalid (n, s, zeta)");
+  if (!w || !out) return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  size_t need = 0;
+  sfgmres_sketch_workspace_bytes(s, &need);
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const int E = s + kPartExtra;
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(base);
+  double* part = reinterpret_cast<double*>(base + align256(sizeof(DevCtl)));
+  double* red = reinterpret_cast<double*>(base + align256(sizeof(DevCtl)) +
+                                          align256((size_t)kMaxGrid * E * 8));
+  const int G = rows_grid(n);
+  SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
+  SFG_HIP(launch_normalize_sketch(false, G, n, w, nullptr, nullptr, nullptr, s, zeta,
+                                  (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), part, E,
+                                  st));
+  RqArgs r{};
+  r.part = part;
+  r.G = G;
+  r.E = E;
+  r.s = s;
+  r.inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
+  r.ctl = ctl;
+  r.red = red;
+  r.out_c = out;
+  r.nwin = 0;
+  SFG_HIP(launch_rq(kRqReduce, r, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
+int sfgmres_spmv_workspace_bytes(int64_t n, int64_t nnz, int32_t s, size_t* bytes) {
+  if (!bytes || n < 1 || nnz < 0 || s < 1 || s > SFGMRES_MAX_S) return SFGMRES_ERR_INVALID;
+  const size_t E = (size_t)s + kPartExtra;
+  *bytes = align256(sizeof(DevCtl)) + align256((size_t)(nnz / 128 + 3) * 4) +
+           align256((size_t)kMaxGrid * E * 8) + align256(E * 8);
+  return SFGMRES_OK;
+}
+
+int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u, double scale,
+                        double* w, int32_t s, int32_t zeta, uint64_t seed, const double* U,
+                        int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2,
+                        void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!A || !A->row_ptr || !u || !c || !norm2 || (A->nnz > 0 && (!A->col_idx || !A->val)))
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  if (A->n < 1 || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) || s < 1 || s > SFGMRES_MAX_S ||
+      zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA || nwin < 0 || nwin > SFGMRES_MAX_T ||
+      (nwin > 0 && (!U || !dots || ldu < A->n)))
+    return fail(h, SFGMRES_ERR_INVALID, "invalid sizes");
+  size_t need = 0;
+  sfgmres_spmv_workspace_bytes(A->n, A->nnz, s, &need);
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const int E = s + kPartExtra;
+  size_t off = 0;
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + off);
+  off += align256(sizeof(DevCtl));
+  int32_t* tiles = reinterpret_cast<int32_t*>(base + off);
+  off += align256((size_t)(A->nnz / 128 + 3) * 4);
+  double* part = reinterpret_cast<double*>(base + off);
+  off += align256((size_t)kMaxGrid * E * 8);
+  double* red = reinterpret_cast<double*>(base + off);
+  const int32_t wt = tile_width(A->nnz);
+  const int32_t ntiles = (int32_t)(A->nnz / wt + 1);
+  const int Gp = spmv_grid(ntiles);
+  SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
+  SFG_HIP(launch_tiles(A->row_ptr, A->n, A->nnz, wt, tiles, ntiles, st));
+  SpmvArgs a{};
+  a.n = A->n;
+  a.row_ptr = A->row_ptr;
+  a.col_idx = A->col_idx;
+  a.val = A->val;
+  a.tiles = tiles;
+  a.ntiles = ntiles;
+  a.x = u;
+  a.scale_val = scale;
+  a.w = w;
+  a.s = s;
+  a.zeta = zeta;
+  a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
+  a.k1 = (uint32_t)(seed >> 32);
+  a.U = U;
+  a.ldu = ldu;
+  a.l0 = 0;
+  a.nwin = nwin;
+  a.part = part;
+  a.E = E;
+  a.ctl = ctl;
+  a.hs = h->hs_dev;
+  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, st));
+  RqArgs r{};
+  r.part = part;
+  r.G = Gp;
+  r.E = E;
+  r.s = s;
+  r.nwin = nwin;
+  r.inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
+  r.ctl = ctl;
+  r.red = red;
+  r.out_c = c;
+  r.out_dots = dots;
+  r.out_norm2 = norm2;
+  SFG_HIP(launch_rq(kRqReduce, r, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,616 @@
+// Vector kernels of the sketched-FGMRES path: the truncated-Arnoldi update
+// (Section 4.1), the outer modified Gram-Schmidt passes with the Givens
+// update of the Hessenberg least-squares problem (Algorithm 1), the
+// normalisation of v_{j+1} fused with its sketch, the small triangular
+// solves, the tall-skinny combinations z_j = B_k y and x = x0 + Z y, the
+// float32 value cast, the adjoint's CSR transpose and value gradient, and the
+// sketch export used by tests.
+#include "kernels.hpp"
+
+namespace sfg {
+
+constexpr int kVecThreads = 256;
+
+// ---------------------------------------------------------------- control
+__global__ void k_init_ctl(DevCtl* c, int32_t m, int32_t t, int32_t s, double cond_threshold,
+                           double tol) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  DevCtl z = {};
+  z.m = m;
+  z.t = t;
+  z.s = s;
+  z.cond_threshold = cond_threshold;
+  z.tol_abs = tol;  // relative until the residual kernel multiplies by ||b||
+  z.factor = INFINITY;
+  *c = z;
+}
+
+hipError_t launch_init_ctl(DevCtl* ctl, int32_t m, int32_t t, int32_t s, double cond_threshold,
+                           double tol, hipStream_t st) {
+  hipLaunchKernelGGL(k_init_ctl, dim3(1), dim3(64), 0, st, ctl, m, t, s, cond_threshold, tol);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------ truncated Arnoldi update
+// u_{i+1} = w - sum_l coef_l u_l over the window; ||u_{i+1}||^2 reduced by
+// the last workgroup into the scale sigma_{i+1} = 1/||u_{i+1}||.
+template <typename VT>
+__global__ __launch_bounds__(kVecThreads) void k_arnoldi(int64_t n, const VT* __restrict__ W,
+                                                         VT* __restrict__ B, int64_t ldb,
+                                                         int32_t l0, int32_t nwin,
+                                                         int32_t inext,
+                                                         const double* __restrict__ coef,
+                                                         double* sigma, double* part,
+                                                         DevCtl* ctl, HostStatus* hs,
+                                                         int32_t step) {
+  __shared__ double scratch[kVecThreads / kWave];
+  __shared__ double cf[kMaxT];
+  __shared__ int flag;
+  if (ctl->stop_k != 0) return;
+  const int tid = threadIdx.x;
+  if (tid < kMaxT) cf[tid] = tid < nwin ? coef[tid] : 0.0;
+  __syncthreads();
+  VT* __restrict__ out = B + (int64_t)inext * ldb;
+  double n2 = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
+  for (int64_t r = (int64_t)blockIdx.x * kVecThreads + tid; r < n; r += stride) {
+    double acc = static_cast<double>(W[r]);
+#pragma unroll
+    for (int l = 0; l < kMaxT; ++l)
+      if (l < nwin) acc -= cf[l] * static_cast<double>(B[(int64_t)(l0 + l) * ldb + r]);
+    const VT u = static_cast<VT>(acc);
+    out[r] = u;
+    const double ud = static_cast<double>(u);
+    n2 += ud * ud;
+  }
+  n2 = block_sum(n2, scratch);
+  if (tid == 0) part[blockIdx.x] = n2;
+  if (!last_block_arrival(&ctl->ticket[2], gridDim.x, &flag)) return;
+  double tsum = 0.0;
+  for (int i = tid; i < (int)gridDim.x; i += kVecThreads) tsum += part[i];
+  tsum = block_sum(tsum, scratch);
+  if (tid == 0) {
+    if (tsum == 0.0) {
+      ctl->stop_k = step + 1;
+      ctl->stop_step = step + 1;
+      ctl->stop_reason = SFGMRES_STOP_BREAKDOWN;
+      host_store_i32(&hs->stop_k, ctl->stop_k);
+      host_store_i32(&hs->stop_step, ctl->stop_step);
+      host_store_i32(&hs->stop_reason, ctl->stop_reason);
+      __threadfence_system();
+    } else {
+      sigma[inext] = 1.0 / sqrt(tsum);
+    }
+  }
+}
+
+hipError_t launch_arnoldi_update(bool fp32, int grid, int64_t n, const void* W, void* B,
+                                 int64_t ldb, int32_t l0, int32_t nwin, int32_t inext,
+                                 const double* coef, double* sigma, double* part, DevCtl* ctl,
+                                 HostStatus* hs, int32_t step, hipStream_t st) {
+  if (fp32)
+    hipLaunchKernelGGL(k_arnoldi<float>, dim3(grid), dim3(kVecThreads), 0, st, n,
+                       static_cast<const float*>(W), static_cast<float*>(B), ldb, l0, nwin,
+                       inext, coef, sigma, part, ctl, hs, step);
+  else
+    hipLaunchKernelGGL(k_arnoldi<double>, dim3(grid), dim3(kVecThreads), 0, st, n,
+                       static_cast<const double*>(W), static_cast<double*>(B), ldb, l0, nwin,
+                       inext, coef, sigma, part, ctl, hs, step);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- outer Gram-Schmidt + Givens
+// Pass l of modified Gram-Schmidt at outer step j: w <- w - h_{l,j} v_l and
+// the next coefficient <w, v_{l+1}>, or for the last pass ||w||, which gives
+// h_{j+1,j}; the last pass also rotates column j of the Hessenberg matrix
+// with the previous Givens rotations, forms rotation j, updates g and
+// publishes |g_{j+1}| (the minimised residual) and the FFOM residual
+// |g_{j+1}| / |c_j| (eq. (2.1) via the standard FOM/GMRES relation).
+__global__ __launch_bounds__(kVecThreads) void k_mgs(
+    int64_t n, double* __restrict__ W, const double* __restrict__ Vcur,
+    const double* __restrict__ Vnext, const double* hcur, double* hout, double* part,
+    DevCtl* ctl, int last, double* H, double* HR, double* cs, double* sn, double* g, int32_t j,
+    int32_t ldh, HostStatus* hs) {
+  __shared__ double scratch[kVecThreads / kWave];
+  __shared__ int flag;
+  const int tid = threadIdx.x;
+  const double h = *hcur;
+  double acc = 0.0;
+  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
+  for (int64_t r = (int64_t)blockIdx.x * kVecThreads + tid; r < n; r += stride) {
+    const double wv = W[r] - h * Vcur[r];
+    W[r] = wv;
+    acc += wv * (last ? wv : Vnext[r]);
+  }
+  acc = block_sum(acc, scratch);
+  if (tid == 0) part[blockIdx.x] = acc;
+  if (!last_block_arrival(&ctl->ticket[3], gridDim.x, &flag)) return;
+  double tsum = 0.0;
+  for (int i = tid; i < (int)gridDim.x; i += kVecThreads) tsum += part[i];
+  tsum = block_sum(tsum, scratch);
+  if (tid != 0) return;
+  if (!last) {
+    *hout = tsum;
+    return;
+  }
+  const double hn = sqrt(tsum);
+  *hout = hn;
+  ctl->hnext = hn;
+  // Givens update of column j
+  double* col = H + (int64_t)j * ldh;
+  double* rc = HR + (int64_t)j * ldh;
+  for (int i = 0; i <= j + 1; ++i) rc[i] = col[i];
+  for (int i = 0; i < j; ++i) {
+    const double t1 = cs[i] * rc[i] + sn[i] * rc[i + 1];
+    const double t2 = -sn[i] * rc[i] + cs[i] * rc[i + 1];
+    rc[i] = t1;
+    rc[i + 1] = t2;
+  }
+  const double av = rc[j], bvv = rc[j + 1];
+  const double rr = hypot(av, bvv);
+  double c = 1.0, s = 0.0;
+  if (rr != 0.0) {
+    c = av / rr;
+    s = bvv / rr;
+  }
+  rc[j] = rr;
+  rc[j + 1] = 0.0;
+  cs[j] = c;
+  sn[j] = s;
+  const double gj = g[j];
+  g[j + 1] = -s * gj;
+  g[j] = c * gj;
+  const double rho = fabs(g[j + 1]);
+  const double ffom = (c != 0.0) ? rho / fabs(c) : INFINITY;
+  ctl->rho = rho;
+  ctl->ffom = ffom;
+  ctl->factor = ffom;
+  if ((!isfinite(rho) || !isfinite(hn)) && ctl->error == 0) ctl->error = SFGMRES_ERR_NONFINITE;
+  const bool c2 = ctl->stop_reason == SFGMRES_STOP_C2;
+  host_store_i32(&hs->outer_j, j + 1);
+  host_store_i32(&hs->k, ctl->stop_k);
+  host_store_i32(&hs->stop_reason, ctl->stop_reason);
+  host_store_i32(&hs->error, ctl->error);
+  host_store_f64(&hs->rho, rho);
+  host_store_f64(&hs->ffom, ffom);
+  host_store_f64(&hs->hnext, hn);
+  host_store_f64(&hs->cond, c2 ? ctl->cond_prev : ctl->cond_cur);
+  host_store_f64(&hs->rho_hat, c2 ? ctl->rho_prev : ctl->rho_cur);
+  host_store_f64(&hs->rhat_true, sqrt(ctl->rhat2));
+  __threadfence_system();
+}
+
+hipError_t launch_mgs(int grid, int64_t n, double* W, const double* Vcur, const double* Vnext,
+                      const double* hcur, double* hout, double* part, DevCtl* ctl, int last,
+                      double* H, double* HR, double* cs, double* sn, double* g, int32_t j,
+                      int32_t ldh, HostStatus* hs, hipStream_t st) {
+  hipLaunchKernelGGL(k_mgs, dim3(grid), dim3(kVecThreads), 0, st, n, W, Vcur, Vnext, hcur, hout,
+                     part, ctl, last, H, HR, cs, sn, g, j, ldh, hs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------ v_{j+1} = w / h fused with S v
+template <typename VT, int ZB>
+__global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double* __restrict__ W,
+                                                        const double* hptr,
+                                                        double* __restrict__ Vout,
+                                                        VT* __restrict__ Bout, int32_t s,
+                                                        int32_t zeta, uint32_t k0, uint32_t k1,
+                                                        double* part, int32_t E) {
+  extern __shared__ double lds_sk[];
+  const int tid = threadIdx.x;
+  for (int q = tid; q < s; q += kVecThreads) lds_sk[q] = 0.0;
+  __syncthreads();
+  const double h = hptr ? *hptr : 1.0;
+  const int G = gridDim.x;
+  const int gi = xcd_logical_block(blockIdx.x, G);
+  const int64_t r0 = n * gi / G;
+  const int64_t r1 = n * (gi + 1) / G;
+  for (int64_t r = r0 + tid; r < r1; r += kVecThreads) {
+    double v;
+    if (hptr)
+      v = h != 0.0 ? W[r] / h : 0.0;
+    else
+      v = W[r];
+    if (Vout) Vout[r] = v;
+    if (Bout) Bout[r] = static_cast<VT>(v);
+    sketch_scatter<ZB>(lds_sk, (uint32_t)r, v, s, zeta, k0, k1);
+  }
+  __syncthreads();
+  double* prow = part + (int64_t)blockIdx.x * E;
+  for (int q = tid; q < s; q += kVecThreads) prow[q] = lds_sk[q];
+}
+
+template <typename VT>
+static void launch_normsk_t(int zb, int grid, size_t lds, hipStream_t st, int64_t n,
+                            const double* W, const double* hptr, double* Vout, VT* Bout,
+                            int32_t s, int32_t zeta, uint32_t k0, uint32_t k1, double* part,
+                            int32_t E) {
+  switch (zb) {
+    case 1:
+      hipLaunchKernelGGL((k_normsk<VT, 1>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
+                         Vout, Bout, s, zeta, k0, k1, part, E);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_normsk<VT, 2>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
+                         Vout, Bout, s, zeta, k0, k1, part, E);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_normsk<VT, 3>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
+                         Vout, Bout, s, zeta, k0, k1, part, E);
+      break;
+    default:
+      hipLaunchKernelGGL((k_normsk<VT, 4>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
+                         Vout, Bout, s, zeta, k0, k1, part, E);
+      break;
+  }
+}
+
+hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double* W,
+                                   const double* hptr, double* Vout, void* Bout, int32_t s,
+                                   int32_t zeta, uint32_t k0, uint32_t k1, double* part,
+                                   int32_t E, hipStream_t st) {
+  const int zb = zeta_blocks(zeta);
+  const size_t lds = (size_t)s * sizeof(double);
+  if (fp32)
+    launch_normsk_t<float>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<float*>(Bout), s,
+                           zeta, k0, k1, part, E);
+  else
+    launch_normsk_t<double>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<double*>(Bout), s,
+                            zeta, k0, k1, part, E);
+  return hipGetLastError();
+}
+
+// ----------------------------------------------- small triangular solves
+// y = R^{-1} d[0:k] for the inner dimension k chosen on the device, then
+// y_l * sigma_l so that z_j = sum_l y_l u_l over the unnormalised vectors.
+__global__ __launch_bounds__(kWave) void k_finalize(const DevCtl* ctl, const double* R,
+                                                    const double* d, const double* sigma,
+                                                    int32_t m, double* y) {
+  __shared__ double rhs[kMaxM];
+  __shared__ double ys[kMaxM];
+  const int tid = threadIdx.x;
+  const int k = ctl->stop_k;
+  if (k <= 0 || k > m) return;
+  for (int p = tid; p < k; p += kWave) rhs[p] = d[p];
+  __syncthreads();
+  for (int l = k - 1; l >= 0; --l) {
+    const double yl = rhs[l] / R[(int64_t)l * m + l];
+    if (tid == 0) ys[l] = yl;
+    for (int p = tid; p < l; p += kWave) rhs[p] -= R[(int64_t)l * m + p] * yl;
+    __syncthreads();
+  }
+  for (int p = tid; p < k; p += kWave) y[p] = ys[p] * sigma[p];
+}
+
+hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
+                           const double* sigma, int32_t m, double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, st, ctl, R, d, sigma, m, y);
+  return hipGetLastError();
+}
+
+// Back substitution with the Givens-rotated Hessenberg factor (column-major,
+// leading dimension ldh): y = HR[0:J,0:J]^{-1} g[0:J].
+__global__ __launch_bounds__(kWave) void k_backsolve(const double* HR, const double* g,
+                                                     int32_t J, int32_t ldh, double* y) {
+  extern __shared__ double sh[];
+  double* rhs = sh;
+  double* ys = sh + J;
+  const int tid = threadIdx.x;
+  for (int p = tid; p < J; p += kWave) rhs[p] = g[p];
+  __syncthreads();
+  for (int l = J - 1; l >= 0; --l) {
+    const double yl = rhs[l] / HR[(int64_t)l * ldh + l];
+    if (tid == 0) ys[l] = yl;
+    for (int p = tid; p < l; p += kWave) rhs[p] -= HR[(int64_t)l * ldh + p] * yl;
+    __syncthreads();
+  }
+  for (int p = tid; p < J; p += kWave) y[p] = ys[p];
+}
+
+hipError_t launch_backsolve(const double* HR, const double* g, int32_t J, int32_t ldh,
+                            double* y, hipStream_t st) {
+  hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(kWave), (size_t)2 * J * sizeof(double), st, HR,
+                     g, J, ldh, y);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- tall-skinny combination
+// out = add + sum_{l<k} y_l B[:, l], k read from the device (kdev) or given.
+template <typename VT>
+__global__ __launch_bounds__(kVecThreads) void k_combine(int64_t n, const VT* __restrict__ B,
+                                                         int64_t ldb,
+                                                         const double* __restrict__ y,
+                                                         const int32_t* kdev, int32_t khost,
+                                                         const double* __restrict__ add,
+                                                         double* __restrict__ out) {
+  extern __shared__ double ys[];
+  const int k = kdev ? *kdev : khost;
+  for (int l = threadIdx.x; l < k; l += kVecThreads) ys[l] = y[l];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
+  for (int64_t r = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; r < n; r += stride) {
+    double acc = add ? add[r] : 0.0;
+    for (int l = 0; l < k; ++l) acc += ys[l] * static_cast<double>(B[(int64_t)l * ldb + r]);
+    out[r] = acc;
+  }
+}
+
+static int vec_grid(int64_t n) {
+  int64_t g = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
+  if (g > 2048) g = 2048;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, const double* y,
+                          const int32_t* kdev, int32_t khost, const double* add, double* out,
+                          hipStream_t st) {
+  const int kmax = kdev ? kMaxM : khost;
+  const size_t lds = (size_t)(kmax > 0 ? kmax : 1) * sizeof(double);
+  if (fp32)
+    hipLaunchKernelGGL(k_combine<float>, dim3(vec_grid(n)), dim3(kVecThreads), lds, st, n,
+                       static_cast<const float*>(B), ldb, y, kdev, khost, add, out);
+  else
+    hipLaunchKernelGGL(k_combine<double>, dim3(vec_grid(n)), dim3(kVecThreads), lds, st, n,
+                       static_cast<const double*>(B), ldb, y, kdev, khost, add, out);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ elementwise
+__global__ void k_cast_f32(const double* __restrict__ src, float* __restrict__ dst,
+                           int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    dst[i] = static_cast<float>(src[i]);
+}
+
+hipError_t launch_cast_f32(const double* src, float* dst, int64_t count, hipStream_t st) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cast_f32, dim3(vec_grid(count)), dim3(kVecThreads), 0, st, src, dst,
+                     count);
+  return hipGetLastError();
+}
+
+__global__ void k_copy_or_zero(const double* __restrict__ src, double* __restrict__ dst,
+                               int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+    dst[i] = src ? src[i] : 0.0;
+}
+
+hipError_t launch_copy_or_zero(const double* src, double* dst, int64_t n, hipStream_t st) {
+  hipLaunchKernelGGL(k_copy_or_zero, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, src, dst, n);
+  return hipGetLastError();
+}
+
+// grad[p] = -lam[row(p)] * x[col(p)]
+__global__ void k_gradient(const int32_t* __restrict__ row_ptr,
+                           const int32_t* __restrict__ col_idx, int64_t n,
+                           const double* __restrict__ lam, const double* __restrict__ x,
+                           double* __restrict__ grad) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const double li = lam[i];
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) grad[p] = -li * x[col_idx[p]];
+  }
+}
+
+hipError_t launch_gradient(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,
+                           const double* lam, const double* x, double* grad, hipStream_t st) {
+  hipLaunchKernelGGL(k_gradient, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, row_ptr, col_idx,
+                     n, lam, x, grad);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ transpose
+constexpr int kScanThreads = 1024;
+constexpr int kScanPer = 4;
+constexpr int kScanChunk = kScanThreads * kScanPer;
+
+size_t transpose_scan_tmp_ints(int64_t n) { return (size_t)((n + kScanChunk - 1) / kScanChunk) + 2; }
+
+__global__ void k_zero_i32(int32_t* p, int64_t count) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    p[i] = 0;
+}
+
+__global__ void k_count_cols(const int32_t* __restrict__ col_idx, int64_t nnz, int32_t* cnt) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < nnz; p += stride)
+    atomicAdd(&cnt[col_idx[p]], 1);
+}
+
+// exclusive scan helpers: per-thread sums of kScanPer items, then a
+// workgroup scan of the thread sums (waves via shuffles, wave totals in LDS)
+__device__ static int block_exclusive_scan(int v, int* wtot, int& total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  int incl = v;
+#pragma unroll
+  for (int off = 1; off < kWave; off <<= 1) {
+    const int o = __shfl_up(incl, off, kWave);
+    if (lane >= off) incl += o;
+  }
+  if (lane == kWave - 1) wtot[wid] = incl;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int run = 0;
+    for (int i = 0; i < kScanThreads / kWave; ++i) {
+      const int t = wtot[i];
+      wtot[i] = run;
+      run += t;
+    }
+    wtot[kScanThreads / kWave] = run;
+  }
+  __syncthreads();
+  total = wtot[kScanThreads / kWave];
+  const int excl = incl - v + wtot[wid];
+  __syncthreads();
+  return excl;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_sums(const int32_t* cnt, int64_t n,
+                                                            int32_t* bsum) {
+  __shared__ int wtot[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+  int v = 0;
+  for (int u = 0; u < kScanPer; ++u)
+    if (base + u < n) v += cnt[base + u];
+  int total;
+  block_exclusive_scan(v, wtot, total);
+  if (threadIdx.x == 0) bsum[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(int32_t* bsum, int64_t nb) {
+  __shared__ int wtot[kScanThreads / kWave + 1];
+  int carry = 0;
+  for (int64_t base = 0; base < nb; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const int v = i < nb ? bsum[i] : 0;
+    int total;
+    const int ex = block_exclusive_scan(v, wtot, total);
+    if (i < nb) bsum[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) bsum[nb] = carry;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(const int32_t* cnt, int64_t n,
+                                                             const int32_t* bsum,
+                                                             int32_t* out) {
+  __shared__ int wtot[kScanThreads / kWave + 1];
+  const int64_t base = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+  int loc[kScanPer];
+  int v = 0;
+  for (int u = 0; u < kScanPer; ++u) {
+    loc[u] = (base + u < n) ? cnt[base + u] : 0;
+    v += loc[u];
+  }
+  int total;
+  int ex = block_exclusive_scan(v, wtot, total) + bsum[blockIdx.x];
+  for (int u = 0; u < kScanPer; ++u) {
+    if (base + u < n) out[base + u] = ex;
+    ex += loc[u];
+  }
+}
+
+__global__ void k_fill_transpose(const int32_t* __restrict__ row_ptr,
+                                 const int32_t* __restrict__ col_idx, int64_t n,
+                                 const int32_t* __restrict__ rp_t, int32_t* cursor,
+                                 int32_t* __restrict__ col_t, int32_t* __restrict__ perm) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) {
+      const int c = col_idx[p];
+      const int pos = rp_t[c] + atomicAdd(&cursor[c], 1);
+      col_t[pos] = (int32_t)i;
+      perm[pos] = p;
+    }
+  }
+}
+
+// Sort each row of A^T by (column, source position) with an in-place
+// heapsort, then gather the values.
+__device__ static bool pair_less(int a0, int a1, int b0, int b1) {
+  return a0 < b0 || (a0 == b0 && a1 < b1);
+}
+
+__device__ static void sift_down(int32_t* k0, int32_t* k1, int start, int end) {
+  int root = start;
+  while (2 * root + 1 <= end) {
+    int child = 2 * root + 1;
+    int sw = root;
+    if (pair_less(k0[sw], k1[sw], k0[child], k1[child])) sw = child;
+    if (child + 1 <= end && pair_less(k0[sw], k1[sw], k0[child + 1], k1[child + 1]))
+      sw = child + 1;
+    if (sw == root) return;
+    const int t0 = k0[root], t1 = k1[root];
+    k0[root] = k0[sw];
+    k1[root] = k1[sw];
+    k0[sw] = t0;
+    k1[sw] = t1;
+    root = sw;
+  }
+}
+
+__global__ void k_sort_rows(const int32_t* __restrict__ rp_t, int64_t n, int32_t* col_t,
+                            int32_t* perm, const double* __restrict__ val,
+                            double* __restrict__ val_t) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const int a = rp_t[r];
+    const int len = rp_t[r + 1] - a;
+    int32_t* k0 = col_t + a;
+    int32_t* k1 = perm + a;
+    if (len > 1) {
+      for (int st = (len - 2) / 2; st >= 0; --st) sift_down(k0, k1, st, len - 1);
+      for (int end = len - 1; end > 0; --end) {
+        const int t0 = k0[0], t1 = k1[0];
+        k0[0] = k0[end];
+        k1[0] = k1[end];
+        k0[end] = t0;
+        k1[end] = t1;
+        sift_down(k0, k1, 0, end - 1);
+      }
+    }
+    if (val_t)
+      for (int q = 0; q < len; ++q) val_t[a + q] = val[k1[q]];
+  }
+}
+
+__global__ void k_copy_i32_last(const int32_t* src, int32_t* dst) { *dst = *src; }
+
+hipError_t launch_transpose(const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                            int64_t n, int64_t nnz, int32_t* rp_t, int32_t* col_t,
+                            double* val_t, int32_t* perm, int32_t* cursor, int32_t* scan_tmp,
+                            hipStream_t st) {
+  const int g = vec_grid(n + 1);
+  hipLaunchKernelGGL(k_zero_i32, dim3(g), dim3(kVecThreads), 0, st, cursor, n + 1);
+  hipLaunchKernelGGL(k_count_cols, dim3(vec_grid(nnz > 0 ? nnz : 1)), dim3(kVecThreads), 0, st,
+                     col_idx, nnz, cursor);
+  const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, st, cursor, n,
+                     scan_tmp);
+  hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, scan_tmp, nb);
+  hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, cursor, n,
+                     scan_tmp, rp_t);
+  // rp_t[n] = nnz
+  hipLaunchKernelGGL(k_copy_i32_last, dim3(1), dim3(1), 0, st, scan_tmp + nb, rp_t + n);
+  hipLaunchKernelGGL(k_zero_i32, dim3(g), dim3(kVecThreads), 0, st, cursor, n + 1);
+  hipLaunchKernelGGL(k_fill_transpose, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, row_ptr,
+                     col_idx, n, rp_t, cursor, col_t, perm);
+  hipLaunchKernelGGL(k_sort_rows, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, rp_t, n, col_t,
+                     perm, val, val_t);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- sketch export
+__global__ void k_sketch_materialize(int64_t n, int32_t s, int32_t zeta, uint32_t k0,
+                                     uint32_t k1, int32_t* __restrict__ rows,
+                                     int8_t* __restrict__ signs) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    int rw[kMaxZeta];
+    uint32_t neg;
+    sketch_column<kMaxZeta / 4>((uint32_t)r, s, zeta, k0, k1, rw, neg);
+#pragma unroll
+    for (int d = 0; d < kMaxZeta; ++d) {
+      if (d < zeta) {
+        rows[r * zeta + d] = rw[d];
+        signs[r * zeta + d] = ((neg >> d) & 1u) ? (int8_t)-1 : (int8_t)1;
+      }
+    }
+  }
+}
+
+hipError_t launch_sketch_materialize(int64_t n, int32_t s, int32_t zeta, uint32_t k0,
+                                     uint32_t k1, int32_t* rows, int8_t* signs,
+                                     hipStream_t st) {
+  hipLaunchKernelGGL(k_sketch_materialize, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, n, s,
+                     zeta, k0, k1, rows, signs);
+  return hipGetLastError();
+}
+
+}  // namespace sfg
