@@ -62,7 +62,7 @@ extern "C" {
 
 /* Limits checked by every entry point. */
 #define SFGMRES_MAX_ZETA   16     /* nonzeros per sketch column                   */
-#define SFGMRES_MAX_S      2048   /* sketch rows                                  */
+#define SFGMRES_MAX_S      1024   /* sketch rows                                  */
 #define SFGMRES_MAX_M      512    /* inner basis dimension                        */
 #define SFGMRES_MAX_T      8      /* Arnoldi truncation window                    */
 #define SFGMRES_MAX_OUTER  2000   /* outer FGMRES steps                           */
@@ -124,9 +124,13 @@ int sfgmres_default_options(sfgmres_options* opt);
 
 /* Workspace bytes needed by sfgmres_solve (adjoint = 0) or
  * sfgmres_solve_adjoint (adjoint = 1) for a problem with n unknowns, nnz
- * nonzeros, inner dimension m, window t, sketch rows s under *opt (NULL =
- * defaults).  Writes the size to *bytes. */
-int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s,
+ * nonzeros, inner dimension m, window t, sketch rows s and zeta nonzeros per
+ * sketch column under *opt (NULL = defaults).  Writes the size to *bytes.
+ * The workspace holds, among others, the inner basis (n x (m+1), float64 or
+ * float32), the outer bases V and Z (n x (max_outer+1) each, float64), the
+ * packed sketch (8 ceil(zeta/4) bytes per column of S) and, for the adjoint,
+ * CSR(A^T). */
+int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
                             const sfgmres_options* opt, int32_t adjoint, size_t* bytes);
 
 /* Create a handle bound to the current HIP device. */
@@ -186,18 +190,23 @@ int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t
                       int32_t* col_idx_t, double* val_t, int32_t* perm, void* ws,
                       size_t ws_bytes, void* stream);
 
-/* The sketch S (s x n) defined by (seed, s, zeta): for every column r,
- * rows[r*zeta + d] in [0, s) (distinct over d) and signs[r*zeta + d] in
- * {-1, +1}; the nonzero value is signs/sqrt(zeta).  Column r's entries come
- * from Philox4x32-10 with key (seed mod 2^32, seed div 2^32) and counter
- * (r, block, 0, 0) by Floyd's sampling.  rows [n*zeta] int32, signs [n*zeta]
- * int8, device arrays. */
-int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta,
-                               uint64_t seed, int32_t* rows, int8_t* signs, void* stream);
+/* Workspace bytes of sfgmres_sketch_materialize and sfgmres_sketch_apply
+ * for an s x n sketch with zeta nonzeros per column. */
+int sfgmres_sketch_workspace_bytes(int64_t n, int32_t s, int32_t zeta, size_t* bytes);
 
-/* out[s] = S w for w [n] (float64), with the same kernel family the solver
- * uses for its sketches.  Needs sfgmres_sketch_workspace_bytes(s). */
-int sfgmres_sketch_workspace_bytes(int32_t s, size_t* bytes);
+/* The sketch S (s x n) defined by (seed, s, zeta), as the solver generates
+ * it (Section 4.1's sparse sketch with zeta nonzeros per column): for every
+ * column r, rows[r*zeta + d] in [0, s) (distinct over d) and
+ * signs[r*zeta + d] in {-1, +1}; the nonzero value is signs/sqrt(zeta).
+ * Column r's entries come from Philox4x32-10 with key (seed mod 2^32,
+ * seed div 2^32) and counter (r, block, 0, 0) by Floyd's sampling.
+ * rows [n*zeta] int32, signs [n*zeta] int8: device arrays. */
+int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta,
+                               uint64_t seed, int32_t* rows, int8_t* signs, void* ws,
+                               size_t ws_bytes, void* stream);
+
+/* out[s] = S w for w [n] (float64), with the packed sketch and the sketch
+ * kernel the solver uses for S v_j. */
 int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, uint64_t seed,
                          const double* w, double* out, void* ws, size_t ws_bytes,
                          void* stream);
@@ -207,7 +216,8 @@ int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, u
  * n x nwin column-major array U, leading dimension ldu), norm2 = ||w||^2.
  * u, w, U: float64 [n].  c: [s], dots: [nwin] (nwin <= SFGMRES_MAX_T),
  * norm2: [1] device outputs.  Needs sfgmres_spmv_workspace_bytes. */
-int sfgmres_spmv_workspace_bytes(int64_t n, int64_t nnz, int32_t s, size_t* bytes);
+int sfgmres_spmv_workspace_bytes(int64_t n, int64_t nnz, int32_t s, int32_t zeta,
+                                 size_t* bytes);
 int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u, double scale,
                         double* w, int32_t s, int32_t zeta, uint64_t seed, const double* U,
                         int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2,

@@ -26,7 +26,7 @@ MIXED = 1
 STOP_REASONS = {1: "C1", 2: "C2", 3: "C3", 4: "breakdown", 5: "forced"}
 
 MAX_ZETA = 16
-MAX_S = 2048
+MAX_S = 1024
 MAX_M = 512
 MAX_T = 8
 MAX_OUTER = 2000
@@ -82,7 +82,8 @@ class Info(C.Structure):
 SIGNATURES = {
     "sfgmres_default_options": (C.c_int, [C.POINTER(Options)]),
     "sfgmres_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32, C.c_int32,
-                                          C.POINTER(Options), C.c_int32, C.POINTER(C.c_size_t)]),
+                                          C.c_int32, C.POINTER(Options), C.c_int32,
+                                          C.POINTER(C.c_size_t)]),
     "sfgmres_create": (C.c_int, [C.POINTER(C.c_void_p)]),
     "sfgmres_destroy": (None, [C.c_void_p]),
     "sfgmres_last_error": (C.c_char_p, [C.c_void_p]),
@@ -98,12 +99,14 @@ SIGNATURES = {
     "sfgmres_transpose": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_void_p, C.c_void_p,
                                     C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p]),
     "sfgmres_sketch_materialize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
-                                             C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p]),
-    "sfgmres_sketch_workspace_bytes": (C.c_int, [C.c_int32, C.POINTER(C.c_size_t)]),
+                                             C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
+                                             C.c_size_t, C.c_void_p]),
+    "sfgmres_sketch_workspace_bytes": (C.c_int, [C.c_int64, C.c_int32, C.c_int32,
+                                                 C.POINTER(C.c_size_t)]),
     "sfgmres_sketch_apply": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32, C.c_uint64,
                                        C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
                                        C.c_void_p]),
-    "sfgmres_spmv_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int32,
+    "sfgmres_spmv_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32,
                                                C.POINTER(C.c_size_t)]),
     "sfgmres_spmv_sketch": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_void_p, C.c_double,
                                       C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,

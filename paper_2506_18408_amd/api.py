@@ -169,8 +169,8 @@ def release_workspaces() -> None:
 def workspace_bytes(n, nnz, p: SolveParams, adjoint=False) -> int:
     out = C.c_size_t()
     o = _options(p)
-    rc = L.load().sfgmres_workspace_bytes(n, nnz, p.m, p.t, p.s, C.byref(o), 1 if adjoint else 0,
-                                          C.byref(out))
+    rc = L.load().sfgmres_workspace_bytes(n, nnz, p.m, p.t, p.s, p.zeta, C.byref(o),
+                                          1 if adjoint else 0, C.byref(out))
     if rc != 0:
         raise SFGMRESError(rc, "invalid sizes for the workspace query")
     return out.value
@@ -254,9 +254,13 @@ def sketch_materialize(n: int, s: int, zeta: int, seed: int, device="cuda"):
     dev = torch.device(device)
     rows = torch.empty(n * zeta, dtype=torch.int32, device=dev)
     signs = torch.empty(n * zeta, dtype=torch.int8, device=dev)
+    need = C.c_size_t()
+    _check(L.load().sfgmres_sketch_workspace_bytes(n, s, zeta, C.byref(need)), None)
+    ws = _workspace(need.value, dev, "sketch")
     h = _handle(dev)
     _check(L.load().sfgmres_sketch_materialize(h, n, s, zeta, seed & (2**64 - 1), rows.data_ptr(),
-                                               signs.data_ptr(), _stream()), h)
+                                               signs.data_ptr(), ws.data_ptr(), ws.numel(),
+                                               _stream()), h)
     return rows.view(n, zeta), signs.view(n, zeta)
 
 
@@ -265,7 +269,7 @@ def sketch_apply(w: torch.Tensor, s: int, zeta: int, seed: int) -> torch.Tensor:
     n = w.numel()
     out = torch.empty(s, dtype=torch.float64, device=w.device)
     need = C.c_size_t()
-    _check(L.load().sfgmres_sketch_workspace_bytes(s, C.byref(need)), None)
+    _check(L.load().sfgmres_sketch_workspace_bytes(n, s, zeta, C.byref(need)), None)
     ws = _workspace(need.value, w.device, "sketch")
     h = _handle(w.device)
     _check(L.load().sfgmres_sketch_apply(h, n, s, zeta, seed & (2**64 - 1),
@@ -287,7 +291,7 @@ def spmv_sketch(row_ptr, col_idx, val, u, s, zeta, seed, scale=1.0, U=None):
     if U is not None:
         Ucm = U.t().contiguous()  # column-major storage: column l contiguous
     need = C.c_size_t()
-    _check(L.load().sfgmres_spmv_workspace_bytes(A.n, A.nnz, s, C.byref(need)), None)
+    _check(L.load().sfgmres_spmv_workspace_bytes(A.n, A.nnz, s, zeta, C.byref(need)), None)
     ws = _workspace(need.value, dev, "spmv")
     h = _handle(dev)
     _check(L.load().sfgmres_spmv_sketch(h, C.byref(A), u.contiguous().data_ptr(), scale,

@@ -1,7 +1,14 @@
 // Internal definitions shared by the sketched-FGMRES HIP kernels and the host
 // driver: device control block, host-visible status block, workspace layout,
-// the Philox4x32-10 generator, the sketch column definition and block
-// reductions.  gfx950 only (64-lane wavefronts).
+// the Philox4x32-10 generator, the sketch column definition, the packed
+// sketch format and block reductions.  gfx950 only (64-lane wavefronts).
+//
+// Cross-workgroup reductions never use a "last workgroup finishes" ticket:
+// on a multi-XCD part every agent-scope fence writes back and invalidates
+// the workgroup's L2, which costs more than the reduction.  Every multi-
+// workgroup kernel writes one row of partial results per workgroup, and a
+// later kernel (a one-workgroup finisher, or the consumer itself) sums the
+// rows in slot order, so results are also reproducible bit for bit.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,19 +24,36 @@ constexpr int kMaxZeta = SFGMRES_MAX_ZETA;
 constexpr int kMaxS = SFGMRES_MAX_S;
 constexpr int kMaxM = SFGMRES_MAX_M;
 
-// Fused SpMV: threads per workgroup, LDS product capacity (nonzeros per tile)
-// and the persistent-grid cap.
+// Fused SpMV: threads per workgroup, nonzeros staged per tile (registers,
+// then LDS), the tiling (256-row tiles when every row has at most
+// kShortRow nonzeros, else tiles of kTileNnz nonzeros, which with rows of at
+// most kStage - kTileNnz + 1 nonzeros always fit the stage) and the
+// persistent-grid cap (4 workgroups per CU).
 constexpr int kSpmvThreads = 256;
-constexpr int kTileCap = 4096;
+constexpr int kStage = 2048;
+constexpr int kShortRow = kStage / kSpmvThreads;
+constexpr int kRowTile = kSpmvThreads;
+constexpr int kTileNnz = 1024;
 constexpr int kMaxGrid = 1024;
-// Partial-sum row layout written by every persistent kernel:
-//   [0, s)              sketch accumulators
+// Vector kernels: threads per workgroup and grid cap (one partial per
+// workgroup in the vector partial buffer).
+constexpr int kVecThreads = 256;
+constexpr int kVecGrid = 1024;
+// Partial-sum row layout written by every persistent SpMV kernel:
+//   [0, s)              sketch accumulators (sum of +-w_r, unscaled)
 //   [s, s + kMaxT)      dot products
 //   s + kMaxT           squared norm
 //   s + kMaxT + 1       second squared norm / extra scalar
 constexpr int kPartExtra = kMaxT + 2;
 
-// Device control block (lives in the workspace).
+// Packed sketch: every column r of S is stored as 4*ZB 16-bit fields
+// (ZB = ceil(zeta/4), a multiple of 8 bytes per column): bits 0..14 hold
+// the row in [0, s), bit 15 the sign (1 = negative); unused fields are
+// 0xFFFF.
+constexpr uint16_t kSkEmpty = 0xFFFFu;
+
+// Device control block (lives in the workspace).  Scalars are written by
+// one-workgroup kernels only.
 struct DevCtl {
   // inner cycle
   int32_t stop_k;        // 0 while the cycle runs, else the chosen dimension k_j
@@ -55,8 +79,6 @@ struct DevCtl {
   double ffom;
   double hnext;          // h_{j+1,j}
   double cs_last;
-  // tickets for last-workgroup reductions (reset by the last workgroup)
-  uint32_t ticket[8];
 };
 
 // Host-visible status block (pinned, device-mapped).
@@ -74,16 +96,21 @@ struct HostStatus {
 
 // Offsets (bytes) of every workspace region.
 struct Layout {
-  size_t ctl, tiles, part, red, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z, sigma,
-      hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, at_rowptr, at_col, at_val,
-      at_perm, at_cursor, scan_tmp, total;
+  size_t ctl, tiles, tp, ipart, part, vpart, red, skp, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z,
+      sigma, hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, at_rowptr, at_col,
+      at_val, at_perm, at_cursor, scan_tmp, total;
   int64_t ld;        // leading dimension (elements) of the n-vectors
   int64_t ntiles_max;
   int32_t grid;      // persistent grid size used for the partial buffer
 };
 
-Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t max_outer,
-                   int32_t precision, int32_t adjoint);
+Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
+                   int32_t max_outer, int32_t precision, int32_t adjoint);
+
+// Bytes of the packed sketch of an n-column S with zeta nonzeros per column.
+inline size_t packed_sketch_bytes(int64_t n, int32_t zeta) {
+  return (size_t)n * (size_t)((zeta + 3) / 4) * 8;
+}
 
 // ---------------------------------------------------------------- Philox
 // Philox4x32-10 (Salmon et al., SC'11): four 32-bit counter words, two key
@@ -147,18 +174,26 @@ __device__ __forceinline__ void sketch_column(uint32_t col, int s, int zeta, uin
   }
 }
 
-// Scatter +-v into the LDS accumulators of column `col` of S.
+// Scatter +-v into the LDS accumulators of column `col` of S, read from the
+// packed sketch (ZB 8-byte groups per column).  Every wave owns a private
+// copy of the s accumulators (a workgroup sums its copies in wave order at
+// the end), so the order of the additions into one accumulator depends only
+// on the static row-to-lane assignment and the sketch of a vector is
+// reproducible bit for bit from run to run.
 template <int ZB>
-__device__ __forceinline__ void sketch_scatter(double* lds_sk, uint32_t col, double v, int s,
-                                               int zeta, uint32_t k0, uint32_t k1) {
-  int rows[4 * ZB];
-  uint32_t neg;
-  sketch_column<ZB>(col, s, zeta, k0, k1, rows, neg);
+__device__ __forceinline__ void sketch_scatter_packed(double* lds_sk, const uint2* __restrict__ skp,
+                                                      int64_t col, double v) {
 #pragma unroll
-  for (int d = 0; d < 4 * ZB; ++d) {
-    if (d < zeta) {
-      const double a = ((neg >> d) & 1u) ? -v : v;
-      __hip_atomic_fetch_add(&lds_sk[rows[d]], a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  for (int b = 0; b < ZB; ++b) {
+    const uint2 q = skp[col * ZB + b];
+    const uint32_t f[4] = {q.x & 0xFFFFu, q.x >> 16, q.y & 0xFFFFu, q.y >> 16};
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      if (f[e] != kSkEmpty) {
+        const double a = (f[e] & 0x8000u) ? -v : v;
+        __hip_atomic_fetch_add(&lds_sk[f[e] & 0x7FFFu], a, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
     }
   }
 }
@@ -186,6 +221,15 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   return r;
 }
 
+// Sum of src[0], src[stride], ..., src[(count-1) stride] by one workgroup
+// in a fixed order (thread-strided partial sums, then block_sum).
+__device__ __forceinline__ double block_sum_strided(const double* src, int count, int64_t stride,
+                                                    double* scratch) {
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < count; i += blockDim.x) acc += src[(int64_t)i * stride];
+  return block_sum(acc, scratch);
+}
+
 // Persistent-grid logical block id: consecutive hardware workgroup ids are
 // dealt round-robin to the 8 XCDs, so give each XCD a contiguous range of
 // logical ids (and hence of rows / tiles) to keep gathers inside one L2.
@@ -193,28 +237,6 @@ __device__ __forceinline__ int xcd_logical_block(int b, int nb) {
   constexpr int kXcd = 8;
   if (nb % kXcd != 0) return b;
   return (b % kXcd) * (nb / kXcd) + b / kXcd;
-}
-
-// Last-workgroup detection: every workgroup calls this once after writing
-// its partial results; returns true in exactly one workgroup (the last to
-// arrive), which may then read all partials.  The counter is reset there.
-__device__ __forceinline__ bool last_block_arrival(uint32_t* counter, int nblocks,
-                                                   int* lds_flag) {
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const uint32_t prev =
-        __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    *lds_flag = (prev == (uint32_t)(nblocks - 1)) ? 1 : 0;
-  }
-  __syncthreads();
-  const bool last = *lds_flag != 0;
-  if (last) {
-    __threadfence();
-    if (threadIdx.x == 0)
-      __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  return last;
 }
 
 // Stores into the pinned host status block (system scope).

@@ -1,26 +1,64 @@
-// Reduce-then-decide kernel of one inner sGMRES step (Section 3).
+// Reduce and decide: the sketched least-squares step of one inner sGMRES
+// step (Section 3).
 //
-// Many workgroups first combine the per-workgroup partial rows written by the
-// fused SpMV (sketch column c_i = S A b_i, truncated-Arnoldi dots, ||w||^2),
-// each summing a 16-entry slice over all rows in slot order.  The last
-// workgroup to finish then, in float64:
+// k_reduce_rows (many workgroups) combines the per-workgroup partial rows of
+// the fused SpMV (raw sketch S y, truncated-Arnoldi dots, ||y||^2), each
+// workgroup summing a 16-entry slice over all rows in slot order.
+//
+// k_rq (one workgroup) then, in float64:
+//   * forms sigma_i = 1/||u_i|| of the current (unnormalised) Arnoldi vector
+//     from the norm partials of the previous Arnoldi update, and the new
+//     column c_i = S A b_i / sqrt(zeta) of S A B_i (b_i = sigma_i u_i; for
+//     t > 0 the SpMV returned y = A u_i, for t = 0 already y = A b_i);
 //   * appends c_i to the Householder QR of S A B_i (compact-WY form
 //     Q = I - V T V^T: c <- c - V T^T V^T c, a new reflector for c[i:],
 //     T extended by -tau T V^T v), carries d = Q^T S v_j along, and reads the
 //     sketched least-squares residual ||d[i+1:]|| (the estimate used by C3);
-//   * extends the incremental condition estimate of R (Bischof's ICE, the
-//     same recurrence as the oracle: top eigenpairs of two 2x2 matrices);
+//   * extends the incremental condition estimate of R (Bischof's ICE: top
+//     eigenpairs of two 2x2 matrices);
 //   * applies C2 (estimate above threshold: drop column i), C3 (bound of
 //     eq. (2.2) below tol), C1 (i = m), or a forced replay dimension;
-//   * stores the truncated-Arnoldi coefficients for the vector update, or,
-//     for t = 0, the scale 1/||A b_i|| of the next power-basis vector.
-// The mode kRqInit instead reduces d0 = S v_j and resets the cycle state.
+//   * stores the truncated-Arnoldi coefficients sigma_i sigma_l^2 <y, u_l>
+//     and the scale sigma_i of y for the vector update, or, for t = 0, the
+//     scale of the next power-basis vector.
+// The mode kRqInit instead takes d0 = S v_j and resets the cycle state.
 #include "kernels.hpp"
 
 namespace sfg {
 
 constexpr int kRqThreads = 1024;
-constexpr int kRqSlice = 16;  // entries per reduction workgroup
+constexpr int kRedThreads = 1024;
+constexpr int kRedSlice = 16;  // entries per reduction workgroup
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const double* __restrict__ part,
+                                                             int32_t G, int32_t E,
+                                                             double* __restrict__ red,
+                                                             const DevCtl* ctl, int predicated) {
+  __shared__ double sl[kRedThreads];
+  if (predicated && ctl->stop_k != 0) return;
+  const int tid = threadIdx.x;
+  const int e = blockIdx.x * kRedSlice + (tid % kRedSlice);
+  const int rg = tid / kRedSlice;
+  constexpr int nrg = kRedThreads / kRedSlice;
+  double acc = 0.0;
+  if (e < E)
+    for (int r = rg; r < G; r += nrg) acc += part[(int64_t)r * E + e];
+  sl[tid] = acc;
+  __syncthreads();
+  if (tid < kRedSlice) {
+    double t = 0.0;
+    for (int r = 0; r < nrg; ++r) t += sl[r * kRedSlice + tid];
+    if (e < E) red[e] = t;
+  }
+}
+
+hipError_t launch_reduce_rows(const double* part, int32_t G, int32_t E, double* red,
+                              const DevCtl* ctl, bool predicated, hipStream_t st) {
+  const int nb = (E + kRedSlice - 1) / kRedSlice;
+  hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kRedThreads), 0, st, part, G, E, red, ctl,
+                     predicated ? 1 : 0);
+  return hipGetLastError();
+}
 
 // Top eigenvalue / unit eigenvector of [[a, b], [b, d]] via the symmetric
 // Schur rotation (Golub & Van Loan, Sec. 8.5.2).
@@ -66,9 +104,7 @@ __device__ static void publish_inner(HostStatus* hs, const DevCtl* c, int done) 
 }
 
 __global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
-  __shared__ double sl[kRqThreads];
   __shared__ double scratch[kRqThreads / kWave];
-  __shared__ int lds_flag;
   __shared__ double cv[kMaxS];
   __shared__ double av[kMaxM];
   __shared__ double bv[kMaxM];
@@ -80,24 +116,6 @@ __global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
   const int lane = tid & (kWave - 1);
   const int wid = tid / kWave;
   constexpr int nw = kRqThreads / kWave;
-
-  // ---- parallel slice reduction of the partial rows ---------------------
-  {
-    const int e = blockIdx.x * kRqSlice + (tid % kRqSlice);
-    const int rg = tid / kRqSlice;
-    constexpr int nrg = kRqThreads / kRqSlice;
-    double acc = 0.0;
-    if (e < a.E)
-      for (int r = rg; r < a.G; r += nrg) acc += a.part[(int64_t)r * a.E + e];
-    sl[tid] = acc;
-    __syncthreads();
-    if (tid < kRqSlice) {
-      double t = 0.0;
-      for (int r = 0; r < nrg; ++r) t += sl[r * kRqSlice + tid];
-      if (e < a.E) a.red[e] = t;
-    }
-  }
-  if (!last_block_arrival(&ctl->ticket[1], gridDim.x, &lds_flag)) return;
 
   const int s = a.s;
   const int m = a.m;
@@ -137,7 +155,28 @@ __global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
   // ---- kRqStep: one column appended to the sketched QR -------------------
   const int k = ctl->qr_k;  // existing columns; the new one has index k
   const int step = a.step;  // == k
-  for (int q = tid; q < s; q += kRqThreads) cv[q] = red[q] * a.inv_sqrt_zeta;
+  // sigma_i of the current Arnoldi vector u_i
+  if (a.t > 0 && step > 0) {
+    const double n2u = block_sum_strided(a.vpart, a.Gv, 1, scratch);
+    if (n2u == 0.0) {
+      // u_i = 0: truncated Arnoldi broke down; keep the i columns built so far
+      if (tid == 0) {
+        ctl->stop_k = step;
+        ctl->stop_step = step;
+        ctl->stop_reason = SFGMRES_STOP_BREAKDOWN;
+        publish_inner(a.hs, ctl, step);
+      }
+      return;
+    }
+    if (tid == 0) bc[0] = 1.0 / sqrt(n2u);
+  } else if (tid == 0) {
+    bc[0] = a.sigma[step];
+  }
+  __syncthreads();
+  const double sig = bc[0];
+  if (tid == 0) a.sigma[step] = sig;
+  const double cscale = (a.t > 0 ? sig : 1.0) * a.inv_sqrt_zeta;
+  for (int q = tid; q < s; q += kRqThreads) cv[q] = red[q] * cscale;
   __syncthreads();
 
   // a = V^T c  (column l of V is zero above row l, one at row l)
@@ -319,7 +358,7 @@ __global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
     }
     if (!stop) {
       if (a.t == 0) {
-        // power basis: the next vector is A b_i itself, scaled by 1/||A b_i||
+        // power basis: the next vector is y = A b_i itself; sigma_{i+1} = 1/||y||
         const double n2 = red[s + kMaxT];
         if (n2 == 0.0) {
           stop = ncols;
@@ -328,11 +367,14 @@ __global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
           a.sigma[step + 1] = 1.0 / sqrt(n2);
         }
       } else {
-        // window coefficients sigma_l * h_l with h_l = sigma_l <w, u_l>
+        // u_{i+1} = sigma_i y - sum_l sigma_i sigma_l^2 <y, u_l> u_l: A b_i
+        // minus its projections h_l b_l on the window b_l = sigma_l u_l,
+        // h_l = sigma_i sigma_l <y, u_l>; ||u_{i+1}|| = h_{i+1,i}
         for (int l = 0; l < a.nwin; ++l) {
-          const double sg = a.sigma[a.l0 + l];
-          a.coef[l] = sg * sg * red[s + l];
+          const double sg = (a.l0 + l == step) ? sig : a.sigma[a.l0 + l];
+          a.coef[l] = sig * sg * sg * red[s + l];
         }
+        a.coef[kMaxT] = sig;
       }
     }
     if (!isfinite(rho_hat) && ctl->error == 0) ctl->error = SFGMRES_ERR_NONFINITE;
@@ -346,8 +388,7 @@ __global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
 }
 
 hipError_t launch_rq(int mode, const RqArgs& a, hipStream_t st) {
-  const int nred = (a.E + kRqSlice - 1) / kRqSlice;
-  hipLaunchKernelGGL(k_rq, dim3(nred), dim3(kRqThreads), 0, st, a, mode);
+  hipLaunchKernelGGL(k_rq, dim3(1), dim3(kRqThreads), 0, st, a, mode);
   return hipGetLastError();
 }
 

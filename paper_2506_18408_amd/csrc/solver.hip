@@ -1,15 +1,23 @@
 // Host driver and C ABI of the sketched-FGMRES solver (include/sfgmres.h).
 //
 // One call runs Algorithm 1 of Guettel & Pearson (arXiv 2506.18408) on the
-// caller's stream: the initial residual, then per outer step one sGMRES
-// cycle (Section 3) built from the fused SpMV+sketch kernel, the
-// reduce-and-decide kernel and, for t > 0, the truncated-Arnoldi update, then
-// z_j = B_k y, the outer SpMV, modified Gram-Schmidt, the Givens update and
-// the normalised v_{j+1} with its sketch.  The host stays a few inner steps
-// ahead of the device: every inner kernel is predicated on the device's stop
-// flag, and the host polls a pinned status block (written by the decision
-// kernel) to stop enqueuing once the cycle has ended.  The host synchronises
-// once per outer step to read the minimised residual.
+// caller's stream: the sketch S is generated once (packed), then the initial
+// residual, then per outer step one sGMRES cycle (Section 3), then z_j =
+// B_k y, the outer SpMV, modified Gram-Schmidt, the Givens update and the
+// normalised v_{j+1} with its sketch.
+//
+// One inner step i is four launches: the fused SpMV y = A u_i (+ S y, window
+// dots, ||y||^2 as per-workgroup partial rows), the row reduction, the
+// one-workgroup decision kernel (sigma_i, QR column, ICE, C1-C3, Arnoldi
+// coefficients) and, for t > 0, the truncated-Arnoldi update u_{i+1}.  The
+// inner basis is kept unnormalised (u_i = the orthogonalised A b_{i-1}, of
+// norm h_{i,i-1}, with sigma_i = 1/||u_i|| held on the device), so no kernel
+// waits for a scalar its predecessor has just reduced.
+// The host stays a few inner steps ahead of the device: every inner kernel is
+// predicated on the device's stop flag, and the host polls a pinned status
+// block (written by the decision kernel) to stop enqueuing once the cycle has
+// ended.  The host synchronises once per outer step to read the minimised
+// residual.
 #include <math.h>
 #include <string.h>
 
@@ -33,13 +41,13 @@ namespace sfg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t J,
-                   int32_t precision, int32_t adjoint) {
+Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
+                   int32_t J, int32_t precision, int32_t adjoint) {
   (void)t;
   Layout L{};
   const bool f32 = precision == SFGMRES_MIXED;
   L.ld = (n + 63) / 64 * 64;
-  L.ntiles_max = nnz / 128 + 2;
+  L.ntiles_max = n / kRowTile + nnz / kTileNnz + 3;
   L.grid = kMaxGrid;
   const int64_t E = s + kPartExtra;
   const size_t vt = f32 ? 4 : 8;
@@ -51,8 +59,12 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   };
   L.ctl = take(sizeof(DevCtl));
   L.tiles = take((size_t)(L.ntiles_max + 1) * 4);
+  L.tp = take((size_t)(L.ntiles_max + 1) * 4);
+  L.ipart = take((size_t)(kVecGrid + 1) * 4);
   L.part = take((size_t)kMaxGrid * E * 8);
+  L.vpart = take((size_t)kVecGrid * 8);
   L.red = take((size_t)E * 8);
+  L.skp = take(packed_sketch_bytes(n, zeta));
   L.qr_V = take((size_t)s * m * 8);
   L.qr_T = take((size_t)m * m * 8);
   L.qr_R = take((size_t)m * m * 8);
@@ -62,7 +74,7 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.ice_x = take((size_t)(m + 1) * 8);
   L.ice_z = take((size_t)(m + 1) * 8);
   L.sigma = take((size_t)(m + 2) * 8);
-  L.hwin = take((size_t)kMaxT * 8);
+  L.hwin = take((size_t)(kMaxT + 1) * 8);
   L.yin = take((size_t)(m + 1) * 8);
   L.H = take((size_t)(J + 1) * J * 8);
   L.HR = take((size_t)(J + 1) * J * 8);
@@ -121,13 +133,18 @@ sfgmres_options defaults() {
   return o;
 }
 
+bool sketch_args_ok(int64_t n, int32_t s, int32_t zeta) {
+  return n >= 1 && n < ((int64_t)1 << 31) && s >= 1 && s <= SFGMRES_MAX_S && zeta >= 1 &&
+         zeta <= s && zeta <= SFGMRES_MAX_ZETA;
+}
+
 int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s,
                  int32_t zeta, double tol, const sfgmres_options& o) {
   if (n < 1) return fail(h, SFGMRES_ERR_INVALID, "n must be >= 1");
   if (nnz < 0 || nnz >= (int64_t)1 << 31) return fail(h, SFGMRES_ERR_INVALID, "nnz out of range");
   if (n >= (int64_t)1 << 31) return fail(h, SFGMRES_ERR_INVALID, "n must be < 2^31");
   if (m < 1 || m > SFGMRES_MAX_M) return fail(h, SFGMRES_ERR_INVALID, "need 1 <= m <= 512");
-  if (s <= m || s > SFGMRES_MAX_S) return fail(h, SFGMRES_ERR_INVALID, "need m < s <= 2048");
+  if (s <= m || s > SFGMRES_MAX_S) return fail(h, SFGMRES_ERR_INVALID, "need m < s <= 1024");
   if (t < 0 || t > m || t > SFGMRES_MAX_T)
     return fail(h, SFGMRES_ERR_INVALID, "need 0 <= t <= min(m, 8)");
   if (zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA)
@@ -141,34 +158,57 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
   return SFGMRES_OK;
 }
 
+// Persistent grid of the SpMV kernels: a multiple of the 8 XCDs.
 int spmv_grid(int64_t ntiles) {
   int64_t g = std::min<int64_t>(ntiles, kMaxGrid);
   if (g >= 8) g -= g % 8;
   return (int)std::max<int64_t>(g, 1);
 }
 
+// Grid of the row-range sketch kernel (one partial row each, <= kMaxGrid).
 int rows_grid(int64_t n) {
   int64_t g = std::min<int64_t>((n + 1023) / 1024, kMaxGrid);
   if (g >= 8) g -= g % 8;
   return (int)std::max<int64_t>(g, 1);
 }
 
-int stream_grid(int64_t n) {
-  int64_t g = std::min<int64_t>((n + 1023) / 1024, 2048);
-  return (int)std::max<int64_t>(g, 1);
-}
+// Tiling of the SpMV kernels for A: 256-row tiles (one row per lane) when
+// every row has at most kShortRow nonzeros, else tiles of about kTileNnz
+// nonzeros.  Reads the longest row back to the host (one synchronisation).
+struct Tiling {
+  int32_t ntiles;
+  int32_t grid;
+  int32_t max_row;
+};
 
-int32_t tile_width(int64_t nnz) {
-  int64_t w = 128;
-  while (w < 2048 && w * 2 * 1024 <= nnz) w *= 2;
-  return (int32_t)w;
+int plan_tiling(sfgmres_handle h, const sfgmres_csr* A, int32_t* tiles, int32_t* tp,
+                int32_t* ipart, hipStream_t st, Tiling* T) {
+  int32_t* out = ipart + kVecGrid;
+  SFG_HIP(launch_max_rowlen(A->row_ptr, A->n, ipart, out, st));
+  int32_t maxlen = 0;
+  SFG_HIP(hipMemcpyAsync(&maxlen, out, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  int32_t rpt = 0;
+  int64_t ntiles;
+  if (maxlen <= kShortRow) {
+    rpt = kRowTile;
+    ntiles = (A->n + rpt - 1) / rpt;
+  } else {
+    ntiles = A->nnz / kTileNnz + 1;
+  }
+  SFG_HIP(launch_tiles(A->row_ptr, A->n, kTileNnz, rpt, tiles, tp, (int32_t)ntiles, st));
+  T->ntiles = (int32_t)ntiles;
+  T->grid = spmv_grid(ntiles);
+  T->max_row = maxlen;
+  return SFGMRES_OK;
 }
 
 struct Ptrs {
   DevCtl* ctl;
-  int32_t* tiles;
-  double *part, *red, *V, *T, *R, *d, *scal, *tau, *ice_x, *ice_z, *sigma, *coef, *yin, *H, *HR,
-      *cs, *sn, *g, *yout, *Vb, *Zb, *W64, *X;
+  int32_t *tiles, *tp, *ipart;
+  double *part, *vpart, *red, *V, *T, *R, *d, *scal, *tau, *ice_x, *ice_z, *sigma, *coef, *yin,
+      *H, *HR, *cs, *sn, *g, *yout, *Vb, *Zb, *W64, *X;
+  uint2* skp;
   void* Bb;
   float *W32, *val32;
 };
@@ -177,8 +217,12 @@ Ptrs make_ptrs(char* base, const Layout& L) {
   Ptrs p;
   p.ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
   p.tiles = reinterpret_cast<int32_t*>(base + L.tiles);
+  p.tp = reinterpret_cast<int32_t*>(base + L.tp);
+  p.ipart = reinterpret_cast<int32_t*>(base + L.ipart);
   p.part = reinterpret_cast<double*>(base + L.part);
+  p.vpart = reinterpret_cast<double*>(base + L.vpart);
   p.red = reinterpret_cast<double*>(base + L.red);
+  p.skp = reinterpret_cast<uint2*>(base + L.skp);
   p.V = reinterpret_cast<double*>(base + L.qr_V);
   p.T = reinterpret_cast<double*>(base + L.qr_T);
   p.R = reinterpret_cast<double*>(base + L.qr_R);
@@ -243,7 +287,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   if (rc) return rc;
   if (!A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val)) || !b || !x)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  const Layout L = make_layout(n, nnz, m, t, s, o.max_outer, o.precision, 0);
+  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   char* base = static_cast<char*>(ws);
@@ -254,6 +298,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int64_t ld = L.ld;
   const size_t vt = f32 ? 4 : 8;
   const int E = s + kPartExtra;
+  const int zb = zeta_blocks(zeta);
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu);
   const uint32_t k1 = (uint32_t)(seed >> 32);
   const double inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
@@ -282,16 +327,18 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     }
   }
 
-  // ---- setup: control block, nnz-balanced tiles, float32 values ----------
-  const int32_t wt = tile_width(nnz);
-  const int32_t ntiles = (int32_t)(nnz / wt + 1);
-  const int Gp = spmv_grid(ntiles);
+  // ---- setup: control block, nnz-balanced tiles, float32 values, sketch --
+  Tiling tiling{};
+  rc = plan_tiling(h, A, P.tiles, P.tp, P.ipart, st, &tiling);
+  if (rc) return rc;
+  const int32_t ntiles = tiling.ntiles;
+  const int Gp = tiling.grid;
   const int Gn = rows_grid(n);
-  const int G2 = stream_grid(n);
+  const int G2 = vec_grid(n);
   memset((void*)hsh, 0, sizeof(HostStatus));
   SFG_HIP(launch_init_ctl(P.ctl, m, t, s, o.cond_threshold, tol, st));
-  SFG_HIP(launch_tiles(A->row_ptr, n, nnz, wt, P.tiles, ntiles, st));
   if (f32) SFG_HIP(launch_cast_f32(A->val, P.val32, nnz, st));
+  SFG_HIP(launch_sketch_pack(n, s, zeta, k0, k1, P.skp, st));
 
   SpmvArgs base_args{};
   base_args.n = n;
@@ -299,23 +346,24 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   base_args.col_idx = A->col_idx;
   base_args.val = A->val;
   base_args.tiles = P.tiles;
+  base_args.tp = P.tp;
   base_args.ntiles = ntiles;
   base_args.part = P.part;
   base_args.E = E;
   base_args.ctl = P.ctl;
-  base_args.hs = hsd;
   base_args.scale_val = 1.0;
+  base_args.skp = P.skp;
 
   RqArgs rq{};
-  rq.part = P.part;
-  rq.E = E;
+  rq.red = P.red;
+  rq.vpart = P.vpart;
+  rq.Gv = G2;
   rq.s = s;
   rq.m = m;
   rq.t = t;
   rq.inv_sqrt_zeta = inv_sqrt_zeta;
   rq.ctl = P.ctl;
   rq.hs = hsd;
-  rq.red = P.red;
   rq.V = P.V;
   rq.T = P.T;
   rq.R = P.R;
@@ -333,14 +381,14 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     a.x = x0;
     a.w = P.W64;
     a.b = b;
-    a.out0 = P.g;
-    SFG_HIP(launch_spmv(kModeResid, false, Gp, a, st));
+    SFG_HIP(launch_spmv(kModeResid, false, Gp, a, 0, st));
+    SFG_HIP(launch_spmv_finish(kModeResid, P.part, Gp, E, P.ctl, P.g, hsd, st));
   }
-  SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, &P.ctl->beta, Vcol(0), Bcol(0), s, zeta, k0,
-                                  k1, P.part, E, st));
+  SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, &P.ctl->beta, Vcol(0), Bcol(0), s, P.skp,
+                                  zb, P.part, E, st));
+  SFG_HIP(launch_reduce_rows(P.part, Gn, E, P.red, P.ctl, false, st));
   {
     RqArgs r = rq;
-    r.G = Gn;
     r.forced_k = forced ? forced[0] : 0;
     SFG_HIP(launch_rq(kRqInit, r, st));
   }
@@ -375,6 +423,17 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     return finish_info(SFGMRES_OK, 0, true, beta / nb, beta / nb);
   }
 
+  auto true_residual = [&](double* xv, double* r2) -> int {
+    SpmvArgs a = base_args;
+    a.x = xv;
+    a.b = b;
+    SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, 0, st));
+    SFG_HIP(launch_spmv_finish(kModeTrueRes, P.part, Gp, E, P.ctl, P.scal, hsd, st));
+    SFG_HIP(hipMemcpyAsync(r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    SFG_HIP(hipStreamSynchronize(st));
+    return SFGMRES_OK;
+  };
+
   // ---- outer FGMRES loop ---------------------------------------------------
   int J_done = 0;
   bool conv = false;
@@ -385,7 +444,6 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     hsh->stop_k = 0;
     hsh->inner_step_done = 0;
     hsh->stop_step = 0;
-    int enq = 0;
     for (int i = 0; i < m; ++i) {
       if (i >= lookahead) {
         const int need = i - lookahead + 1;
@@ -400,31 +458,29 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       SpmvArgs a = base_args;
       a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
       a.x = Bcol(i);
-      a.scale_ptr = P.sigma + i;
+      // t = 0: y = sigma_i A u_i = A b_i is the next (unnormalised) power-basis
+      // vector; t > 0: y = A u_i, scaled inside the Arnoldi update
+      a.scale_ptr = (t == 0) ? P.sigma + i : nullptr;
       a.w = (t == 0) ? Bcol(i + 1) : (f32 ? static_cast<void*>(P.W32) : static_cast<void*>(P.W64));
       a.s = s;
-      a.zeta = zeta;
-      a.k0 = k0;
-      a.k1 = k1;
       a.U = P.Bb;
       a.ldu = ld;
       a.l0 = l0;
       a.nwin = nwin;
       if (o.profile) SFG_HIP(hipEventRecord(h->ev[2 * i], st));
-      SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, st));
+      SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st));
       if (o.profile) SFG_HIP(hipEventRecord(h->ev[2 * i + 1], st));
+      SFG_HIP(launch_reduce_rows(P.part, Gp, E, P.red, P.ctl, true, st));
       RqArgs r = rq;
-      r.G = Gp;
       r.step = i;
       r.nwin = nwin;
       r.l0 = l0;
       SFG_HIP(launch_rq(kRqStep, r, st));
       if (t > 0) {
         const void* Wv = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
-        SFG_HIP(launch_arnoldi_update(f32, G2, n, Wv, P.Bb, ld, l0, nwin, i + 1, P.coef, P.sigma,
-                                      P.part, P.ctl, hsd, i, st));
+        SFG_HIP(launch_arnoldi_update(f32, G2, n, Wv, P.Bb, ld, l0, nwin, i + 1, P.coef, P.vpart,
+                                      P.ctl, st));
       }
-      enq = i + 1;
     }
     // z_j = B_k y_k
     SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
@@ -436,26 +492,28 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       a.w = P.W64;
       a.v0 = Vcol(0);
       a.vj = Vcol(j);
-      a.out0 = P.H + (int64_t)j * ldh;
-      SFG_HIP(launch_spmv(kModeOuter, false, Gp, a, st));
+      SFG_HIP(launch_spmv(kModeOuter, false, Gp, a, 0, st));
+      SFG_HIP(launch_spmv_finish(kModeOuter, P.part, Gp, E, P.ctl, P.H + (int64_t)j * ldh, hsd,
+                                 st));
     }
     for (int l = 0; l <= j; ++l) {
       const bool last = l == j;
-      SFG_HIP(launch_mgs(G2, n, P.W64, Vcol(l), last ? Vcol(l) : Vcol(l + 1),
-                         P.H + (int64_t)j * ldh + l, P.H + (int64_t)j * ldh + l + 1, P.part,
-                         P.ctl, last ? 1 : 0, P.H, P.HR, P.cs, P.sn, P.g, j, ldh, hsd, st));
+      double* hcol = P.H + (int64_t)j * ldh;
+      SFG_HIP(launch_mgs_pass(G2, n, P.W64, Vcol(l), last ? Vcol(l) : Vcol(l + 1), hcol + l,
+                              P.vpart, last ? 1 : 0, st));
+      SFG_HIP(launch_mgs_finish(P.vpart, G2, hcol + l + 1, P.ctl, last ? 1 : 0, P.H, P.HR, P.cs,
+                                P.sn, P.g, j, ldh, hsd, st));
     }
     // v_{j+1}, its copy as the next cycle's b_1, and S v_{j+1}
     SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, P.H + (int64_t)j * ldh + j + 1,
-                                    Vcol(j + 1), Bcol(0), s, zeta, k0, k1, P.part, E, st));
+                                    Vcol(j + 1), Bcol(0), s, P.skp, zb, P.part, E, st));
+    SFG_HIP(launch_reduce_rows(P.part, Gn, E, P.red, P.ctl, false, st));
     {
       RqArgs r = rq;
-      r.G = Gn;
       r.forced_k = (forced && j + 1 < J) ? forced[j + 1] : 0;
       SFG_HIP(launch_rq(kRqInit, r, st));
     }
     SFG_HIP(hipStreamSynchronize(st));
-    (void)enq;
     const int err = hsh->error;
     const int kj = hsh->k;
     const double rho = hsh->rho;
@@ -493,14 +551,9 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     if (o.record_true_residual) {
       SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st));
       SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, P.X, st));
-      SpmvArgs a = base_args;
-      a.x = P.X;
-      a.b = b;
-      a.out0 = P.scal;
-      SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, st));
       double r2 = 0.0;
-      SFG_HIP(hipMemcpyAsync(&r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
-      SFG_HIP(hipStreamSynchronize(st));
+      rc = true_residual(P.X, &r2);
+      if (rc) return rc;
       if (info && info->true_residual_history) info->true_residual_history[j] = sqrt(r2) / nb;
     }
     if (hsh->hnext == 0.0 || rho <= tol * nb) {
@@ -512,18 +565,37 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   // ---- x = x0 + Z y, true residual ----------------------------------------
   SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st));
   SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, x, st));
-  {
-    SpmvArgs a = base_args;
-    a.x = x;
-    a.b = b;
-    a.out0 = P.scal;
-    SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, st));
-  }
   double r2 = 0.0;
-  SFG_HIP(hipMemcpyAsync(&r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
-  SFG_HIP(hipStreamSynchronize(st));
+  rc = true_residual(x, &r2);
+  if (rc) return rc;
   const int status = conv ? SFGMRES_OK : SFGMRES_NOT_CONVERGED;
   return finish_info(status, J_done, conv, rho_last / nb, sqrt(r2) / nb);
+}
+
+// Workspace of the stand-alone sketch and SpMV entry points.
+struct SmallLayout {
+  size_t ctl, tiles, tp, ipart, part, red, skp, total;
+};
+
+SmallLayout small_layout(int64_t n, int64_t nnz, int32_t s, int32_t zeta) {
+  SmallLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t E = (size_t)s + kPartExtra;
+  L.ctl = take(sizeof(DevCtl));
+  const size_t ntiles_max = (size_t)(n / kRowTile + nnz / kTileNnz + 3);
+  L.tiles = take((ntiles_max + 1) * 4);
+  L.tp = take((ntiles_max + 1) * 4);
+  L.ipart = take((size_t)(kVecGrid + 1) * 4);
+  L.part = take((size_t)kMaxGrid * E * 8);
+  L.red = take(E * 8);
+  L.skp = take(packed_sketch_bytes(n, zeta));
+  L.total = off;
+  return L;
 }
 
 }  // namespace
@@ -536,14 +608,14 @@ int sfgmres_default_options(sfgmres_options* opt) {
   return SFGMRES_OK;
 }
 
-int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s,
+int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
                             const sfgmres_options* opt, int32_t adjoint, size_t* bytes) {
   if (!bytes) return SFGMRES_ERR_INVALID;
   const sfgmres_options o = opt ? *opt : defaults();
   if (n < 1 || nnz < 0 || m < 1 || s <= m || s > SFGMRES_MAX_S || m > SFGMRES_MAX_M || t < 0 ||
-      o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
+      zeta < 1 || zeta > SFGMRES_MAX_ZETA || o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
     return SFGMRES_ERR_INVALID;
-  *bytes = make_layout(n, nnz, m, t, s, o.max_outer, o.precision, adjoint ? 1 : 0).total;
+  *bytes = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, adjoint ? 1 : 0).total;
   return SFGMRES_OK;
 }
 
@@ -611,7 +683,9 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   const sfgmres_options o = opt ? *opt : defaults();
   int rc = check_params(h, A->n, A->nnz, m, t, s, zeta, tol, o);
   if (rc) return rc;
-  const Layout L = make_layout(A->n, A->nnz, m, t, s, o.max_outer, o.precision, 1);
+  if ((A->nnz > 0 && (!A->col_idx || !A->val)) || !g || !lambda)
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  const Layout L = make_layout(A->n, A->nnz, m, t, s, zeta, o.max_outer, o.precision, 1);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -667,23 +741,27 @@ int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t
   return SFGMRES_OK;
 }
 
-int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta,
-                               uint64_t seed, int32_t* rows, int8_t* signs, void* stream) {
-  if (!h) return SFGMRES_ERR_INVALID;
-  if (n < 1 || s < 1 || s > SFGMRES_MAX_S || zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA)
-    return fail(h, SFGMRES_ERR_INVALID, "invalid (n, s, zeta)");
-  if (!rows || !signs) return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  SFG_HIP(launch_sketch_materialize(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu),
-                                    (uint32_t)(seed >> 32), rows, signs, st));
-  SFG_HIP(hipStreamSynchronize(st));
+int sfgmres_sketch_workspace_bytes(int64_t n, int32_t s, int32_t zeta, size_t* bytes) {
+  if (!bytes || !sketch_args_ok(n, s, zeta)) return SFGMRES_ERR_INVALID;
+  *bytes = small_layout(n, 0, s, zeta).total;
   return SFGMRES_OK;
 }
 
-int sfgmres_sketch_workspace_bytes(int32_t s, size_t* bytes) {
-  if (!bytes || s < 1 || s > SFGMRES_MAX_S) return SFGMRES_ERR_INVALID;
-  const size_t E = (size_t)s + kPartExtra;
-  *bytes = align256(sizeof(DevCtl)) + align256((size_t)kMaxGrid * E * 8) + align256(E * 8);
+int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta,
+                               uint64_t seed, int32_t* rows, int8_t* signs, void* ws,
+                               size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!sketch_args_ok(n, s, zeta)) return fail(h, SFGMRES_ERR_INVALID, "invalid (n, s, zeta)");
+  if (!rows || !signs) return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  const SmallLayout L = small_layout(n, 0, s, zeta);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  uint2* skp = reinterpret_cast<uint2*>(static_cast<char*>(ws) + L.skp);
+  SFG_HIP(launch_sketch_pack(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32),
+                             skp, st));
+  SFG_HIP(launch_sketch_unpack(n, zeta, skp, rows, signs, st));
+  SFG_HIP(hipStreamSynchronize(st));
   return SFGMRES_OK;
 }
 
@@ -691,33 +769,30 @@ int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, u
                          const double* w, double* out, void* ws, size_t ws_bytes,
                          void* stream) {
   if (!h) return SFGMRES_ERR_INVALID;
-  if (n < 1 || s < 1 || s > SFGMRES_MAX_S || zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA)
-    return fail(h, SFGMRES_ERR_INVALID, "invalid (n, s, zeta)");
+  if (!sketch_args_ok(n, s, zeta)) return fail(h, SFGMRES_ERR_INVALID, "invalid (n, s, zeta)");
   if (!w || !out) return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  size_t need = 0;
-  sfgmres_sketch_workspace_bytes(s, &need);
-  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+  const SmallLayout L = small_layout(n, 0, s, zeta);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const int E = s + kPartExtra;
-  DevCtl* ctl = reinterpret_cast<DevCtl*>(base);
-  double* part = reinterpret_cast<double*>(base + align256(sizeof(DevCtl)));
-  double* red = reinterpret_cast<double*>(base + align256(sizeof(DevCtl)) +
-                                          align256((size_t)kMaxGrid * E * 8));
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
+  double* part = reinterpret_cast<double*>(base + L.part);
+  double* red = reinterpret_cast<double*>(base + L.red);
+  uint2* skp = reinterpret_cast<uint2*>(base + L.skp);
   const int G = rows_grid(n);
   SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
-  SFG_HIP(launch_normalize_sketch(false, G, n, w, nullptr, nullptr, nullptr, s, zeta,
-                                  (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32), part, E,
-                                  st));
+  SFG_HIP(launch_sketch_pack(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32),
+                             skp, st));
+  SFG_HIP(launch_normalize_sketch(false, G, n, w, nullptr, nullptr, nullptr, s, skp,
+                                  zeta_blocks(zeta), part, E, st));
+  SFG_HIP(launch_reduce_rows(part, G, E, red, ctl, false, st));
   RqArgs r{};
-  r.part = part;
-  r.G = G;
-  r.E = E;
+  r.red = red;
   r.s = s;
   r.inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
   r.ctl = ctl;
-  r.red = red;
   r.out_c = out;
   r.nwin = 0;
   SFG_HIP(launch_rq(kRqReduce, r, st));
@@ -725,11 +800,9 @@ int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, u
   return SFGMRES_OK;
 }
 
-int sfgmres_spmv_workspace_bytes(int64_t n, int64_t nnz, int32_t s, size_t* bytes) {
-  if (!bytes || n < 1 || nnz < 0 || s < 1 || s > SFGMRES_MAX_S) return SFGMRES_ERR_INVALID;
-  const size_t E = (size_t)s + kPartExtra;
-  *bytes = align256(sizeof(DevCtl)) + align256((size_t)(nnz / 128 + 3) * 4) +
-           align256((size_t)kMaxGrid * E * 8) + align256(E * 8);
+int sfgmres_spmv_workspace_bytes(int64_t n, int64_t nnz, int32_t s, int32_t zeta, size_t* bytes) {
+  if (!bytes || nnz < 0 || !sketch_args_ok(n, s, zeta)) return SFGMRES_ERR_INVALID;
+  *bytes = small_layout(n, nnz, s, zeta).total;
   return SFGMRES_OK;
 }
 
@@ -740,44 +813,43 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   if (!h) return SFGMRES_ERR_INVALID;
   if (!A || !A->row_ptr || !u || !c || !norm2 || (A->nnz > 0 && (!A->col_idx || !A->val)))
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  if (A->n < 1 || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) || s < 1 || s > SFGMRES_MAX_S ||
-      zeta < 1 || zeta > s || zeta > SFGMRES_MAX_ZETA || nwin < 0 || nwin > SFGMRES_MAX_T ||
-      (nwin > 0 && (!U || !dots || ldu < A->n)))
+  if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) || !sketch_args_ok(A->n, s, zeta) || nwin < 0 ||
+      nwin > SFGMRES_MAX_T || (nwin > 0 && (!U || !dots || ldu < A->n)))
     return fail(h, SFGMRES_ERR_INVALID, "invalid sizes");
-  size_t need = 0;
-  sfgmres_spmv_workspace_bytes(A->n, A->nnz, s, &need);
-  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+  const SmallLayout L = small_layout(A->n, A->nnz, s, zeta);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
   const int E = s + kPartExtra;
-  size_t off = 0;
-  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + off);
-  off += align256(sizeof(DevCtl));
-  int32_t* tiles = reinterpret_cast<int32_t*>(base + off);
-  off += align256((size_t)(A->nnz / 128 + 3) * 4);
-  double* part = reinterpret_cast<double*>(base + off);
-  off += align256((size_t)kMaxGrid * E * 8);
-  double* red = reinterpret_cast<double*>(base + off);
-  const int32_t wt = tile_width(A->nnz);
-  const int32_t ntiles = (int32_t)(A->nnz / wt + 1);
-  const int Gp = spmv_grid(ntiles);
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
+  int32_t* tiles = reinterpret_cast<int32_t*>(base + L.tiles);
+  int32_t* tp = reinterpret_cast<int32_t*>(base + L.tp);
+  int32_t* ipart = reinterpret_cast<int32_t*>(base + L.ipart);
+  double* part = reinterpret_cast<double*>(base + L.part);
+  double* red = reinterpret_cast<double*>(base + L.red);
+  uint2* skp = reinterpret_cast<uint2*>(base + L.skp);
+  Tiling tiling{};
+  const int prc = plan_tiling(h, A, tiles, tp, ipart, st, &tiling);
+  if (prc) return prc;
+  const int32_t ntiles = tiling.ntiles;
+  const int Gp = tiling.grid;
   SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
-  SFG_HIP(launch_tiles(A->row_ptr, A->n, A->nnz, wt, tiles, ntiles, st));
+  SFG_HIP(launch_sketch_pack(A->n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu),
+                             (uint32_t)(seed >> 32), skp, st));
   SpmvArgs a{};
   a.n = A->n;
   a.row_ptr = A->row_ptr;
   a.col_idx = A->col_idx;
   a.val = A->val;
   a.tiles = tiles;
+  a.tp = tp;
   a.ntiles = ntiles;
   a.x = u;
   a.scale_val = scale;
   a.w = w;
   a.s = s;
-  a.zeta = zeta;
-  a.k0 = (uint32_t)(seed & 0xFFFFFFFFu);
-  a.k1 = (uint32_t)(seed >> 32);
+  a.skp = skp;
   a.U = U;
   a.ldu = ldu;
   a.l0 = 0;
@@ -785,17 +857,14 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   a.part = part;
   a.E = E;
   a.ctl = ctl;
-  a.hs = h->hs_dev;
-  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, st));
+  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, zeta_blocks(zeta), st));
+  SFG_HIP(launch_reduce_rows(part, Gp, E, red, ctl, false, st));
   RqArgs r{};
-  r.part = part;
-  r.G = Gp;
-  r.E = E;
+  r.red = red;
   r.s = s;
   r.nwin = nwin;
   r.inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
   r.ctl = ctl;
-  r.red = red;
   r.out_c = c;
   r.out_dots = dots;
   r.out_norm2 = norm2;

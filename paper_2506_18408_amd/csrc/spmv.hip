@@ -1,65 +1,118 @@
-// Fused CSR SpMV kernels: w = A u with the sketch S w, the truncated-Arnoldi
-// dot products and squared norms computed in the same pass (the inner step of
-// sketched GMRES, Section 3 with the sketch and truncated Arnoldi of
+// Fused CSR SpMV kernels: y = A u with the sketch S y, the truncated-Arnoldi
+// dot products and the squared norm computed in the same pass (the inner
+// step of sketched GMRES, Section 3 with the sketch and truncated Arnoldi of
 // Section 4.1), plus the outer-loop variants of Algorithm 1 (A z_j with the
-// first Gram-Schmidt dot; the initial residual b - A x0; a true residual).
+// first Gram-Schmidt dot; the initial residual b - A x0; a true residual),
+// and the generation of the packed sketch.
 //
-// Design (gfx950): a persistent grid of 256-thread workgroups walks
-// nnz-balanced row tiles.  A tile's nonzeros are streamed with coalesced
-// loads into LDS as products val*x[col] (phase A), then groups of 1..64 lanes
-// reduce one row each from LDS (phase B, group width chosen per tile from its
-// row count), and the row leader runs the epilogue: scale, store, scatter
-// +-w_r into the workgroup's LDS sketch accumulators (zeta Floyd-sampled rows
-// generated from Philox4x32-10 in registers, no sketch stored in HBM) and
-// accumulate the dot products in registers.  Each workgroup finally writes one
-// row of partial sums; a separate reduction (or the last workgroup, for the
-// scalar-only variants) combines the rows in a fixed order.
+// Design (gfx950): a persistent grid of 256-thread workgroups walks row
+// tiles (256 rows each when every row has at most 8 nonzeros, else tiles of
+// about 1024 nonzeros); each XCD gets a contiguous range of tiles.  A tile's
+// nonzeros (at most kStage) are loaded with coalesced loads into registers,
+// multiplied by the gathered x[col] and staged in LDS; groups of 1..64 lanes
+// then reduce one row each from LDS, and the row leader runs the epilogue:
+// store, scatter +-y_r into its wave's LDS sketch accumulators (the zeta rows
+// and signs of column r of S come from the packed sketch) and accumulate the
+// dot products in registers.  The loop is software-pipelined: the next
+// tile's column indices and values are requested before the current tile's
+// reduction and epilogue, and the epilogue's own inputs (window vectors,
+// packed sketch) before its LDS reads, so every wave keeps memory requests
+// in flight.  Each workgroup finally writes one row of partial sums; a
+// separate kernel combines the rows in a fixed order.
 #include "kernels.hpp"
 
 namespace sfg {
 
-__global__ void k_tiles(const int32_t* __restrict__ row_ptr, int64_t n, int64_t nnz, int32_t wt,
-                        int32_t* __restrict__ tiles, int32_t ntiles) {
+// Tile boundaries: tiles[b] = first row of tile b, tp[b] = row_ptr[tiles[b]].
+// rows_per_tile > 0: fixed row count; else the first row whose first nonzero
+// index is >= b * wt.
+__global__ void k_tiles(const int32_t* __restrict__ row_ptr, int64_t n, int32_t wt,
+                        int32_t rows_per_tile, int32_t* __restrict__ tiles,
+                        int32_t* __restrict__ tp, int32_t ntiles) {
   const int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (b > ntiles) return;
+  int64_t row;
   if (b == 0) {
-    tiles[0] = 0;
-    return;
+    row = 0;
+  } else if (b == ntiles) {
+    row = n;
+  } else if (rows_per_tile > 0) {
+    row = b * rows_per_tile < n ? b * rows_per_tile : n;
+  } else {
+    const int64_t target = b * (int64_t)wt;
+    int64_t lo = 0, hi = n;
+    while (lo < hi) {
+      const int64_t mid = (lo + hi) >> 1;
+      if ((int64_t)row_ptr[mid] < target)
+        lo = mid + 1;
+      else
+        hi = mid;
+    }
+    row = lo;
   }
-  if (b == ntiles) {
-    tiles[ntiles] = (int32_t)n;
-    return;
-  }
-  // first row whose first nonzero index is >= b * wt
-  const int64_t target = b * (int64_t)wt;
-  int64_t lo = 0, hi = n;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if ((int64_t)row_ptr[mid] < target)
-      lo = mid + 1;
-    else
-      hi = mid;
-  }
-  tiles[b] = (int32_t)lo;
+  tiles[b] = (int32_t)row;
+  tp[b] = row_ptr[row];
 }
 
-hipError_t launch_tiles(const int32_t* row_ptr, int64_t n, int64_t nnz, int32_t wt,
-                        int32_t* tiles, int32_t ntiles, hipStream_t st) {
+hipError_t launch_tiles(const int32_t* row_ptr, int64_t n, int32_t wt, int32_t rows_per_tile,
+                        int32_t* tiles, int32_t* tp, int32_t ntiles, hipStream_t st) {
   const int threads = 256;
   const int blocks = (int)((ntiles + 1 + threads - 1) / threads);
-  hipLaunchKernelGGL(k_tiles, dim3(blocks), dim3(threads), 0, st, row_ptr, n, nnz, wt, tiles,
-                     ntiles);
+  hipLaunchKernelGGL(k_tiles, dim3(blocks), dim3(threads), 0, st, row_ptr, n, wt, rows_per_tile,
+                     tiles, tp, ntiles);
   return hipGetLastError();
 }
 
-template <typename VT, int ZB, int MODE>
+// Longest row: per-workgroup maxima, then one workgroup takes the maximum.
+__global__ __launch_bounds__(256) void k_rowlen_part(const int32_t* __restrict__ row_ptr,
+                                                     int64_t n, int32_t* __restrict__ part) {
+  __shared__ int32_t sm[256];
+  int32_t mx = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const int32_t len = row_ptr[r + 1] - row_ptr[r];
+    mx = len > mx ? len : mx;
+  }
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o && sm[threadIdx.x + o] > sm[threadIdx.x]) sm[threadIdx.x] = sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(256) void k_rowlen_final(const int32_t* __restrict__ part, int32_t G,
+                                                      int32_t* __restrict__ out) {
+  __shared__ int32_t sm[256];
+  int32_t mx = 0;
+  for (int i = threadIdx.x; i < G; i += blockDim.x) mx = part[i] > mx ? part[i] : mx;
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o && sm[threadIdx.x + o] > sm[threadIdx.x]) sm[threadIdx.x] = sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, int32_t* out,
+                             hipStream_t st) {
+  const int g = vec_grid(n);
+  hipLaunchKernelGGL(k_rowlen_part, dim3(g), dim3(256), 0, st, row_ptr, n, part);
+  hipLaunchKernelGGL(k_rowlen_final, dim3(1), dim3(256), 0, st, part, g, out);
+  return hipGetLastError();
+}
+
+template <typename VT, int ZB, int MODE, int NW>
 __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
   constexpr bool kSketch = ZB > 0;
   constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain);
-  __shared__ double prod[kTileCap];
-  extern __shared__ double lds_sk[];  // s doubles when sketching
-  __shared__ double scratch[kSpmvThreads / kWave];
-  __shared__ int lds_flag;
+  constexpr int kWaves = kSpmvThreads / kWave;
+  constexpr int kU = kStage / kSpmvThreads;
+  __shared__ double prod[kStage];
+  extern __shared__ double lds_sk[];  // kWaves x s doubles when sketching (per-wave copies)
+  __shared__ double scratch[kWaves];
 
   if (MODE == kModeInner && a.ctl->stop_k != 0) return;
 
@@ -76,74 +129,119 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
   VT* __restrict__ w = static_cast<VT*>(a.w);
   const VT* __restrict__ U = static_cast<const VT*>(a.U);
   const bool has_x = (MODE != kModeResid) || a.has_x;
-  const double scale = kInnerLike ? (a.scale_ptr ? *a.scale_ptr : a.scale_val) : 1.0;
+  const double scale = (MODE == kModePlain)   ? a.scale_val
+                       : (MODE == kModeInner) ? (a.scale_ptr ? *a.scale_ptr : 1.0)
+                                              : 1.0;
+  const int nwin = NW < a.nwin ? NW : a.nwin;
 
+  double* const wave_sk = lds_sk + (tid / kWave) * a.s;
   if (kSketch)
-    for (int q = tid; q < a.s; q += kSpmvThreads) lds_sk[q] = 0.0;
+    for (int q = tid; q < kWaves * a.s; q += kSpmvThreads) lds_sk[q] = 0.0;
 
-  double dacc[kMaxT];
+  double dacc[NW > 0 ? NW : 1];
 #pragma unroll
-  for (int l = 0; l < kMaxT; ++l) dacc[l] = 0.0;
+  for (int l = 0; l < (NW > 0 ? NW : 1); ++l) dacc[l] = 0.0;
   double n2 = 0.0, ex = 0.0;
 
-  auto epilogue = [&](int r, double y) {
+  // inputs of the epilogue of row r, independent of the row sum
+  struct Pre {
+    double u[NW > 0 ? NW : 1];
+    uint2 sk[ZB > 0 ? ZB : 1];
+    double b0, b1;
+  };
+  auto load_pre = [&](int r, Pre& p) {
+    if constexpr (kInnerLike) {
+#pragma unroll
+      for (int l = 0; l < NW; ++l)
+        p.u[l] = l < nwin ? static_cast<double>(U[(int64_t)(a.l0 + l) * a.ldu + r]) : 0.0;
+#pragma unroll
+      for (int b = 0; b < ZB; ++b) p.sk[b] = a.skp[(int64_t)r * ZB + b];
+    } else if constexpr (MODE == kModeOuter) {
+      p.b0 = a.v0[r];
+      p.b1 = a.vj[r];
+    } else {
+      p.b0 = a.b[r];
+    }
+  };
+  auto epilogue = [&](int r, double y, const Pre& p) {
     if constexpr (kInnerLike) {
       const VT wv = static_cast<VT>(scale * y);
       if (w) w[r] = wv;
       const double wd = static_cast<double>(wv);
-      if constexpr (kSketch) sketch_scatter<ZB>(lds_sk, (uint32_t)r, wd, a.s, a.zeta, a.k0, a.k1);
+      if constexpr (kSketch) {
 #pragma unroll
-      for (int l = 0; l < kMaxT; ++l)
-        if (l < a.nwin) dacc[l] += wd * static_cast<double>(U[(int64_t)(a.l0 + l) * a.ldu + r]);
+        for (int b = 0; b < ZB; ++b) {
+          const uint32_t f[4] = {p.sk[b].x & 0xFFFFu, p.sk[b].x >> 16, p.sk[b].y & 0xFFFFu,
+                                 p.sk[b].y >> 16};
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            if (f[e] != kSkEmpty) {
+              const double av = (f[e] & 0x8000u) ? -wd : wd;
+              __hip_atomic_fetch_add(&wave_sk[f[e] & 0x7FFFu], av, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int l = 0; l < NW; ++l) dacc[l] += wd * p.u[l];
       n2 += wd * wd;
     } else if constexpr (MODE == kModeOuter) {
       w[r] = static_cast<VT>(y);
-      dacc[0] += y * a.v0[r];
-      const double dl = a.vj[r] - y;
+      dacc[0] += y * p.b0;
+      const double dl = p.b1 - y;
       ex += dl * dl;
     } else if constexpr (MODE == kModeResid) {
-      const double br = a.b[r];
+      const double br = p.b0;
       const double wr = br - y;
       w[r] = static_cast<VT>(wr);
       n2 += wr * wr;
       ex += br * br;
     } else {  // kModeTrueRes
-      const double wr = a.b[r] - y;
+      const double wr = p.b0 - y;
       n2 += wr * wr;
     }
   };
 
+  // staged nonzeros of the tile being loaded
+  int ci[kU];
+  double vv[kU];
+  int c_r0 = 0, c_r1 = 0, c_p0 = 0, c_L = 0;
+  auto fetch = [&](int tl) {
+    c_r0 = a.tiles[tl];
+    c_r1 = a.tiles[tl + 1];
+    c_p0 = a.tp[tl];
+    c_L = a.tp[tl + 1] - c_p0;
+    if (has_x && c_L <= kStage) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const int q = u * kSpmvThreads + tid;
+        if (q < c_L) {
+          ci[u] = __builtin_nontemporal_load(&col_idx[c_p0 + q]);
+          vv[u] = static_cast<double>(__builtin_nontemporal_load(&val[c_p0 + q]));
+        }
+      }
+    }
+  };
+
+  if (t0 < t1) fetch(t0);
   __syncthreads();
   for (int tl = t0; tl < t1; ++tl) {
-    const int r0 = a.tiles[tl];
-    const int r1 = a.tiles[tl + 1];
-    if (r0 >= r1) continue;
-    const int p0 = row_ptr[r0];
-    const int L = row_ptr[r1] - p0;
-    if (L <= kTileCap) {
-      // phase A: coalesced stream of the tile's nonzeros into LDS products
+    const int r0 = c_r0, r1 = c_r1, p0 = c_p0, L = c_L;
+    if (r0 >= r1) {
+      if (tl + 1 < t1) fetch(tl + 1);
+      continue;
+    }
+    if (L <= kStage) {
       if (has_x) {
-        constexpr int kU = 8;
-        for (int base = 0; base < L; base += kU * kSpmvThreads) {
-          int cidx[kU];
-          double vv[kU];
 #pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int q = base + u * kSpmvThreads + tid;
-            if (q < L) {
-              cidx[u] = __builtin_nontemporal_load(&col_idx[p0 + q]);
-              vv[u] = static_cast<double>(__builtin_nontemporal_load(&val[p0 + q]));
-            }
-          }
-#pragma unroll
-          for (int u = 0; u < kU; ++u) {
-            const int q = base + u * kSpmvThreads + tid;
-            if (q < L) prod[q] = vv[u] * static_cast<double>(x[cidx[u]]);
-          }
+        for (int u = 0; u < kU; ++u) {
+          const int q = u * kSpmvThreads + tid;
+          if (q < L) prod[q] = vv[u] * static_cast<double>(x[ci[u]]);
         }
       }
       __syncthreads();
-      // phase B: groups of gsz lanes reduce one row each
+      if (tl + 1 < t1) fetch(tl + 1);  // in flight during this tile's reduction
       const int nrows = r1 - r0;
       int gsz = 1;
       while (gsz < kWave && nrows * gsz * 2 <= kSpmvThreads) gsz <<= 1;
@@ -152,6 +250,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
       const int gl = tid & (gsz - 1);
       for (int rr = grp; rr < nrows; rr += ngroups) {
         const int r = r0 + rr;
+        Pre pre;
+        if (gl == 0) load_pre(r, pre);
         double acc = 0.0;
         if (has_x) {
           const int qa = row_ptr[r] - p0;
@@ -159,11 +259,11 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
           for (int q = qa + gl; q < qe; q += gsz) acc += prod[q];
         }
         for (int off = gsz >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
-        if (gl == 0) epilogue(r, acc);
+        if (gl == 0) epilogue(r, acc, pre);
       }
       __syncthreads();
     } else {
-      // tile holding a row longer than the LDS capacity: whole workgroup per row
+      // a tile whose rows exceed the stage: the whole workgroup per row
       for (int r = r0; r < r1; ++r) {
         double acc = 0.0;
         if (has_x) {
@@ -173,29 +273,38 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
             acc += static_cast<double>(val[q]) * static_cast<double>(x[col_idx[q]]);
         }
         acc = block_sum(acc, scratch);
-        if (tid == 0) epilogue(r, acc);
+        if (tid == 0) {
+          Pre pre;
+          load_pre(r, pre);
+          epilogue(r, acc, pre);
+        }
       }
+      if (tl + 1 < t1) fetch(tl + 1);
     }
   }
 
   // one row of partial sums per workgroup (fixed slot = blockIdx.x)
   double* prow = a.part + (int64_t)blockIdx.x * a.E;
-  const int sb = kSketch ? a.s : 0;
   if constexpr (kSketch) {
     __syncthreads();
-    for (int q = tid; q < a.s; q += kSpmvThreads) prow[q] = lds_sk[q];
+    for (int q = tid; q < a.s; q += kSpmvThreads) {
+      double v = lds_sk[q];
+#pragma unroll
+      for (int wv = 1; wv < kWaves; ++wv) v += lds_sk[wv * a.s + q];
+      prow[q] = v;
+    }
   }
+  const int sb = kSketch ? a.s : 0;
   if constexpr (kInnerLike) {
 #pragma unroll
-    for (int l = 0; l < kMaxT; ++l) {
-      if (l < a.nwin) {
+    for (int l = 0; l < NW; ++l) {
+      if (l < nwin) {
         const double v = block_sum(dacc[l], scratch);
         if (tid == 0) prow[sb + l] = v;
       }
     }
     const double v = block_sum(n2, scratch);
     if (tid == 0) prow[sb + kMaxT] = v;
-    return;
   } else {
     const double s0 = block_sum(MODE == kModeOuter ? dacc[0] : n2, scratch);
     const double s1 = block_sum(ex, scratch);
@@ -203,84 +312,168 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
       prow[kMaxT] = s0;
       prow[kMaxT + 1] = s1;
     }
-    if (!last_block_arrival(&a.ctl->ticket[0], G, &lds_flag)) return;
-    // the last workgroup combines the scalar partials in slot order
-    double t0s = 0.0, t1s = 0.0;
-    for (int i = tid; i < G; i += kSpmvThreads) {
-      t0s += a.part[(int64_t)i * a.E + kMaxT];
-      t1s += a.part[(int64_t)i * a.E + kMaxT + 1];
-    }
-    t0s = block_sum(t0s, scratch);
-    t1s = block_sum(t1s, scratch);
-    if (tid == 0) {
-      DevCtl* c = a.ctl;
-      if (MODE == kModeOuter) {
-        a.out0[0] = t0s;   // h_{1,j}
-        c->rhat2 = t1s;
-      } else if (MODE == kModeResid) {
-        const double beta = sqrt(t0s);
-        const double nb = sqrt(t1s);
-        c->beta = beta;
-        c->nb = nb;
-        c->factor = beta;
-        c->tol_abs = c->tol_abs * nb;  // tol_abs held the relative tol until here
-        a.out0[0] = beta;              // g_1 = beta
-        if (!isfinite(beta) || !isfinite(nb)) c->error = SFGMRES_ERR_NONFINITE;
-        host_store_f64(&a.hs->beta, beta);
-        host_store_f64(&a.hs->nb, nb);
-        host_store_i32(&a.hs->error, c->error);
-        __threadfence_system();
-      } else {
-        a.out0[0] = t0s;
-      }
-    }
+  }
+}
+
+template <typename VT, int MODE, int NW>
+static void launch_spmv_zb(int zb, int grid, const SpmvArgs& a, hipStream_t st) {
+  const size_t lds = zb > 0 ? (size_t)(kSpmvThreads / kWave) * a.s * sizeof(double) : 0;
+  switch (zb) {
+    case 0:
+      hipLaunchKernelGGL((k_spmv<VT, 0, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      break;
+    case 1:
+      hipLaunchKernelGGL((k_spmv<VT, 1, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      break;
+    case 2:
+      hipLaunchKernelGGL((k_spmv<VT, 2, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      break;
+    case 3:
+      hipLaunchKernelGGL((k_spmv<VT, 3, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      break;
+    default:
+      hipLaunchKernelGGL((k_spmv<VT, 4, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      break;
   }
 }
 
 template <typename VT, int MODE>
-static hipError_t launch_spmv_t(int zb, int grid, const SpmvArgs& a, hipStream_t st) {
-  const size_t lds = zb > 0 ? (size_t)a.s * sizeof(double) : 0;
-  switch (zb) {
-    case 0:
-      hipLaunchKernelGGL((k_spmv<VT, 0, MODE>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+static void launch_spmv_nw(int zb, int grid, const SpmvArgs& a, hipStream_t st) {
+  if (a.nwin <= 0)
+    launch_spmv_zb<VT, MODE, 0>(zb, grid, a, st);
+  else if (a.nwin <= 2)
+    launch_spmv_zb<VT, MODE, 2>(zb, grid, a, st);
+  else if (a.nwin <= 4)
+    launch_spmv_zb<VT, MODE, 4>(zb, grid, a, st);
+  else
+    launch_spmv_zb<VT, MODE, kMaxT>(zb, grid, a, st);
+}
+
+hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st) {
+  switch (mode) {
+    case kModeInner:
+      if (fp32)
+        launch_spmv_nw<float, kModeInner>(zb, grid, a, st);
+      else
+        launch_spmv_nw<double, kModeInner>(zb, grid, a, st);
       break;
-    case 1:
-      hipLaunchKernelGGL((k_spmv<VT, 1, MODE>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+    case kModePlain:
+      launch_spmv_nw<double, kModePlain>(zb, grid, a, st);
       break;
-    case 2:
-      hipLaunchKernelGGL((k_spmv<VT, 2, MODE>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+    case kModeOuter:
+      hipLaunchKernelGGL((k_spmv<double, 0, kModeOuter, 1>), dim3(grid), dim3(kSpmvThreads), 0,
+                         st, a);
       break;
-    case 3:
-      hipLaunchKernelGGL((k_spmv<VT, 3, MODE>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+    case kModeResid:
+      hipLaunchKernelGGL((k_spmv<double, 0, kModeResid, 0>), dim3(grid), dim3(kSpmvThreads), 0,
+                         st, a);
       break;
     default:
-      hipLaunchKernelGGL((k_spmv<VT, 4, MODE>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      hipLaunchKernelGGL((k_spmv<double, 0, kModeTrueRes, 0>), dim3(grid), dim3(kSpmvThreads), 0,
+                         st, a);
       break;
   }
   return hipGetLastError();
 }
 
-hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, hipStream_t st) {
-  const int zb = a.s > 0 ? zeta_blocks(a.zeta) : 0;
-  switch (mode) {
-    case kModeInner:
-      return fp32 ? launch_spmv_t<float, kModeInner>(zb, grid, a, st)
-                  : launch_spmv_t<double, kModeInner>(zb, grid, a, st);
-    case kModePlain:
-      return launch_spmv_t<double, kModePlain>(zb, grid, a, st);
-    case kModeOuter:
-      hipLaunchKernelGGL((k_spmv<double, 0, kModeOuter>), dim3(grid), dim3(kSpmvThreads), 0, st,
-                         a);
-      return hipGetLastError();
-    case kModeResid:
-      hipLaunchKernelGGL((k_spmv<double, 0, kModeResid>), dim3(grid), dim3(kSpmvThreads), 0, st,
-                         a);
-      return hipGetLastError();
-    default:
-      hipLaunchKernelGGL((k_spmv<double, 0, kModeTrueRes>), dim3(grid), dim3(kSpmvThreads), 0,
-                         st, a);
-      return hipGetLastError();
+// ---------------------------------------------------------------- finisher
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv_finish(int mode, const double* part,
+                                                              int32_t G, int32_t E, DevCtl* c,
+                                                              double* out0, HostStatus* hs) {
+  __shared__ double scratch[kSpmvThreads / kWave];
+  const double t0s = block_sum_strided(part + kMaxT, G, E, scratch);
+  const double t1s = block_sum_strided(part + kMaxT + 1, G, E, scratch);
+  if (threadIdx.x != 0) return;
+  if (mode == kModeOuter) {
+    out0[0] = t0s;  // h_{1,j}
+    c->rhat2 = t1s;
+  } else if (mode == kModeResid) {
+    const double beta = sqrt(t0s);
+    const double nb = sqrt(t1s);
+    c->beta = beta;
+    c->nb = nb;
+    c->factor = beta;
+    c->tol_abs = c->tol_abs * nb;  // tol_abs held the relative tol until here
+    out0[0] = beta;                // g_1 = beta
+    if (!isfinite(beta) || !isfinite(nb)) c->error = SFGMRES_ERR_NONFINITE;
+    host_store_f64(&hs->beta, beta);
+    host_store_f64(&hs->nb, nb);
+    host_store_i32(&hs->error, c->error);
+    __threadfence_system();
+  } else {
+    out0[0] = t0s;
   }
+}
+
+hipError_t launch_spmv_finish(int mode, const double* part, int32_t G, int32_t E, DevCtl* ctl,
+                              double* out0, HostStatus* hs, hipStream_t st) {
+  hipLaunchKernelGGL(k_spmv_finish, dim3(1), dim3(kSpmvThreads), 0, st, mode, part, G, E, ctl,
+                     out0, hs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ packed sketch
+template <int ZB>
+__global__ void k_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, uint32_t k1,
+                              uint2* __restrict__ skp) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    int rows[4 * ZB];
+    uint32_t neg;
+    sketch_column<ZB>((uint32_t)r, s, zeta, k0, k1, rows, neg);
+#pragma unroll
+    for (int b = 0; b < ZB; ++b) {
+      uint32_t f[4];
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int d = 4 * b + e;
+        f[e] = d < zeta ? ((uint32_t)rows[d] | (((neg >> d) & 1u) << 15)) : kSkEmpty;
+      }
+      skp[r * ZB + b] = make_uint2(f[0] | (f[1] << 16), f[2] | (f[3] << 16));
+    }
+  }
+}
+
+hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, uint32_t k1,
+                              uint2* skp, hipStream_t st) {
+  const int grid = vec_grid(n);
+  switch (zeta_blocks(zeta)) {
+    case 1:
+      hipLaunchKernelGGL(k_sketch_pack<1>, dim3(grid), dim3(256), 0, st, n, s, zeta, k0, k1, skp);
+      break;
+    case 2:
+      hipLaunchKernelGGL(k_sketch_pack<2>, dim3(grid), dim3(256), 0, st, n, s, zeta, k0, k1, skp);
+      break;
+    case 3:
+      hipLaunchKernelGGL(k_sketch_pack<3>, dim3(grid), dim3(256), 0, st, n, s, zeta, k0, k1, skp);
+      break;
+    default:
+      hipLaunchKernelGGL(k_sketch_pack<4>, dim3(grid), dim3(256), 0, st, n, s, zeta, k0, k1, skp);
+      break;
+  }
+  return hipGetLastError();
+}
+
+__global__ void k_sketch_unpack(int64_t n, int32_t zeta, const uint2* __restrict__ skp,
+                                int32_t* __restrict__ rows, int8_t* __restrict__ signs) {
+  const int zb = zeta_blocks(zeta);
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    for (int d = 0; d < zeta; ++d) {
+      const uint2 q = skp[r * zb + d / 4];
+      const uint32_t word = (d & 2) ? q.y : q.x;
+      const uint32_t f = (d & 1) ? (word >> 16) : (word & 0xFFFFu);
+      rows[r * zeta + d] = (int32_t)(f & 0x7FFFu);
+      signs[r * zeta + d] = (f & 0x8000u) ? (int8_t)-1 : (int8_t)1;
+    }
+  }
+}
+
+hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const uint2* skp, int32_t* rows,
+                                int8_t* signs, hipStream_t st) {
+  hipLaunchKernelGGL(k_sketch_unpack, dim3(vec_grid(n)), dim3(256), 0, st, n, zeta, skp, rows,
+                     signs);
+  return hipGetLastError();
 }
 
 }  // namespace sfg

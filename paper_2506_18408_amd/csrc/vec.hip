@@ -1,15 +1,24 @@
 // Vector kernels of the sketched-FGMRES path: the truncated-Arnoldi update
-// (Section 4.1), the outer modified Gram-Schmidt passes with the Givens
-// update of the Hessenberg least-squares problem (Algorithm 1), the
-// normalisation of v_{j+1} fused with its sketch, the small triangular
-// solves, the tall-skinny combinations z_j = B_k y and x = x0 + Z y, the
-// float32 value cast, the adjoint's CSR transpose and value gradient, and the
-// sketch export used by tests.
+// (Section 4.1), the outer modified Gram-Schmidt passes and the Givens update
+// of the Hessenberg least-squares problem (Algorithm 1), the normalisation of
+// v_{j+1} fused with its sketch, the small triangular solves, the tall-skinny
+// combinations z_j = B_k y and x = x0 + Z y, the float32 value cast, and the
+// adjoint's CSR transpose and value gradient.
+//
+// Streaming loops load every input of kUnroll elements per thread before
+// they compute and store, so each thread keeps several loads in flight.
 #include "kernels.hpp"
 
 namespace sfg {
 
-constexpr int kVecThreads = 256;
+constexpr int kUnroll = 4;
+
+int vec_grid(int64_t n) {
+  int64_t g = (n + kVecThreads * kUnroll - 1) / (kVecThreads * kUnroll);
+  if (g > kVecGrid) g = kVecGrid;
+  if (g < 1) g = 1;
+  return (int)g;
+}
 
 // ---------------------------------------------------------------- control
 __global__ void k_init_ctl(DevCtl* c, int32_t m, int32_t t, int32_t s, double cond_threshold,
@@ -20,7 +29,7 @@ __global__ void k_init_ctl(DevCtl* c, int32_t m, int32_t t, int32_t s, double co
   z.t = t;
   z.s = s;
   z.cond_threshold = cond_threshold;
-  z.tol_abs = tol;  // relative until the residual kernel multiplies by ||b||
+  z.tol_abs = tol;  // relative until the residual finisher multiplies by ||b||
   z.factor = INFINITY;
   *c = z;
 }
@@ -32,103 +41,132 @@ hipError_t launch_init_ctl(DevCtl* ctl, int32_t m, int32_t t, int32_t s, double 
 }
 
 // ------------------------------------------------ truncated Arnoldi update
-// u_{i+1} = w - sum_l coef_l u_l over the window; ||u_{i+1}||^2 reduced by
-// the last workgroup into the scale sigma_{i+1} = 1/||u_{i+1}||.
+// u_{i+1} = coef_t y - sum_l coef_l u_l over the window; each workgroup writes its
+// partial ||u_{i+1}||^2 to vpart[blockIdx.x] (summed by the next decision
+// kernel into sigma_{i+1}).
 template <typename VT>
 __global__ __launch_bounds__(kVecThreads) void k_arnoldi(int64_t n, const VT* __restrict__ W,
-                                                         VT* __restrict__ B, int64_t ldb,
-                                                         int32_t l0, int32_t nwin,
-                                                         int32_t inext,
+                                                         VT* B, int64_t ldb, int32_t l0,
+                                                         int32_t nwin, int32_t inext,
                                                          const double* __restrict__ coef,
-                                                         double* sigma, double* part,
-                                                         DevCtl* ctl, HostStatus* hs,
-                                                         int32_t step) {
+                                                         double* __restrict__ vpart,
+                                                         const DevCtl* ctl) {
   __shared__ double scratch[kVecThreads / kWave];
-  __shared__ double cf[kMaxT];
-  __shared__ int flag;
+  __shared__ double cf[kMaxT + 1];
   if (ctl->stop_k != 0) return;
   const int tid = threadIdx.x;
-  if (tid < kMaxT) cf[tid] = tid < nwin ? coef[tid] : 0.0;
+  if (tid <= kMaxT) cf[tid] = (tid < nwin || tid == kMaxT) ? coef[tid] : 0.0;
   __syncthreads();
-  VT* __restrict__ out = B + (int64_t)inext * ldb;
+  const double ys = cf[kMaxT];
+  VT* out = B + (int64_t)inext * ldb;
+  const VT* win = B + (int64_t)l0 * ldb;
   double n2 = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
-  for (int64_t r = (int64_t)blockIdx.x * kVecThreads + tid; r < n; r += stride) {
-    double acc = static_cast<double>(W[r]);
+  const int64_t step = (int64_t)gridDim.x * kVecThreads * kUnroll;
+  for (int64_t base = (int64_t)blockIdx.x * kVecThreads * kUnroll + tid; base < n; base += step) {
+    double acc[kUnroll];
 #pragma unroll
-    for (int l = 0; l < kMaxT; ++l)
-      if (l < nwin) acc -= cf[l] * static_cast<double>(B[(int64_t)(l0 + l) * ldb + r]);
-    const VT u = static_cast<VT>(acc);
-    out[r] = u;
-    const double ud = static_cast<double>(u);
-    n2 += ud * ud;
-  }
-  n2 = block_sum(n2, scratch);
-  if (tid == 0) part[blockIdx.x] = n2;
-  if (!last_block_arrival(&ctl->ticket[2], gridDim.x, &flag)) return;
-  double tsum = 0.0;
-  for (int i = tid; i < (int)gridDim.x; i += kVecThreads) tsum += part[i];
-  tsum = block_sum(tsum, scratch);
-  if (tid == 0) {
-    if (tsum == 0.0) {
-      ctl->stop_k = step + 1;
-      ctl->stop_step = step + 1;
-      ctl->stop_reason = SFGMRES_STOP_BREAKDOWN;
-      host_store_i32(&hs->stop_k, ctl->stop_k);
-      host_store_i32(&hs->stop_step, ctl->stop_step);
-      host_store_i32(&hs->stop_reason, ctl->stop_reason);
-      __threadfence_system();
-    } else {
-      sigma[inext] = 1.0 / sqrt(tsum);
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = base + u * kVecThreads;
+      acc[u] = r < n ? ys * static_cast<double>(W[r]) : 0.0;
+    }
+    for (int l = 0; l < nwin; ++l) {
+      double bl[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t r = base + u * kVecThreads;
+        bl[u] = r < n ? static_cast<double>(win[(int64_t)l * ldb + r]) : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) acc[u] -= cf[l] * bl[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = base + u * kVecThreads;
+      if (r < n) {
+        const VT v = static_cast<VT>(acc[u]);
+        out[r] = v;
+        const double vd = static_cast<double>(v);
+        n2 += vd * vd;
+      }
     }
   }
+  n2 = block_sum(n2, scratch);
+  if (tid == 0) vpart[blockIdx.x] = n2;
 }
 
 hipError_t launch_arnoldi_update(bool fp32, int grid, int64_t n, const void* W, void* B,
                                  int64_t ldb, int32_t l0, int32_t nwin, int32_t inext,
-                                 const double* coef, double* sigma, double* part, DevCtl* ctl,
-                                 HostStatus* hs, int32_t step, hipStream_t st) {
+                                 const double* coef, double* vpart, const DevCtl* ctl,
+                                 hipStream_t st) {
   if (fp32)
     hipLaunchKernelGGL(k_arnoldi<float>, dim3(grid), dim3(kVecThreads), 0, st, n,
                        static_cast<const float*>(W), static_cast<float*>(B), ldb, l0, nwin,
-                       inext, coef, sigma, part, ctl, hs, step);
+                       inext, coef, vpart, ctl);
   else
     hipLaunchKernelGGL(k_arnoldi<double>, dim3(grid), dim3(kVecThreads), 0, st, n,
                        static_cast<const double*>(W), static_cast<double*>(B), ldb, l0, nwin,
-                       inext, coef, sigma, part, ctl, hs, step);
+                       inext, coef, vpart, ctl);
   return hipGetLastError();
 }
 
 // ------------------------------------------- outer Gram-Schmidt + Givens
 // Pass l of modified Gram-Schmidt at outer step j: w <- w - h_{l,j} v_l and
-// the next coefficient <w, v_{l+1}>, or for the last pass ||w||, which gives
-// h_{j+1,j}; the last pass also rotates column j of the Hessenberg matrix
-// with the previous Givens rotations, forms rotation j, updates g and
-// publishes |g_{j+1}| (the minimised residual) and the FFOM residual
-// |g_{j+1}| / |c_j| (eq. (2.1) via the standard FOM/GMRES relation).
-__global__ __launch_bounds__(kVecThreads) void k_mgs(
-    int64_t n, double* __restrict__ W, const double* __restrict__ Vcur,
-    const double* __restrict__ Vnext, const double* hcur, double* hout, double* part,
-    DevCtl* ctl, int last, double* H, double* HR, double* cs, double* sn, double* g, int32_t j,
-    int32_t ldh, HostStatus* hs) {
+// the partial sums of the next coefficient <w, v_{l+1}>, or for the last
+// pass of ||w||^2.
+__global__ __launch_bounds__(kVecThreads) void k_mgs_pass(int64_t n, double* __restrict__ W,
+                                                          const double* __restrict__ Vcur,
+                                                          const double* __restrict__ Vnext,
+                                                          const double* hcur,
+                                                          double* __restrict__ vpart,
+                                                          int last) {
   __shared__ double scratch[kVecThreads / kWave];
-  __shared__ int flag;
   const int tid = threadIdx.x;
   const double h = *hcur;
   double acc = 0.0;
-  const int64_t stride = (int64_t)gridDim.x * kVecThreads;
-  for (int64_t r = (int64_t)blockIdx.x * kVecThreads + tid; r < n; r += stride) {
-    const double wv = W[r] - h * Vcur[r];
-    W[r] = wv;
-    acc += wv * (last ? wv : Vnext[r]);
+  const int64_t step = (int64_t)gridDim.x * kVecThreads * kUnroll;
+  for (int64_t base = (int64_t)blockIdx.x * kVecThreads * kUnroll + tid; base < n; base += step) {
+    double wv[kUnroll], vc[kUnroll], vn[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = base + u * kVecThreads;
+      const bool ok = r < n;
+      wv[u] = ok ? W[r] : 0.0;
+      vc[u] = ok ? Vcur[r] : 0.0;
+      vn[u] = (ok && !last) ? Vnext[r] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = base + u * kVecThreads;
+      const double x = wv[u] - h * vc[u];
+      if (r < n) W[r] = x;
+      acc += x * (last ? x : vn[u]);
+    }
   }
   acc = block_sum(acc, scratch);
-  if (tid == 0) part[blockIdx.x] = acc;
-  if (!last_block_arrival(&ctl->ticket[3], gridDim.x, &flag)) return;
-  double tsum = 0.0;
-  for (int i = tid; i < (int)gridDim.x; i += kVecThreads) tsum += part[i];
-  tsum = block_sum(tsum, scratch);
-  if (tid != 0) return;
+  if (tid == 0) vpart[blockIdx.x] = acc;
+}
+
+hipError_t launch_mgs_pass(int grid, int64_t n, double* W, const double* Vcur,
+                           const double* Vnext, const double* hcur, double* vpart, int last,
+                           hipStream_t st) {
+  hipLaunchKernelGGL(k_mgs_pass, dim3(grid), dim3(kVecThreads), 0, st, n, W, Vcur, Vnext, hcur,
+                     vpart, last);
+  return hipGetLastError();
+}
+
+// Sums the pass partials in slot order: the next coefficient h_{l+1,j}, or,
+// after the last pass, h_{j+1,j} = ||w||; then rotates column j of the
+// Hessenberg matrix with the previous Givens rotations, forms rotation j,
+// updates g and publishes |g_{j+1}| (the minimised residual) and the FFOM
+// residual |g_{j+1}| / |c_j| (eq. (2.1) via the standard FOM/GMRES relation).
+__global__ __launch_bounds__(kVecThreads) void k_mgs_finish(const double* vpart, int32_t G,
+                                                            double* hout, DevCtl* ctl, int last,
+                                                            double* H, double* HR, double* cs,
+                                                            double* sn, double* g, int32_t j,
+                                                            int32_t ldh, HostStatus* hs) {
+  __shared__ double scratch[kVecThreads / kWave];
+  const double tsum = block_sum_strided(vpart, G, 1, scratch);
+  if (threadIdx.x != 0) return;
   if (!last) {
     *hout = tsum;
     return;
@@ -136,7 +174,6 @@ __global__ __launch_bounds__(kVecThreads) void k_mgs(
   const double hn = sqrt(tsum);
   *hout = hn;
   ctl->hnext = hn;
-  // Givens update of column j
   double* col = H + (int64_t)j * ldh;
   double* rc = HR + (int64_t)j * ldh;
   for (int i = 0; i <= j + 1; ++i) rc[i] = col[i];
@@ -180,26 +217,29 @@ __global__ __launch_bounds__(kVecThreads) void k_mgs(
   __threadfence_system();
 }
 
-hipError_t launch_mgs(int grid, int64_t n, double* W, const double* Vcur, const double* Vnext,
-                      const double* hcur, double* hout, double* part, DevCtl* ctl, int last,
-                      double* H, double* HR, double* cs, double* sn, double* g, int32_t j,
-                      int32_t ldh, HostStatus* hs, hipStream_t st) {
-  hipLaunchKernelGGL(k_mgs, dim3(grid), dim3(kVecThreads), 0, st, n, W, Vcur, Vnext, hcur, hout,
-                     part, ctl, last, H, HR, cs, sn, g, j, ldh, hs);
+hipError_t launch_mgs_finish(const double* vpart, int32_t G, double* hout, DevCtl* ctl, int last,
+                             double* H, double* HR, double* cs, double* sn, double* g, int32_t j,
+                             int32_t ldh, HostStatus* hs, hipStream_t st) {
+  hipLaunchKernelGGL(k_mgs_finish, dim3(1), dim3(kVecThreads), 0, st, vpart, G, hout, ctl, last,
+                     H, HR, cs, sn, g, j, ldh, hs);
   return hipGetLastError();
 }
 
 // ------------------------------------------ v_{j+1} = w / h fused with S v
+// hptr == NULL: plain sketch of W (no normalisation, no copies).
 template <typename VT, int ZB>
 __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double* __restrict__ W,
                                                         const double* hptr,
                                                         double* __restrict__ Vout,
-                                                        VT* __restrict__ Bout, int32_t s,
-                                                        int32_t zeta, uint32_t k0, uint32_t k1,
-                                                        double* part, int32_t E) {
-  extern __shared__ double lds_sk[];
+                                                        VT* __restrict__ Bout,
+                                                        const uint2* __restrict__ skp,
+                                                        int32_t s, double* __restrict__ part,
+                                                        int32_t E) {
+  extern __shared__ double lds_sk[];  // per-wave copies of the s accumulators
+  constexpr int kWaves = kVecThreads / kWave;
   const int tid = threadIdx.x;
-  for (int q = tid; q < s; q += kVecThreads) lds_sk[q] = 0.0;
+  double* const wave_sk = lds_sk + (tid / kWave) * s;
+  for (int q = tid; q < kWaves * s; q += kVecThreads) lds_sk[q] = 0.0;
   __syncthreads();
   const double h = hptr ? *hptr : 1.0;
   const int G = gridDim.x;
@@ -214,78 +254,93 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
       v = W[r];
     if (Vout) Vout[r] = v;
     if (Bout) Bout[r] = static_cast<VT>(v);
-    sketch_scatter<ZB>(lds_sk, (uint32_t)r, v, s, zeta, k0, k1);
+    sketch_scatter_packed<ZB>(wave_sk, skp, r, v);
   }
   __syncthreads();
   double* prow = part + (int64_t)blockIdx.x * E;
-  for (int q = tid; q < s; q += kVecThreads) prow[q] = lds_sk[q];
+  for (int q = tid; q < s; q += kVecThreads) {
+    double acc = lds_sk[q];
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w) acc += lds_sk[w * s + q];
+    prow[q] = acc;
+  }
 }
 
 template <typename VT>
 static void launch_normsk_t(int zb, int grid, size_t lds, hipStream_t st, int64_t n,
                             const double* W, const double* hptr, double* Vout, VT* Bout,
-                            int32_t s, int32_t zeta, uint32_t k0, uint32_t k1, double* part,
-                            int32_t E) {
+                            const uint2* skp, int32_t s, double* part, int32_t E) {
   switch (zb) {
     case 1:
       hipLaunchKernelGGL((k_normsk<VT, 1>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, s, zeta, k0, k1, part, E);
+                         Vout, Bout, skp, s, part, E);
       break;
     case 2:
       hipLaunchKernelGGL((k_normsk<VT, 2>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, s, zeta, k0, k1, part, E);
+                         Vout, Bout, skp, s, part, E);
       break;
     case 3:
       hipLaunchKernelGGL((k_normsk<VT, 3>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, s, zeta, k0, k1, part, E);
+                         Vout, Bout, skp, s, part, E);
       break;
     default:
       hipLaunchKernelGGL((k_normsk<VT, 4>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, s, zeta, k0, k1, part, E);
+                         Vout, Bout, skp, s, part, E);
       break;
   }
 }
 
 hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double* W,
                                    const double* hptr, double* Vout, void* Bout, int32_t s,
-                                   int32_t zeta, uint32_t k0, uint32_t k1, double* part,
-                                   int32_t E, hipStream_t st) {
-  const int zb = zeta_blocks(zeta);
-  const size_t lds = (size_t)s * sizeof(double);
+                                   const uint2* skp, int zb, double* part, int32_t E,
+                                   hipStream_t st) {
+  const size_t lds = (size_t)(kVecThreads / kWave) * s * sizeof(double);
   if (fp32)
-    launch_normsk_t<float>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<float*>(Bout), s,
-                           zeta, k0, k1, part, E);
+    launch_normsk_t<float>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<float*>(Bout), skp,
+                           s, part, E);
   else
-    launch_normsk_t<double>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<double*>(Bout), s,
-                            zeta, k0, k1, part, E);
+    launch_normsk_t<double>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<double*>(Bout), skp,
+                            s, part, E);
   return hipGetLastError();
 }
 
 // ----------------------------------------------- small triangular solves
 // y = R^{-1} d[0:k] for the inner dimension k chosen on the device, then
 // y_l * sigma_l so that z_j = sum_l y_l u_l over the unnormalised vectors.
-__global__ __launch_bounds__(kWave) void k_finalize(const DevCtl* ctl, const double* R,
-                                                    const double* d, const double* sigma,
-                                                    int32_t m, double* y) {
+// Columns of R are staged into LDS kFinChunk at a time, so their loads
+// overlap; the substitution itself is one column per barrier.
+constexpr int kFinThreads = 256;
+constexpr int kFinChunk = 8;
+
+__global__ __launch_bounds__(kFinThreads) void k_finalize(const DevCtl* ctl, const double* R,
+                                                          const double* d, const double* sigma,
+                                                          int32_t m, double* y) {
   __shared__ double rhs[kMaxM];
   __shared__ double ys[kMaxM];
-  const int tid = threadIdx.x;
+  __shared__ double col[kFinChunk][kMaxM];
   const int k = ctl->stop_k;
   if (k <= 0 || k > m) return;
-  for (int p = tid; p < k; p += kWave) rhs[p] = d[p];
-  __syncthreads();
-  for (int l = k - 1; l >= 0; --l) {
-    const double yl = rhs[l] / R[(int64_t)l * m + l];
-    if (tid == 0) ys[l] = yl;
-    for (int p = tid; p < l; p += kWave) rhs[p] -= R[(int64_t)l * m + p] * yl;
+  const int tid = threadIdx.x;
+  for (int p = tid; p < k; p += kFinThreads) rhs[p] = d[p];
+  for (int hi = k - 1; hi >= 0; hi -= kFinChunk) {
+    const int lo = hi - kFinChunk + 1 > 0 ? hi - kFinChunk + 1 : 0;
     __syncthreads();
+    for (int c = lo; c <= hi; ++c)
+      for (int p = tid; p <= hi; p += kFinThreads) col[c - lo][p] = R[(int64_t)c * m + p];
+    __syncthreads();
+    for (int l = hi; l >= lo; --l) {
+      const double yl = rhs[l] / col[l - lo][l];
+      if (tid == 0) ys[l] = yl;
+      for (int p = tid; p < l; p += kFinThreads) rhs[p] -= col[l - lo][p] * yl;
+      __syncthreads();
+    }
   }
-  for (int p = tid; p < k; p += kWave) y[p] = ys[p] * sigma[p];
+  for (int p = tid; p < k; p += kFinThreads) y[p] = ys[p] * sigma[p];
 }
 
 hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
                            const double* sigma, int32_t m, double* y, hipStream_t st) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kWave), 0, st, ctl, R, d, sigma, m, y);
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kFinThreads), 0, st, ctl, R, d, sigma, m, y);
   return hipGetLastError();
 }
 
@@ -336,23 +391,17 @@ __global__ __launch_bounds__(kVecThreads) void k_combine(int64_t n, const VT* __
   }
 }
 
-static int vec_grid(int64_t n) {
-  int64_t g = (n + kVecThreads * 4 - 1) / (kVecThreads * 4);
-  if (g > 2048) g = 2048;
-  if (g < 1) g = 1;
-  return (int)g;
-}
-
 hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, const double* y,
                           const int32_t* kdev, int32_t khost, const double* add, double* out,
                           hipStream_t st) {
   const int kmax = kdev ? kMaxM : khost;
   const size_t lds = (size_t)(kmax > 0 ? kmax : 1) * sizeof(double);
+  const int grid = vec_grid(n * kUnroll);
   if (fp32)
-    hipLaunchKernelGGL(k_combine<float>, dim3(vec_grid(n)), dim3(kVecThreads), lds, st, n,
+    hipLaunchKernelGGL(k_combine<float>, dim3(grid), dim3(kVecThreads), lds, st, n,
                        static_cast<const float*>(B), ldb, y, kdev, khost, add, out);
   else
-    hipLaunchKernelGGL(k_combine<double>, dim3(vec_grid(n)), dim3(kVecThreads), lds, st, n,
+    hipLaunchKernelGGL(k_combine<double>, dim3(grid), dim3(kVecThreads), lds, st, n,
                        static_cast<const double*>(B), ldb, y, kdev, khost, add, out);
   return hipGetLastError();
 }
@@ -583,33 +632,6 @@ hipError_t launch_transpose(const int32_t* row_ptr, const int32_t* col_idx, cons
                      col_idx, n, rp_t, cursor, col_t, perm);
   hipLaunchKernelGGL(k_sort_rows, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, rp_t, n, col_t,
                      perm, val, val_t);
-  return hipGetLastError();
-}
-
-// ---------------------------------------------------------- sketch export
-__global__ void k_sketch_materialize(int64_t n, int32_t s, int32_t zeta, uint32_t k0,
-                                     uint32_t k1, int32_t* __restrict__ rows,
-                                     int8_t* __restrict__ signs) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
-    int rw[kMaxZeta];
-    uint32_t neg;
-    sketch_column<kMaxZeta / 4>((uint32_t)r, s, zeta, k0, k1, rw, neg);
-#pragma unroll
-    for (int d = 0; d < kMaxZeta; ++d) {
-      if (d < zeta) {
-        rows[r * zeta + d] = rw[d];
-        signs[r * zeta + d] = ((neg >> d) & 1u) ? (int8_t)-1 : (int8_t)1;
-      }
-    }
-  }
-}
-
-hipError_t launch_sketch_materialize(int64_t n, int32_t s, int32_t zeta, uint32_t k0,
-                                     uint32_t k1, int32_t* rows, int8_t* signs,
-                                     hipStream_t st) {
-  hipLaunchKernelGGL(k_sketch_materialize, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, n, s,
-                     zeta, k0, k1, rows, signs);
   return hipGetLastError();
 }
 

@@ -45,29 +45,29 @@ def test_default_options(lib):
 
 def test_workspace_bytes(lib):
     out = C.c_size_t()
-    assert lib.sfgmres_workspace_bytes(4096, 20224, 30, 2, 60, None, 0, C.byref(out)) == 0
+    assert lib.sfgmres_workspace_bytes(4096, 20224, 30, 2, 60, 8, None, 0, C.byref(out)) == 0
     small = out.value
     assert small > 8 * 4096 * (30 + 1 + 2 * 100 + 1)
     o = L.Options()
     lib.sfgmres_default_options(C.byref(o))
     o.precision = L.MIXED
-    assert lib.sfgmres_workspace_bytes(4096, 20224, 30, 2, 60, C.byref(o), 0, C.byref(out)) == 0
+    assert lib.sfgmres_workspace_bytes(4096, 20224, 30, 2, 60, 8, C.byref(o), 0, C.byref(out)) == 0
     mixed = out.value
     assert mixed < small + 4 * 20224 + 4 * 4096 + 4096
-    assert lib.sfgmres_workspace_bytes(4096, 20224, 30, 2, 60, None, 1, C.byref(out)) == 0
+    assert lib.sfgmres_workspace_bytes(4096, 20224, 30, 2, 60, 8, None, 1, C.byref(out)) == 0
     assert out.value > small + 16 * 20224
     # invalid sizes
-    assert lib.sfgmres_workspace_bytes(4096, 20224, 60, 2, 60, None, 0, C.byref(out)) == L.ERR_INVALID
-    assert lib.sfgmres_workspace_bytes(0, 0, 30, 2, 60, None, 0, C.byref(out)) == L.ERR_INVALID
-    assert lib.sfgmres_workspace_bytes(10, 10, 30, 2, 60, None, 0, None) == L.ERR_INVALID
+    assert lib.sfgmres_workspace_bytes(4096, 20224, 60, 2, 60, 8, None, 0, C.byref(out)) == L.ERR_INVALID
+    assert lib.sfgmres_workspace_bytes(0, 0, 30, 2, 60, 8, None, 0, C.byref(out)) == L.ERR_INVALID
+    assert lib.sfgmres_workspace_bytes(10, 10, 30, 2, 60, 8, None, 0, None) == L.ERR_INVALID
 
 
 def test_small_workspace_queries(lib):
     out = C.c_size_t()
-    assert lib.sfgmres_sketch_workspace_bytes(400, C.byref(out)) == 0 and out.value > 400 * 8
-    assert lib.sfgmres_sketch_workspace_bytes(5000, C.byref(out)) == L.ERR_INVALID
+    assert lib.sfgmres_sketch_workspace_bytes(10**6, 400, 8, C.byref(out)) == 0 and out.value > 16 * 10**6
+    assert lib.sfgmres_sketch_workspace_bytes(10**6, 5000, 8, C.byref(out)) == L.ERR_INVALID
     assert lib.sfgmres_transpose_workspace_bytes(100, 500, C.byref(out)) == 0
-    assert lib.sfgmres_spmv_workspace_bytes(100, 500, 60, C.byref(out)) == 0
+    assert lib.sfgmres_spmv_workspace_bytes(100, 500, 60, 8, C.byref(out)) == 0
 
 
 def test_null_handle_is_rejected(lib):
