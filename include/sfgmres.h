@@ -84,11 +84,17 @@ typedef struct sfgmres_options {
   double  cond_threshold;       /* C2 threshold on the condition estimate, default 1e15 (Sec. 3) */
   int32_t record_true_residual; /* 1: also compute ||b - A x_j|| after every outer step (+1 SpMV
                                    and one n x j combination per step), default 0                */
-  int32_t profile;              /* 1: time every inner SpMV+sketch launch with HIP events,
-                                   default 0                                                     */
-  int32_t lookahead;            /* inner steps enqueued ahead of the last one the device has
-                                   finished deciding; 0 = default (4)                            */
-  int32_t reserved[4];
+  int32_t profile;              /* N > 0: time the inner SpMV+sketch launch of every N-th
+                                   inner step (steps N-1, 2N-1, ...) with HIP events recorded
+                                   at the kernel's own start and end; default 0 (off)            */
+  int32_t lookahead;            /* inner steps the host enqueues ahead of the last column the
+                                   device has decided, 0..64; raised to at least `panel`;
+                                   0 = default (2 panel)                                         */
+  int32_t panel;                /* columns appended to the sketched QR per decision launch,
+                                   0..8; 0 = default (8).  The stopping rule is applied after
+                                   every column whatever the panel; up to panel - 1 inner steps
+                                   past the stop are computed and discarded                      */
+  int32_t reserved[3];
 } sfgmres_options;
 
 /* Solve diagnostics.  Scalars are always written; each per-step array is a
@@ -110,8 +116,8 @@ typedef struct sfgmres_info {
   double* ffom_residual;            /* [max_outer]: FFOM residual norm, eq. (2.1), absolute */
   const int32_t* forced_k;          /* input [max_outer] or NULL: replay these inner
                                        dimensions (k_j steps, no C1-C3 tests)         */
-  double  spmv_ms;                  /* profile: summed duration of the inner SpMV+sketch
-                                       launches that did work                          */
+  double  spmv_ms;                  /* profile: summed duration of the timed inner
+                                       SpMV+sketch launches that did work              */
   int64_t spmv_launches;            /* profile: number of those launches              */
   double  solve_ms;                 /* host wall time of the call                      */
   double  reserved[6];

@@ -50,7 +50,8 @@ class Options(C.Structure):
         ("record_true_residual", C.c_int32),
         ("profile", C.c_int32),
         ("lookahead", C.c_int32),
-        ("reserved", C.c_int32 * 4),
+        ("panel", C.c_int32),
+        ("reserved", C.c_int32 * 3),
     ]
 
 

@@ -31,7 +31,10 @@ class SolveParams:
     m: inner sGMRES basis cap k_max (rule C1); t: Arnoldi truncation window;
     s: sketch rows; zeta: nonzeros per sketch column; tol: relative
     tolerance on ||b - A x|| / ||b||; seed: sketch seed; cond_threshold: C2
-    threshold; precision: "fp64" or "mixed".
+    threshold; precision: "fp64" or "mixed"; lookahead: inner steps the host
+    runs ahead of the device's last decision (0: default); panel: columns
+    per decision launch (0: default 8; the stopping rule still acts after
+    every column).
     """
     m: int = 30
     t: int = 2
@@ -43,6 +46,7 @@ class SolveParams:
     cond_threshold: float = 1e15
     precision: str = "fp64"
     lookahead: int = 0
+    panel: int = 0
 
 
 _HANDLES = {}
@@ -94,8 +98,9 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.max_outer = p.max_outer
     o.cond_threshold = p.cond_threshold
     o.record_true_residual = 1 if record_true_residual else 0
-    o.profile = 1 if profile else 0
+    o.profile = int(profile)  # False/True -> 0/1; N -> every N-th inner step
     o.lookahead = p.lookahead
+    o.panel = p.panel
     return o
 
 

@@ -39,12 +39,16 @@ constexpr int kMaxGrid = 1024;
 // workgroup in the vector partial buffer).
 constexpr int kVecThreads = 256;
 constexpr int kVecGrid = 1024;
-// Partial-sum row layout written by every persistent SpMV kernel:
-//   [0, s)              sketch accumulators (sum of +-w_r, unscaled)
-//   [s, s + kMaxT)      dot products
-//   s + kMaxT           squared norm
-//   s + kMaxT + 1       second squared norm / extra scalar
-constexpr int kPartExtra = kMaxT + 2;
+// Partial sums written by every multi-workgroup kernel, one row per
+// workgroup (slot = blockIdx.x):
+//   sketch rows: s accumulators (sum of +-w_r, unscaled), row stride s;
+//   scalar rows: kDP doubles, row stride kDP:
+//     [0, kMaxT)   dot products
+//     kMaxT        squared norm
+//     kMaxT + 1    second squared norm / extra scalar
+constexpr int kDP = kMaxT + 2;
+// Columns appended to the sketched QR by one decision launch (at most).
+constexpr int kPanel = 8;
 
 // Packed sketch: every column r of S is stored as 4*ZB 16-bit fields
 // (ZB = ceil(zeta/4), a multiple of 8 bytes per column): bits 0..14 hold
@@ -63,7 +67,7 @@ struct DevCtl {
   int32_t forced_k;      // >0: replay this dimension
   int32_t m, t, s;
   int32_t error;         // 0, or a negative SFGMRES_ERR_* raised on the device
-  int32_t pad0;
+  int32_t brk_step;      // inner step whose Arnoldi vector is zero (-1: none)
   double tol_abs;        // tol * ||b||
   double cond_threshold;
   double factor;         // C3 factor: FFOM residual of the previous outer step (beta at j = 1)
@@ -90,13 +94,13 @@ struct HostStatus {
   int32_t outer_j;           // outer step recorded below (1-based)
   int32_t k;
   int32_t error;
-  int32_t pad;
+  int32_t steps_run;         // inner steps fully executed by the cycle that stopped
   double rho, ffom, hnext, cond, rho_hat, rhat_true, beta, nb;
 };
 
 // Offsets (bytes) of every workspace region.
 struct Layout {
-  size_t ctl, tiles, tp, ipart, part, vpart, red, skp, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z,
+  size_t ctl, tiles, tp, ipart, part, dpart, vpart, red, skp, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z,
       sigma, hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, at_rowptr, at_col,
       at_val, at_perm, at_cursor, scan_tmp, total;
   int64_t ld;        // leading dimension (elements) of the n-vectors
@@ -104,8 +108,6 @@ struct Layout {
   int32_t grid;      // persistent grid size used for the partial buffer
 };
 
-Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
-                   int32_t max_outer, int32_t precision, int32_t adjoint);
 
 // Bytes of the packed sketch of an n-column S with zeta nonzeros per column.
 inline size_t packed_sketch_bytes(int64_t n, int32_t zeta) {
@@ -199,10 +201,35 @@ __device__ __forceinline__ void sketch_scatter_packed(double* lds_sk, const uint
 }
 
 // ------------------------------------------------------------- reductions
+// A lane-to-lane move of a double with a DPP pattern (the two 32-bit halves
+// moved separately).
+template <int kCtrl>
+__device__ __forceinline__ double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xFFFFFFFFll), kCtrl, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), kCtrl, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double read_lane(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xFFFFFFFFll), lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wave; every lane gets the same value.  Within
+// each row of 16 lanes: exchange with lane^1 and lane^2 (quad permutes), then
+// add the values 4 and 8 lanes along (row rotations), which leaves the row
+// sum in lane 0 of the row; the four row sums are then read as scalars and
+// added in row order.  No LDS traffic; the order is fixed, so the result is
+// reproducible bit for bit.  Must be called with all 64 lanes active.
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int off = kWave / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, kWave);
-  return v;
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x128>(v);  // row_ror:8
+  return (read_lane(v, 0) + read_lane(v, 16)) + (read_lane(v, 32) + read_lane(v, 48));
 }
 
 // Sum of v over the workgroup (fixed order: waves combined in wave order).
@@ -219,6 +246,29 @@ __device__ __forceinline__ double block_sum(double v, double* scratch) {
   for (int i = 0; i < nw; ++i) r += scratch[i];
   __syncthreads();
   return r;
+}
+
+// Sums of NV values over the workgroup at once (fixed order, as block_sum);
+// every thread gets the NV sums.  `buf` holds (blockDim.x/64) * NV doubles.
+template <int NV>
+__device__ __forceinline__ void block_sum_vec(double (&v)[NV], double* buf) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  const int nw = (blockDim.x + kWave - 1) / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double r = 0.0;
+    for (int w = 0; w < nw; ++w) r += buf[w * NV + i];
+    v[i] = r;
+  }
+  __syncthreads();
 }
 
 // Sum of src[0], src[stride], ..., src[(count-1) stride] by one workgroup

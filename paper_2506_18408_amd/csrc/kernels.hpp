@@ -36,8 +36,8 @@ struct SpmvArgs {
   const void* U;            // window base (same type as val), column-major
   int64_t ldu;
   int32_t l0, nwin;         // window columns [l0, l0 + nwin)
-  double* part;             // gridDim.x rows of E doubles
-  int32_t E;
+  double* part;             // sketch rows: gridDim.x rows of s doubles
+  double* dpart;            // scalar rows: gridDim.x rows of kDP doubles
   const DevCtl* ctl;
 };
 
@@ -50,11 +50,14 @@ hipError_t launch_tiles(const int32_t* row_ptr, int64_t n, int32_t wt, int32_t r
                         int32_t* tiles, int32_t* tp, int32_t ntiles, hipStream_t st);
 hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, int32_t* out,
                              hipStream_t st);
-hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st);
+// ev0/ev1 non-null: the launch records them at the kernel's own start and
+// end (timing of the kernel alone).
+hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
-// One-workgroup finisher of the scalar SpMV variants: sums the partial rows
-// (columns kMaxT, kMaxT+1) in slot order and records the mode's scalars.
-hipError_t launch_spmv_finish(int mode, const double* part, int32_t G, int32_t E, DevCtl* ctl,
+// One-workgroup finisher of the scalar SpMV variants: sums the scalar rows
+// (entries kMaxT, kMaxT+1) in slot order and records the mode's scalars.
+hipError_t launch_spmv_finish(int mode, const double* dpart, int32_t G, DevCtl* ctl,
                               double* out0, HostStatus* hs, hipStream_t st);
 
 // Sketch generation (Philox4x32-10 + Floyd) into the packed format, and its
@@ -64,43 +67,64 @@ hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, u
 hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const uint2* skp, int32_t* rows,
                                 int8_t* signs, hipStream_t st);
 
-// Multi-workgroup reduction of G partial rows of E entries into red[E]
-// (slot order), predicated on the stop flag when `predicated`.
-hipError_t launch_reduce_rows(const double* part, int32_t G, int32_t E, double* red,
-                              const DevCtl* ctl, bool predicated, hipStream_t st);
+// Multi-workgroup reduction of sketch rows: for the ring slots
+// (first + y) mod nring, y < nslots, red[slot][e] = sum over the G rows
+// (stride `stride`) of part[slot][row][e], e < count, in slot order.
+// Predicated on the stop flag when `predicated`.
+hipError_t launch_reduce_slots(const double* part, int32_t G, int32_t stride, int32_t count,
+                               int32_t first, int32_t nslots, int32_t nring, int64_t slot_part,
+                               int64_t slot_red, double* red, const DevCtl* ctl, bool predicated,
+                               hipStream_t st);
 
-// Decision kernel (one workgroup) of the sketched QR.
-enum RqMode : int {
-  kRqStep = 0,    // append column i: Householder update, ICE, C1-C3, Arnoldi coefficients
-  kRqInit = 1,    // d0 = S v_j; reset the inner-cycle state
-  kRqReduce = 2,  // copy red into out_c (times 1/sqrt(zeta)) / out_dots / out_norm2 (test export)
+// Truncated-Arnoldi coefficients of inner step `step` (one workgroup): for
+// t > 0 sigma_step = 1/||u_step|| (from the Arnoldi norm partials) and
+// coef[l] = sigma_step sigma_l^2 <y, u_l>, coef[kMaxT] = sigma_step; for
+// t = 0 sigma_{step+1} = 1/||y||.  A zero vector records its step in
+// ctl->brk_step (first one only) and zero coefficients.
+struct CoefArgs {
+  const double* dpart;      // scalar rows of the fused SpMV (G rows of kDP)
+  int32_t G;
+  const double* vpart;      // t > 0, step > 0: norm partials of u_step
+  int32_t Gv;
+  int32_t t, nwin, l0, step;
+  DevCtl* ctl;
+  double* sigma;
+  double* coef;             // kMaxT + 1: window coefficients, then the scale of y
 };
+hipError_t launch_coef(const CoefArgs& a, hipStream_t st);
 
-struct RqArgs {
-  const double* red;        // reduced partial row (E entries)
-  const double* vpart;      // kRqStep, t > 0, step > 0: Arnoldi norm partials of u_i
-  int32_t Gv;               // number of those partials
-  int32_t s, m, t, nwin, l0;
-  int32_t step;             // kRqStep: 0-based inner step i
-  int32_t forced_k;         // kRqInit: replay dimension for the coming cycle (0 = off)
+// Decision kernel (one workgroup): appends columns k0 .. k0+ncols-1 to the
+// sketched QR and decides after each of them.
+struct QrBlockArgs {
+  const double* red;        // reduced sketch rows, ring of nring slots (slot = column mod nring)
+  int64_t slot_red;
+  int32_t nring;
+  int32_t s, m, t;
+  int32_t k0, ncols;        // first column, columns in this launch (1..kPanel)
   double inv_sqrt_zeta;
   DevCtl* ctl;
   HostStatus* hs;
-  double* V;                // s x m Householder vectors (column-major)
-  double* T;                // m x m compact-WY factor (row-major)
+  double* V;                // s x m Householder vectors (column-major, zeros above the unit)
+  double* T;                // m x m compact-WY factor (column-major, upper triangle)
   double* R;                // m x m triangular factor (column-major)
   double* d;                // s: Q^T S v_j
   double* tau;
   double* ice_x;
   double* ice_z;
-  double* sigma;            // basis scales sigma_l = 1 / ||u_l||
-  double* coef;             // kMaxT + 1: window coefficients, then the scale of y
-  double* out_c;            // kRqReduce
-  double* out_dots;
-  double* out_norm2;
+  const double* sigma;      // basis scales sigma_l = 1 / ||u_l||
 };
+size_t qr_block_lds_bytes(int32_t s, int32_t m);
+hipError_t launch_qr_block(const QrBlockArgs& a, hipStream_t st);
 
-hipError_t launch_rq(int mode, const RqArgs& a, hipStream_t st);
+// d = red[0:s] / sqrt(zeta) (= S v_j) and a reset of the inner-cycle state.
+hipError_t launch_rq_init(const double* red, int32_t s, double inv_sqrt_zeta, int32_t forced_k,
+                          DevCtl* ctl, double* d, double* sigma, hipStream_t st);
+
+// Test export of one fused SpMV: out_c = red / sqrt(zeta), the window dots
+// and the squared norm summed from the scalar rows (dpart may be NULL).
+hipError_t launch_sketch_out(const double* red, int32_t s, double inv_sqrt_zeta,
+                             const double* dpart, int32_t G, int32_t nwin, double* out_c,
+                             double* out_dots, double* out_norm2, hipStream_t st);
 
 // Vector kernels (vec.hip).
 hipError_t launch_init_ctl(DevCtl* ctl, int32_t m, int32_t t, int32_t s, double cond_threshold,
@@ -117,8 +141,7 @@ hipError_t launch_mgs_finish(const double* vpart, int32_t G, double* hout, DevCt
                              int32_t ldh, HostStatus* hs, hipStream_t st);
 hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double* W,
                                    const double* hptr, double* Vout, void* Bout, int32_t s,
-                                   const uint2* skp, int zb, double* part, int32_t E,
-                                   hipStream_t st);
+                                   const uint2* skp, int zb, double* part, hipStream_t st);
 hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
                            const double* sigma, int32_t m, double* y, hipStream_t st);
 hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, const double* y,

@@ -1,65 +1,163 @@
-// Reduce and decide: the sketched least-squares step of one inner sGMRES
-// step (Section 3).
+// Coefficients, reductions and decisions of the inner sGMRES cycle
+// (Section 3, with the truncated Arnoldi basis of Section 4.1).
 //
-// k_reduce_rows (many workgroups) combines the per-workgroup partial rows of
-// the fused SpMV (raw sketch S y, truncated-Arnoldi dots, ||y||^2), each
-// workgroup summing a 16-entry slice over all rows in slot order.
+// k_coef (one workgroup, on the critical path of every inner step) sums the
+// window dots and ||y||^2 of the fused SpMV's scalar rows, forms
+// sigma_i = 1/||u_i|| of the current (unnormalised) Arnoldi vector from the
+// norm partials of the previous Arnoldi update, and stores the coefficients
+// of the next vector: u_{i+1} = sigma_i y - sum_l sigma_i sigma_l^2 <y, u_l> u_l,
+// i.e. A b_i minus its projections h_l b_l on the window b_l = sigma_l u_l
+// with h_l = sigma_i sigma_l <y, u_l>; for t = 0 it stores
+// sigma_{i+1} = 1/||y|| of the next power-basis vector y = A b_i.
 //
-// k_rq (one workgroup) then, in float64:
-//   * forms sigma_i = 1/||u_i|| of the current (unnormalised) Arnoldi vector
-//     from the norm partials of the previous Arnoldi update, and the new
-//     column c_i = S A b_i / sqrt(zeta) of S A B_i (b_i = sigma_i u_i; for
-//     t > 0 the SpMV returned y = A u_i, for t = 0 already y = A b_i);
-//   * appends c_i to the Householder QR of S A B_i (compact-WY form
-//     Q = I - V T V^T: c <- c - V T^T V^T c, a new reflector for c[i:],
-//     T extended by -tau T V^T v), carries d = Q^T S v_j along, and reads the
-//     sketched least-squares residual ||d[i+1:]|| (the estimate used by C3);
-//   * extends the incremental condition estimate of R (Bischof's ICE: top
-//     eigenpairs of two 2x2 matrices);
-//   * applies C2 (estimate above threshold: drop column i), C3 (bound of
-//     eq. (2.2) below tol), C1 (i = m), or a forced replay dimension;
-//   * stores the truncated-Arnoldi coefficients sigma_i sigma_l^2 <y, u_l>
-//     and the scale sigma_i of y for the vector update, or, for t = 0, the
-//     scale of the next power-basis vector.
-// The mode kRqInit instead takes d0 = S v_j and resets the cycle state.
+// The sketched least-squares problem only decides when the cycle stops and
+// gives the final coefficients y_k: the Krylov basis never waits for it.  So
+// p consecutive inner steps run first, each leaving the raw sketch S y_i as
+// per-workgroup partial rows in its ring slot, and then
+//
+// k_reduce_slots (many workgroups) sums the partial rows of the p slots in
+// slot order, and
+//
+// k_qr_block (one workgroup, 1024 threads) appends the p columns
+// c_i = S A b_i / sqrt(zeta) (b_i = sigma_i u_i; for t = 0 the SpMV already
+// returned A b_i) to the Householder QR of S A B, in float64:
+//   * blocked update with the existing reflectors in compact-WY form
+//     (Q = I - V T V^T, T upper triangular): A = V^T C, B = T^T A,
+//     C <- C - V B, one pass over V (twice) and T for all p columns;
+//   * the p new reflectors column by column (right-looking inside the
+//     panel), with d = Q^T S v_j carried along, the sketched least-squares
+//     residual ||d[i+1:]|| (the estimate C3 uses) and Bischof's incremental
+//     condition estimate of R (the estimate C2 uses) after every column;
+//   * the decision after every column, in this order: a zero Arnoldi vector
+//     (truncated-Arnoldi breakdown), a forced replay dimension, C2 (estimate
+//     above threshold: drop the column), C3 (bound of eq. (2.2) below tol),
+//     C1 (i = m).  Column i's decision uses the quantities a one-column
+//     update gives (R_i is the leading block of R_k), so the blocking
+//     changes rounding only; steps run past the stop are discarded;
+//   * if the cycle goes on, T extended by the p new reflectors.
+// It is the only writer of the stop flag.  k_rq_init takes d0 = S v_j and
+// resets the cycle state; k_sketch_out is the test export of one fused SpMV.
 #include "kernels.hpp"
 
 namespace sfg {
 
-constexpr int kRqThreads = 1024;
-constexpr int kRedThreads = 1024;
-constexpr int kRedSlice = 16;  // entries per reduction workgroup
+// ------------------------------------------------------------ coefficients
+constexpr int kCoefThreads = 256;
 
-__global__ __launch_bounds__(kRedThreads) void k_reduce_rows(const double* __restrict__ part,
-                                                             int32_t G, int32_t E,
-                                                             double* __restrict__ red,
-                                                             const DevCtl* ctl, int predicated) {
+__global__ __launch_bounds__(kCoefThreads) void k_coef(CoefArgs a) {
+  constexpr int kNV = kMaxT + 2;  // window dots, ||y||^2, ||u_step||^2
+  __shared__ double buf[(kCoefThreads / kWave) * kNV];
+  DevCtl* ctl = a.ctl;
+  const int tid = threadIdx.x;
+  const int step = a.step;
+  // every load first (one round trip): the scalar rows of the SpMV, the
+  // norm partials of the Arnoldi update, the window's sigmas, the stop flag
+  double v[kNV];
+#pragma unroll
+  for (int l = 0; l < kNV; ++l) v[l] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxGrid / kCoefThreads; ++u) {
+    const int g = tid + u * kCoefThreads;
+    if (g < a.G) {
+      const double* row = a.dpart + (int64_t)g * kDP;
+#pragma unroll
+      for (int l = 0; l < kMaxT; ++l)
+        if (l < a.nwin) v[l] += row[l];
+      v[kMaxT] += row[kMaxT];
+    }
+  }
+  const bool use_u = a.t > 0 && step > 0;
+#pragma unroll
+  for (int u = 0; u < kVecGrid / kCoefThreads; ++u) {
+    const int g = tid + u * kCoefThreads;
+    if (use_u && g < a.Gv) v[kMaxT + 1] += a.vpart[g];
+  }
+  double sgw[kMaxT];
+#pragma unroll
+  for (int l = 0; l < kMaxT; ++l)
+    sgw[l] = (tid == 0 && l < a.nwin && a.l0 + l < step) ? a.sigma[a.l0 + l] : 0.0;
+  const int stopped = ctl->stop_k;
+  block_sum_vec<kNV>(v, buf);
+  if (stopped != 0 || tid != 0) return;
+  if (a.t > 0) {
+    double sig = 1.0;
+    bool brk = false;
+    if (step > 0) {
+      brk = v[kMaxT + 1] == 0.0;
+      sig = brk ? 0.0 : 1.0 / sqrt(v[kMaxT + 1]);
+    }
+    a.sigma[step] = sig;
+    if (brk && ctl->brk_step < 0) ctl->brk_step = step;  // u_step = 0
+    for (int l = 0; l < a.nwin; ++l) {
+      const double sg = (a.l0 + l == step) ? sig : sgw[l];
+      a.coef[l] = sig * sg * sg * v[l];
+    }
+    a.coef[kMaxT] = sig;
+  } else {
+    const double n2 = v[kMaxT];
+    if (n2 == 0.0) {
+      if (ctl->brk_step < 0) ctl->brk_step = step + 1;  // the next power-basis vector is zero
+      a.sigma[step + 1] = 0.0;
+    } else {
+      a.sigma[step + 1] = 1.0 / sqrt(n2);
+    }
+  }
+}
+
+hipError_t launch_coef(const CoefArgs& a, hipStream_t st) {
+  hipLaunchKernelGGL(k_coef, dim3(1), dim3(kCoefThreads), 0, st, a);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------ reductions
+constexpr int kRedThreads = 256;
+constexpr int kRedSlice = 8;  // entries per reduction workgroup
+
+__global__ __launch_bounds__(kRedThreads) void k_reduce_slots(
+    const double* __restrict__ part, int32_t G, int32_t stride, int32_t count, int32_t first,
+    int32_t nring, int64_t slot_part, int64_t slot_red, double* __restrict__ red,
+    const DevCtl* ctl, int predicated) {
   __shared__ double sl[kRedThreads];
   if (predicated && ctl->stop_k != 0) return;
+  const int slot = (first + (int)blockIdx.y) % nring;
+  const double* p = part + slot * slot_part;
   const int tid = threadIdx.x;
   const int e = blockIdx.x * kRedSlice + (tid % kRedSlice);
   const int rg = tid / kRedSlice;
   constexpr int nrg = kRedThreads / kRedSlice;
+  constexpr int kRU = 8;  // rows in flight per thread
   double acc = 0.0;
-  if (e < E)
-    for (int r = rg; r < G; r += nrg) acc += part[(int64_t)r * E + e];
+  if (e < count) {
+    int r = rg;
+    for (; r + (kRU - 1) * nrg < G; r += kRU * nrg) {
+      double v[kRU];
+#pragma unroll
+      for (int u = 0; u < kRU; ++u) v[u] = p[(int64_t)(r + u * nrg) * stride + e];
+#pragma unroll
+      for (int u = 0; u < kRU; ++u) acc += v[u];
+    }
+    for (; r < G; r += nrg) acc += p[(int64_t)r * stride + e];
+  }
   sl[tid] = acc;
   __syncthreads();
   if (tid < kRedSlice) {
     double t = 0.0;
     for (int r = 0; r < nrg; ++r) t += sl[r * kRedSlice + tid];
-    if (e < E) red[e] = t;
+    if (e < count) red[slot * slot_red + e] = t;
   }
 }
 
-hipError_t launch_reduce_rows(const double* part, int32_t G, int32_t E, double* red,
-                              const DevCtl* ctl, bool predicated, hipStream_t st) {
-  const int nb = (E + kRedSlice - 1) / kRedSlice;
-  hipLaunchKernelGGL(k_reduce_rows, dim3(nb), dim3(kRedThreads), 0, st, part, G, E, red, ctl,
-                     predicated ? 1 : 0);
+hipError_t launch_reduce_slots(const double* part, int32_t G, int32_t stride, int32_t count,
+                               int32_t first, int32_t nslots, int32_t nring, int64_t slot_part,
+                               int64_t slot_red, double* red, const DevCtl* ctl, bool predicated,
+                               hipStream_t st) {
+  const int nb = (count + kRedSlice - 1) / kRedSlice;
+  hipLaunchKernelGGL(k_reduce_slots, dim3(nb, nslots), dim3(kRedThreads), 0, st, part, G, stride,
+                     count, first, nring, slot_part, slot_red, red, ctl, predicated ? 1 : 0);
   return hipGetLastError();
 }
 
+// ------------------------------------------------------------- decisions
 // Top eigenvalue / unit eigenvector of [[a, b], [b, d]] via the symmetric
 // Schur rotation (Golub & Van Loan, Sec. 8.5.2).
 __device__ static void top_eig2(double a, double b, double d, double& lam, double& vs,
@@ -93,302 +191,552 @@ __device__ static void top_eig2(double a, double b, double d, double& lam, doubl
   }
 }
 
-__device__ static void publish_inner(HostStatus* hs, const DevCtl* c, int done) {
-  host_store_i32(&hs->stop_k, c->stop_k);
-  host_store_i32(&hs->stop_step, c->stop_step);
-  host_store_i32(&hs->stop_reason, c->stop_reason);
-  host_store_i32(&hs->error, c->error);
-  __threadfence_system();
-  host_store_i32(&hs->inner_step_done, done);
-  __threadfence_system();
+// The host status block needs no fence: the device flag is the authority,
+// and a host that reads a stale value only enqueues steps that exit at once.
+// One sketch row per thread: every row-wise quantity of the panel (its
+// kPanel columns, d, the condition-estimate vectors) lives in registers.
+constexpr int kQrThreads = 1024;
+static_assert(kQrThreads >= kMaxS && kQrThreads >= kMaxM, "one row per thread");
+constexpr int kQrWaves = kQrThreads / kWave;
+constexpr int kRB = 32;  // reduction entries per wave (>= kPanel (kPanel - 1) / 2)
+constexpr int kRHalf = kQrWaves * kRB + kRB;  // wave partials, then the totals
+
+size_t qr_block_lds_bytes(int32_t s, int32_t m) {
+  return sizeof(double) * ((size_t)kPanel * s + 2 * (size_t)m * kPanel + 2 * (size_t)kRHalf);
 }
 
-__global__ __launch_bounds__(kRqThreads) void k_rq(RqArgs a, int mode) {
-  __shared__ double scratch[kRqThreads / kWave];
-  __shared__ double cv[kMaxS];
-  __shared__ double av[kMaxM];
-  __shared__ double bv[kMaxM];
-  __shared__ double bc[8];
+// Sums of NV values over the workgroup, every thread getting the NV sums:
+// wave sums, then thread i < NV adds the wave partials of entry i in wave
+// order, then every thread reads the NV totals (two barriers, NV reads per
+// thread).  Callers alternate between two buffers: a thread writes buffer b
+// only after passing the barriers of the call that used the other buffer,
+// which every thread reaches only after reading buffer b the time before.
+template <int NV>
+__device__ __forceinline__ void qr_sum(double (&v)[NV], double* rbuf, int& par) {
+  double* buf = rbuf + par * kRHalf;
+  double* tot = buf + kQrWaves * kRB;
+  par ^= 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x < NV) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < kQrWaves; ++w) r += buf[w * NV + threadIdx.x];
+    tot[threadIdx.x] = r;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = tot[i];
+}
 
-  DevCtl* ctl = a.ctl;
-  if (mode == kRqStep && ctl->stop_k != 0) return;
-  const int tid = threadIdx.x;
-  const int lane = tid & (kWave - 1);
-  const int wid = tid / kWave;
-  constexpr int nw = kRqThreads / kWave;
+// Householder reflector for a column whose entry at the pivot row is alpha
+// and whose squared norm below it is x2: H = I - tau v v^T with v = 1 at the
+// pivot and (entry / den) below, H c = beta e_pivot.
+__device__ __forceinline__ void reflector(double alpha, double x2, double& beta, double& tau,
+                                          double& den) {
+  if (x2 == 0.0) {
+    beta = alpha;
+    tau = 0.0;
+    den = 0.0;
+  } else {
+    beta = -copysign(sqrt(alpha * alpha + x2), alpha);
+    tau = (beta - alpha) / beta;
+    den = alpha - beta;
+  }
+}
 
+// y = V^T X over rows >= q0 for the k0 reflectors V (global, column-major,
+// s rows) and the kPanel columns X (LDS, column-major), masked to rows
+// >= q0 + j in column j when `masked`: a wave per pair of reflectors, lanes
+// over rows, kVtChunks row chunks in flight.  Output y[l * kPanel + j] (LDS).
+constexpr int kVtChunks = 4;  // row chunks of 64 in flight per lane
+
+__device__ __forceinline__ void vt_panel(const double* __restrict__ V, int s, int k0, int q0,
+                                         const double* X, bool masked, double* y) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+  for (int lb = wid * 2; lb < k0; lb += kQrWaves * 2) {
+    const bool has1 = lb + 1 < k0;
+    double acc0[kPanel], acc1[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) acc0[j] = acc1[j] = 0.0;
+    for (int qb = q0; qb < s; qb += kWave * kVtChunks) {
+      double v0[kVtChunks], v1[kVtChunks];
+#pragma unroll
+      for (int u = 0; u < kVtChunks; ++u) {
+        const int q = qb + u * kWave + lane;
+        v0[u] = q < s ? V[(int64_t)lb * s + q] : 0.0;
+        v1[u] = (q < s && has1) ? V[(int64_t)(lb + 1) * s + q] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kVtChunks; ++u) {
+        const int q = qb + u * kWave + lane;
+        if (q < s) {
+#pragma unroll
+          for (int j = 0; j < kPanel; ++j) {
+            const double xq = (!masked || q >= q0 + j) ? X[j * s + q] : 0.0;
+            acc0[j] += v0[u] * xq;
+            acc1[j] += v1[u] * xq;
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) {
+      const double r0 = wave_sum(acc0[j]);
+      const double r1 = wave_sum(acc1[j]);
+      if (lane == 0) {
+        y[lb * kPanel + j] = r0;
+        if (has1) y[(lb + 1) * kPanel + j] = r1;
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
+  extern __shared__ double lds[];
+  __shared__ double Wm[kPanel][kPanel];  // Wm[x][y] = v_{k0+x}^T v_{k0+y}, x < y
+  __shared__ double tau_sh[kPanel];
   const int s = a.s;
   const int m = a.m;
-  const double* red = a.red;
+  // LDS: panel (kPanel columns of s, column-major; thread q only ever
+  // touches row q of it outside the V^T products), AU and BX (m x kPanel,
+  // row l at l * kPanel), two reduction buffers
+  double* Cp = lds;
+  double* AU = Cp + (size_t)kPanel * s;
+  double* BX = AU + (size_t)m * kPanel;
+  double* rbuf = BX + (size_t)m * kPanel;
 
-  if (mode == kRqReduce) {
-    for (int q = tid; q < s; q += kRqThreads) a.out_c[q] = red[q] * a.inv_sqrt_zeta;
-    if (a.out_dots && tid < a.nwin) a.out_dots[tid] = red[s + tid];
-    if (a.out_norm2 && tid == 0) a.out_norm2[0] = red[s + kMaxT];
-    return;
-  }
+  DevCtl* ctl = a.ctl;
+  const int q = threadIdx.x;  // this thread's sketch row (and row of T / R)
+  const int lane = q & (kWave - 1);
+  const int wid = q / kWave;
+  const int k0 = a.k0;
+  const int p = a.ncols;
+  const double* __restrict__ V = a.V;
+  const double* __restrict__ T = a.T;
+  const bool row = q < s;
 
-  if (mode == kRqInit) {
-    double nrm = 0.0;
-    for (int q = tid; q < s; q += kRqThreads) {
-      const double v = red[q] * a.inv_sqrt_zeta;
-      a.d[q] = v;
-      nrm += v * v;
+  // ---- every input at once: panel rows, d, estimate vectors, cycle state --
+#pragma unroll
+  for (int j = 0; j < kPanel; ++j) {
+    const int col = k0 + j;
+    double v = 0.0;
+    if (j < p && row) {
+      const double sc = (a.t > 0 ? a.sigma[col] : 1.0) * a.inv_sqrt_zeta;
+      v = a.red[(int64_t)(col % a.nring) * a.slot_red + q] * sc;
     }
-    nrm = block_sum(nrm, scratch);
-    if (tid == 0) {
-      ctl->d0norm = sqrt(nrm);
-      ctl->stop_k = 0;
-      ctl->stop_step = 0;
-      ctl->stop_reason = 0;
-      ctl->qr_k = 0;
-      ctl->forced_k = a.forced_k;
-      ctl->ice_smax = 0.0;
-      ctl->ice_znorm = 0.0;
-      ctl->cond_cur = ctl->cond_prev = 0.0;
-      ctl->rho_cur = ctl->rho_prev = 0.0;
-      a.sigma[0] = 1.0;
-    }
-    return;
+    if (row) Cp[j * s + q] = v;
   }
+  double dq = row ? a.d[q] : 0.0;
+  double xq = q < k0 ? a.ice_x[q] : 0.0;
+  double zq = q < k0 ? a.ice_z[q] : 0.0;
+  const int stop_in = ctl->stop_k;
+  const int brk_step = ctl->brk_step;
+  const int forced_k = ctl->forced_k;
+  const double cond_thr = ctl->cond_threshold;
+  const double factor = ctl->factor;
+  const double tol_abs = ctl->tol_abs;
+  double smax = ctl->ice_smax, znorm = ctl->ice_znorm;
+  double cond_cur = ctl->cond_cur, cond_prev = ctl->cond_prev;
+  double rho_cur = ctl->rho_cur, rho_prev = ctl->rho_prev;
+  int err = ctl->error;
+  if (stop_in != 0) return;
+  __syncthreads();
+  int par = 0;
 
-  // ---- kRqStep: one column appended to the sketched QR -------------------
-  const int k = ctl->qr_k;  // existing columns; the new one has index k
-  const int step = a.step;  // == k
-  // sigma_i of the current Arnoldi vector u_i
-  if (a.t > 0 && step > 0) {
-    const double n2u = block_sum_strided(a.vpart, a.Gv, 1, scratch);
-    if (n2u == 0.0) {
-      // u_i = 0: truncated Arnoldi broke down; keep the i columns built so far
-      if (tid == 0) {
-        ctl->stop_k = step;
-        ctl->stop_step = step;
-        ctl->stop_reason = SFGMRES_STOP_BREAKDOWN;
-        publish_inner(a.hs, ctl, step);
+  if (k0 > 0) {
+    // A = V^T C, then B = T^T A (a wave per pair of columns of T, lanes over
+    // its rows), then C <- C - V B (a thread per row)
+    vt_panel(V, s, k0, 0, Cp, false, AU);
+    __syncthreads();
+    for (int lb = wid * 2; lb < k0; lb += kQrWaves * 2) {
+      const bool has1 = lb + 1 < k0;
+      double acc0[kPanel], acc1[kPanel];
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j) acc0[j] = acc1[j] = 0.0;
+      for (int r = lane; r <= lb + 1 && r < k0; r += kWave) {
+        const double t0 = r <= lb ? T[(int64_t)lb * m + r] : 0.0;
+        const double t1 = has1 ? T[(int64_t)(lb + 1) * m + r] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) {
+          const double av = AU[r * kPanel + j];
+          acc0[j] += t0 * av;
+          acc1[j] += t1 * av;
+        }
       }
-      return;
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j) {
+        const double r0 = wave_sum(acc0[j]);
+        const double r1 = wave_sum(acc1[j]);
+        if (lane == 0) {
+          BX[lb * kPanel + j] = r0;
+          if (has1) BX[(lb + 1) * kPanel + j] = r1;
+        }
+      }
     }
-    if (tid == 0) bc[0] = 1.0 / sqrt(n2u);
-  } else if (tid == 0) {
-    bc[0] = a.sigma[step];
-  }
-  __syncthreads();
-  const double sig = bc[0];
-  if (tid == 0) a.sigma[step] = sig;
-  const double cscale = (a.t > 0 ? sig : 1.0) * a.inv_sqrt_zeta;
-  for (int q = tid; q < s; q += kRqThreads) cv[q] = red[q] * cscale;
-  __syncthreads();
-
-  // a = V^T c  (column l of V is zero above row l, one at row l)
-  for (int l = wid; l < k; l += nw) {
-    double acc = 0.0;
-    for (int q = l + lane; q < s; q += kWave) acc += a.V[(int64_t)l * s + q] * cv[q];
-    acc = wave_sum(acc);
-    if (lane == 0) av[l] = acc;
-  }
-  __syncthreads();
-  // b = T^T a  (T upper triangular, row-major)
-  for (int l = tid; l < k; l += kRqThreads) {
-    double acc = 0.0;
-    for (int p = 0; p <= l; ++p) acc += a.T[(int64_t)p * m + l] * av[p];
-    bv[l] = acc;
-  }
-  __syncthreads();
-  // c <- c - V b
-  for (int q = tid; q < s; q += kRqThreads) {
-    double acc = 0.0;
-    const int lmax = q < k - 1 ? q : k - 1;
-    for (int l = 0; l <= lmax; ++l) acc += a.V[(int64_t)l * s + q] * bv[l];
-    cv[q] -= acc;
-  }
-  __syncthreads();
-  // new reflector for c[k:]
-  double x2 = 0.0;
-  for (int q = k + 1 + tid; q < s; q += kRqThreads) x2 += cv[q] * cv[q];
-  x2 = block_sum(x2, scratch);
-  if (tid == 0) {
-    const double alpha = cv[k];
-    double beta, tau, den;
-    if (x2 == 0.0) {
-      beta = alpha;
-      tau = 0.0;
-      den = 0.0;
-    } else {
-      beta = -copysign(sqrt(alpha * alpha + x2), alpha);
-      tau = (beta - alpha) / beta;
-      den = alpha - beta;
+    __syncthreads();
+    if (row) {
+      double acc[kPanel];
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j) acc[j] = 0.0;
+      int l = 0;
+      for (; l + 8 <= k0; l += 8) {
+        double vl[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) vl[u] = V[(int64_t)(l + u) * s + q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int j = 0; j < kPanel; ++j) acc[j] += vl[u] * BX[(l + u) * kPanel + j];
+      }
+      for (; l < k0; ++l) {
+        const double vl = V[(int64_t)l * s + q];
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) acc[j] += vl * BX[l * kPanel + j];
+      }
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j) Cp[j * s + q] -= acc[j];
     }
-    bc[0] = beta;
-    bc[1] = tau;
-    bc[2] = den;
-    a.tau[k] = tau;
-    a.R[(int64_t)k * m + k] = beta;
   }
-  __syncthreads();
-  const double beta = bc[0];
-  const double tau = bc[1];
-  const double den = bc[2];
-  // store the reflector (unit at row k) in V and the new column of R
-  for (int q = tid; q < s; q += kRqThreads) {
-    double v;
-    if (q < k)
-      v = 0.0;
-    else if (q == k)
-      v = 1.0;
-    else
-      v = den != 0.0 ? cv[q] / den : 0.0;
-    a.V[(int64_t)k * s + q] = v;
-    if (q < k) a.R[(int64_t)k * m + q] = cv[q];
-    if (q > k) cv[q] = v;
-  }
-  if (tid == 0) cv[k] = 1.0;
-  __syncthreads();
-  // keep R's new column (rows < k; cv[0:k] is untouched above) for the estimate
-  for (int p = tid; p < k; p += kRqThreads) bv[p] = cv[p];
-  __syncthreads();
-  // u = V_old^T v_k (over rows >= k) -> av
-  for (int l = wid; l < k; l += nw) {
-    double acc = 0.0;
-    for (int q = k + lane; q < s; q += kWave) acc += a.V[(int64_t)l * s + q] * cv[q];
-    acc = wave_sum(acc);
-    if (lane == 0) av[l] = acc;
-  }
-  __syncthreads();
-  // T[:k, k] = -tau T[:k, :k] u ; T[k, k] = tau
-  for (int p = wid; p < k; p += nw) {
-    double acc = 0.0;
-    for (int l = p + lane; l < k; l += kWave) acc += a.T[(int64_t)p * m + l] * av[l];
-    acc = wave_sum(acc);
-    if (lane == 0) a.T[(int64_t)p * m + k] = -tau * acc;
-  }
-  if (tid == 0) a.T[(int64_t)k * m + k] = tau;
-  // d <- H_k d
-  double dl = 0.0;
-  for (int q = k + tid; q < s; q += kRqThreads) dl += cv[q] * a.d[q];
-  dl = block_sum(dl, scratch);
-  for (int q = k + tid; q < s; q += kRqThreads) a.d[q] -= tau * cv[q] * dl;
-  __syncthreads();
-  double rr = 0.0;
-  for (int q = k + 1 + tid; q < s; q += kRqThreads) rr += a.d[q] * a.d[q];
-  rr = block_sum(rr, scratch);
-  const double rho_hat = sqrt(rr);
 
-  // incremental condition estimate with the new column [bv[0:k]; beta]
-  double ax = 0.0, bz = 0.0;
-  for (int p = tid; p < k; p += kRqThreads) {
-    ax += a.ice_x[p] * bv[p];
-    bz += a.ice_z[p] * bv[p];
+  // ---- the panel, column by column --------------------------------------
+  // column kk = k0 + j: reflector on rows >= kk; d and the later panel
+  // columns updated; ||d[kk+1:]|| (C3); Bischof's incremental estimate with
+  // the new column [R(0:kk, kk); beta] (C2); the decision.  The scalars are
+  // computed identically by every thread from the reduced sums.
+  double beta, tau, den;
+  {
+    const double c0 = row ? Cp[q] : 0.0;
+    double r2[2] = {(q > k0 && row) ? c0 * c0 : 0.0, q == k0 ? c0 : 0.0};
+    qr_sum<2>(r2, rbuf, par);
+    reflector(r2[1], r2[0], beta, tau, den);
   }
-  ax = block_sum(ax, scratch);
-  bz = block_sum(bz, scratch);
-  if (tid == 0) {
+  double my_beta = 0.0, my_tau = 0.0;  // of the column whose pivot row is q
+  int stop_k = 0, stop_step = 0, stop_reason = 0, qr_k = k0;
+  bool stopped = false;
+  int done = k0;
+#pragma unroll 1
+  for (int j = 0; j < p; ++j) {
+    const int kk = k0 + j;
+    if (brk_step == kk) {
+      // this column's Arnoldi vector is zero: keep the kk columns before it
+      stop_k = kk;
+      stop_step = kk;
+      stop_reason = SFGMRES_STOP_BREAKDOWN;
+      stopped = true;
+      break;
+    }
+    if (q == kk) {
+      my_beta = beta;
+      my_tau = tau;
+    }
+    if (q == 0) tau_sh[j] = tau;
+    // the reflector vector replaces rows >= kk of column j (rows < kk hold
+    // R's new column)
+    double cj = row ? Cp[j * s + q] : 0.0;
+    if (q == kk)
+      cj = 1.0;
+    else if (q > kk && row)
+      cj = den != 0.0 ? cj / den : 0.0;
+    if (row) Cp[j * s + q] = cj;
+    double cl[kPanel];
+#pragma unroll
+    for (int jj = 0; jj < kPanel; ++jj) cl[jj] = (row && jj > j) ? Cp[jj * s + q] : 0.0;
+    double red[kPanel + 3];
+#pragma unroll
+    for (int i = 0; i < kPanel + 3; ++i) red[i] = 0.0;
+    if (q >= kk && row) {
+      red[0] = cj * dq;
+#pragma unroll
+      for (int jj = 0; jj < kPanel; ++jj) red[1 + jj] = cj * cl[jj];
+    }
+    if (q < kk) {
+      red[kPanel + 1] = xq * cj;
+      red[kPanel + 2] = zq * cj;
+    }
+    qr_sum<kPanel + 3>(red, rbuf, par);
+    double cn = 0.0;  // row q of the next column after this reflector
+    if (q >= kk && row) {
+      const double tv = tau * cj;
+      dq -= tv * red[0];
+#pragma unroll
+      for (int jj = 0; jj < kPanel; ++jj) {
+        if (jj > j) {
+          const double nv = cl[jj] - tv * red[1 + jj];
+          Cp[jj * s + q] = nv;
+          if (jj == j + 1) cn = nv;
+        }
+      }
+    } else if (j + 1 < kPanel && row) {
+      cn = Cp[(j + 1) * s + q];
+    }
+    // ||d[kk+1:]||^2 and the next column's squared tail and pivot
+    double r3[3] = {(q > kk && row) ? dq * dq : 0.0, (q > kk + 1 && row) ? cn * cn : 0.0,
+                    q == kk + 1 ? cn : 0.0};
+    qr_sum<3>(r3, rbuf, par);
+    const double rho_hat = sqrt(r3[0]);
+    const double ax = red[kPanel + 1], bz = red[kPanel + 2];
     const double gam = beta;
     double kappa;
-    if (gam == 0.0 || ctl->ice_smax < 0.0) {
-      ctl->ice_smax = -1.0;  // singular from here on
+    if (gam == 0.0 || smax < 0.0) {
+      smax = -1.0;  // singular from here on
       kappa = INFINITY;
-      bc[3] = 0.0;
-      bc[4] = 0.0;
-      bc[5] = 0.0;
-      bc[6] = 0.0;
-    } else if (k == 0) {
-      ctl->ice_smax = fabs(gam);
-      ctl->ice_znorm = 1.0 / fabs(gam);
-      a.ice_x[0] = 1.0;
-      a.ice_z[0] = 1.0 / gam;
-      kappa = ctl->ice_smax * ctl->ice_znorm;
-      bc[3] = 0.0;
+    } else if (kk == 0) {
+      smax = fabs(gam);
+      znorm = 1.0 / fabs(gam);
+      kappa = smax * znorm;
+      if (q == 0) {
+        xq = 1.0;
+        zq = 1.0 / gam;
+      }
     } else {
-      double lam, vs, vc;
-      const double sm = ctl->ice_smax;
-      top_eig2(sm * sm + ax * ax, ax * gam, gam * gam, lam, vs, vc);
-      bc[3] = vs;
-      bc[4] = vc;
-      ctl->ice_smax = sqrt(lam);
-      const double zn = ctl->ice_znorm;
+      double lam, s1, c1, s2, c2;
+      top_eig2(smax * smax + ax * ax, ax * gam, gam * gam, lam, s1, c1);
+      smax = sqrt(lam);
       const double g2 = gam * gam;
-      top_eig2(zn * zn + bz * bz / g2, -bz / g2, 1.0 / g2, lam, vs, vc);
-      bc[5] = vs;
-      bc[6] = vc;
-      ctl->ice_znorm = sqrt(lam);
-      kappa = ctl->ice_smax * ctl->ice_znorm;
+      top_eig2(znorm * znorm + bz * bz / g2, -bz / g2, 1.0 / g2, lam, s2, c2);
+      znorm = sqrt(lam);
+      kappa = smax * znorm;
+      if (q < kk) {
+        xq *= s1;
+        zq *= s2;
+      } else if (q == kk) {
+        xq = c1;
+        zq = (c2 - s2 * bz) / gam;
+      }
     }
-    bc[7] = kappa;
-  }
-  __syncthreads();
-  if (k > 0 && bc[7] < INFINITY) {
-    const double s1 = bc[3], c1 = bc[4], s2 = bc[5], c2 = bc[6];
-    for (int p = tid; p < k; p += kRqThreads) {
-      a.ice_x[p] *= s1;
-      a.ice_z[p] *= s2;
-    }
-    if (tid == 0) {
-      a.ice_x[k] = c1;
-      a.ice_z[k] = (c2 - s2 * bz) / beta;
-    }
-  }
-
-  if (tid == 0) {
-    const double kappa = bc[7];
-    const int ncols = k + 1;
-    ctl->qr_k = ncols;
-    ctl->cond_prev = ctl->cond_cur;
-    ctl->rho_prev = ctl->rho_cur;
-    ctl->cond_cur = kappa;
-    ctl->rho_cur = rho_hat;
+    const int ncols = kk + 1;
+    qr_k = ncols;
+    cond_prev = cond_cur;
+    rho_prev = rho_cur;
+    cond_cur = kappa;
+    rho_cur = rho_hat;
     int stop = 0, reason = 0;
     if (ncols == 1 && beta == 0.0) {
-      ctl->error = SFGMRES_ERR_BREAKDOWN;
+      err = SFGMRES_ERR_BREAKDOWN;
       stop = 1;
       reason = SFGMRES_STOP_BREAKDOWN;
-    } else if (ctl->forced_k > 0) {
-      if (ncols >= ctl->forced_k) {
-        stop = ctl->forced_k;
+    } else if (forced_k > 0) {
+      if (ncols >= forced_k) {
+        stop = forced_k;
         reason = SFGMRES_STOP_FORCED;
       }
-    } else if (ncols > 1 && kappa > ctl->cond_threshold) {
+    } else if (ncols > 1 && kappa > cond_thr) {
       stop = ncols - 1;
       reason = SFGMRES_STOP_C2;
-    } else if (ctl->factor * rho_hat <= ctl->tol_abs) {
+    } else if (factor * rho_hat <= tol_abs) {
       stop = ncols;
       reason = SFGMRES_STOP_C3;
     } else if (ncols >= m) {
       stop = m;
       reason = SFGMRES_STOP_C1;
     }
-    if (!stop) {
-      if (a.t == 0) {
-        // power basis: the next vector is y = A b_i itself; sigma_{i+1} = 1/||y||
-        const double n2 = red[s + kMaxT];
-        if (n2 == 0.0) {
-          stop = ncols;
-          reason = SFGMRES_STOP_BREAKDOWN;
-        } else {
-          a.sigma[step + 1] = 1.0 / sqrt(n2);
+    if (!isfinite(rho_hat) && err == 0) err = SFGMRES_ERR_NONFINITE;
+    done = ncols;
+    if (stop) {
+      stop_k = stop;
+      stop_step = ncols;
+      stop_reason = reason;
+      stopped = true;
+      break;
+    }
+    reflector(r3[2], r3[1], beta, tau, den);
+  }
+  const int ndone = done - k0;  // columns whose reflector was formed
+
+  // ---- T extended by the p new reflectors (only if the cycle goes on) ----
+  // (Cp holds the new reflectors on rows >= their pivot, R's new columns
+  // above; rows of V above the pivot are zero)
+  double tn[kPanel];
+#pragma unroll
+  for (int j = 0; j < kPanel; ++j) tn[j] = 0.0;
+  if (!stopped) {
+    __syncthreads();  // the panel rows are read across threads below
+    // U = V_old^T V_new (rows >= k0; the new vectors vanish above their unit)
+    vt_panel(V, s, k0, k0, Cp, true, AU);
+    {
+      // wave sums of the products, column y of Wm at a time, into the
+      // reduction buffer (entry y (y - 1) / 2 + x), then one thread per entry
+      // sums the waves in wave order
+      double* buf = rbuf + par * kRHalf;
+      par ^= 1;
+#pragma unroll
+      for (int y = 1; y < kPanel; ++y) {
+        const double cy = (q >= k0 + y && row) ? Cp[y * s + q] : 0.0;
+#pragma unroll
+        for (int x = 0; x < y; ++x) {
+          const double w = wave_sum(cy * (row ? Cp[x * s + q] : 0.0));
+          if (lane == 0) buf[wid * kRB + y * (y - 1) / 2 + x] = w;
         }
-      } else {
-        // u_{i+1} = sigma_i y - sum_l sigma_i sigma_l^2 <y, u_l> u_l: A b_i
-        // minus its projections h_l b_l on the window b_l = sigma_l u_l,
-        // h_l = sigma_i sigma_l <y, u_l>; ||u_{i+1}|| = h_{i+1,i}
-        for (int l = 0; l < a.nwin; ++l) {
-          const double sg = (a.l0 + l == step) ? sig : a.sigma[a.l0 + l];
-          a.coef[l] = sig * sg * sg * red[s + l];
-        }
-        a.coef[kMaxT] = sig;
+      }
+      __syncthreads();  // also publishes AU
+      if (q < kPanel * (kPanel - 1) / 2) {
+        int y = 1;
+        while (y * (y + 1) / 2 <= q) ++y;
+        const int x = q - y * (y - 1) / 2;
+        double r = 0.0;
+        for (int w = 0; w < kQrWaves; ++w) r += buf[w * kRB + q];
+        Wm[x][y] = r;
       }
     }
-    if (!isfinite(rho_hat) && ctl->error == 0) ctl->error = SFGMRES_ERR_NONFINITE;
-    if (stop) {
-      ctl->stop_k = stop;
-      ctl->stop_step = step + 1;
-      ctl->stop_reason = reason;
+    __syncthreads();
+    // row r = q of X = T_old U, then of the new columns:
+    // T(0:kk, kk) = -tau_kk T(0:kk, 0:kk) [U(:, j); Wm(0:j, j)], T(kk, kk) = tau_kk
+    double xr[kPanel];
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) xr[j] = 0.0;
+    if (q < k0) {
+      int l = q;
+      for (; l + 8 <= k0; l += 8) {
+        double tv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) tv[u] = T[(int64_t)(l + u) * m + q];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+#pragma unroll
+          for (int j = 0; j < kPanel; ++j) xr[j] += tv[u] * AU[(l + u) * kPanel + j];
+      }
+      for (; l < k0; ++l) {
+        const double tv = T[(int64_t)l * m + q];
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) xr[j] += tv * AU[l * kPanel + j];
+      }
     }
-    publish_inner(a.hs, ctl, step + 1);
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j) {
+      const int kk = k0 + j;
+      if (q < kk) {
+        double acc = xr[j];
+#pragma unroll
+        for (int jj = 0; jj < j; ++jj)
+          if (q <= k0 + jj) acc += tn[jj] * Wm[jj][j];
+        tn[j] = -tau_sh[j] * acc;
+      } else if (q == kk) {
+        tn[j] = tau_sh[j];
+      }
+    }
+  }
+
+  // ---- write back ---------------------------------------------------------
+  for (int j = 0; j < ndone; ++j) {
+    const int kk = k0 + j;
+    const double cj = row ? Cp[j * s + q] : 0.0;
+    if (row) a.V[(int64_t)kk * s + q] = q < kk ? 0.0 : cj;
+    if (q < kk) a.R[(int64_t)kk * m + q] = cj;
+  }
+  if (q >= k0 && q < done) {
+    a.R[(int64_t)q * m + q] = my_beta;
+    a.tau[q] = my_tau;
+  }
+  if (!stopped) {
+#pragma unroll
+    for (int j = 0; j < kPanel; ++j)
+      if (j < p && q <= k0 + j) a.T[(int64_t)(k0 + j) * m + q] = tn[j];
+  }
+  if (row) a.d[q] = dq;
+  if (q < done) {
+    a.ice_x[q] = xq;
+    a.ice_z[q] = zq;
+  }
+  if (q == 0) {
+    ctl->stop_k = stop_k;
+    ctl->stop_step = stop_step;
+    ctl->stop_reason = stop_reason;
+    ctl->qr_k = qr_k;
+    ctl->error = err;
+    ctl->ice_smax = smax;
+    ctl->ice_znorm = znorm;
+    ctl->cond_cur = cond_cur;
+    ctl->cond_prev = cond_prev;
+    ctl->rho_cur = rho_cur;
+    ctl->rho_prev = rho_prev;
+    host_store_i32(&a.hs->stop_k, stop_k);
+    host_store_i32(&a.hs->stop_step, stop_step);
+    host_store_i32(&a.hs->stop_reason, stop_reason);
+    host_store_i32(&a.hs->error, err);
+    host_store_i32(&a.hs->steps_run, k0 + p);
+    host_store_i32(&a.hs->inner_step_done, done);
   }
 }
 
-hipError_t launch_rq(int mode, const RqArgs& a, hipStream_t st) {
-  hipLaunchKernelGGL(k_rq, dim3(1), dim3(kRqThreads), 0, st, a, mode);
+hipError_t launch_qr_block(const QrBlockArgs& a, hipStream_t st) {
+  const size_t lds = qr_block_lds_bytes(a.s, a.m);
+  static bool attr_set = false;
+  if (!attr_set) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_qr_block),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize,
+                                             (int)qr_block_lds_bytes(kMaxS, kMaxM));
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_qr_block, dim3(1), dim3(kQrThreads), lds, st, a);
+  return hipGetLastError();
+}
+
+// d0 = S v_j (reduced, times 1/sqrt(zeta)); reset the inner-cycle state.
+__global__ __launch_bounds__(256) void k_rq_init(const double* red, int32_t s, double inv_sqrt_zeta,
+                                                 int32_t forced_k, DevCtl* ctl, double* d,
+                                                 double* sigma) {
+  __shared__ double scratch[256 / kWave];
+  double nrm = 0.0;
+  for (int q = threadIdx.x; q < s; q += blockDim.x) {
+    const double v = red[q] * inv_sqrt_zeta;
+    d[q] = v;
+    nrm += v * v;
+  }
+  nrm = block_sum(nrm, scratch);
+  if (threadIdx.x == 0) {
+    ctl->d0norm = sqrt(nrm);
+    ctl->stop_k = 0;
+    ctl->stop_step = 0;
+    ctl->stop_reason = 0;
+    ctl->qr_k = 0;
+    ctl->forced_k = forced_k;
+    ctl->ice_smax = 0.0;
+    ctl->ice_znorm = 0.0;
+    ctl->cond_cur = ctl->cond_prev = 0.0;
+    ctl->rho_cur = ctl->rho_prev = 0.0;
+    ctl->brk_step = -1;
+    sigma[0] = 1.0;
+  }
+}
+
+hipError_t launch_rq_init(const double* red, int32_t s, double inv_sqrt_zeta, int32_t forced_k,
+                          DevCtl* ctl, double* d, double* sigma, hipStream_t st) {
+  hipLaunchKernelGGL(k_rq_init, dim3(1), dim3(256), 0, st, red, s, inv_sqrt_zeta, forced_k, ctl,
+                     d, sigma);
+  return hipGetLastError();
+}
+
+// Test export of one fused SpMV: the reduced sketch times 1/sqrt(zeta), the
+// window dots and ||w||^2 summed from the scalar rows in slot order.
+__global__ __launch_bounds__(256) void k_sketch_out(const double* red, int32_t s,
+                                                    double inv_sqrt_zeta, const double* dpart,
+                                                    int32_t G, int32_t nwin, double* out_c,
+                                                    double* out_dots, double* out_norm2) {
+  __shared__ double scratch[256 / kWave];
+  for (int q = threadIdx.x; q < s; q += blockDim.x) out_c[q] = red[q] * inv_sqrt_zeta;
+  if (!dpart) return;
+  for (int l = 0; l < nwin; ++l) {
+    const double v = block_sum_strided(dpart + l, G, kDP, scratch);
+    if (threadIdx.x == 0 && out_dots) out_dots[l] = v;
+  }
+  const double v = block_sum_strided(dpart + kMaxT, G, kDP, scratch);
+  if (threadIdx.x == 0 && out_norm2) out_norm2[0] = v;
+}
+
+hipError_t launch_sketch_out(const double* red, int32_t s, double inv_sqrt_zeta,
+                             const double* dpart, int32_t G, int32_t nwin, double* out_c,
+                             double* out_dots, double* out_norm2, hipStream_t st) {
+  hipLaunchKernelGGL(k_sketch_out, dim3(1), dim3(256), 0, st, red, s, inv_sqrt_zeta, dpart, G,
+                     nwin, out_c, out_dots, out_norm2);
   return hipGetLastError();
 }
 

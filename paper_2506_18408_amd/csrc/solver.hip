@@ -6,18 +6,23 @@
 // B_k y, the outer SpMV, modified Gram-Schmidt, the Givens update and the
 // normalised v_{j+1} with its sketch.
 //
-// One inner step i is four launches: the fused SpMV y = A u_i (+ S y, window
-// dots, ||y||^2 as per-workgroup partial rows), the row reduction, the
-// one-workgroup decision kernel (sigma_i, QR column, ICE, C1-C3, Arnoldi
-// coefficients) and, for t > 0, the truncated-Arnoldi update u_{i+1}.  The
-// inner basis is kept unnormalised (u_i = the orthogonalised A b_{i-1}, of
-// norm h_{i,i-1}, with sigma_i = 1/||u_i|| held on the device), so no kernel
-// waits for a scalar its predecessor has just reduced.
-// The host stays a few inner steps ahead of the device: every inner kernel is
-// predicated on the device's stop flag, and the host polls a pinned status
-// block (written by the decision kernel) to stop enqueuing once the cycle has
-// ended.  The host synchronises once per outer step to read the minimised
-// residual.
+// The inner steps run on the caller's stream.  Step i is the fused SpMV
+// y = A u_i (+ S y as per-workgroup partial rows in ring slot i mod p, the
+// window dots and ||y||^2 as scalar rows), the one-workgroup coefficient
+// kernel (sigma_i and the window coefficients) and, for t > 0, the
+// truncated-Arnoldi update u_{i+1}.  After every p steps (a panel), one
+// reduction sums the panel's sketch rows and one decision kernel appends its
+// p columns to the sketched QR and decides after each column (C1-C3);
+// only it ends the cycle, so up to p - 1 steps past the stop are computed
+// and discarded.  The inner basis is kept unnormalised (u_i = the
+// orthogonalised A b_{i-1}, of norm h_{i,i-1}, with sigma_i = 1/||u_i|| held
+// on the device), so no kernel waits for a scalar its predecessor has just
+// reduced.
+// The host stays up to `lookahead` inner steps ahead of the last decided
+// column: every inner kernel is predicated on the device's stop flag, and
+// the host polls a pinned status block (written by the decision kernel) to
+// stop enqueuing once the cycle has ended.  The host synchronises once per
+// outer step to read the minimised residual.
 #include <math.h>
 #include <string.h>
 
@@ -34,22 +39,28 @@ struct sfgmres_ctx {
   sfg::HostStatus* hs_host = nullptr;
   sfg::HostStatus* hs_dev = nullptr;
   std::string err;
-  std::vector<hipEvent_t> ev;
+  std::vector<hipEvent_t> ev;  // timing events (profile option)
 };
 
 namespace sfg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Columns per decision launch and the host's lookahead (in inner steps).
+int panel_cols(const sfgmres_options& o) { return o.panel > 0 ? o.panel : kPanel; }
+int lookahead_steps(const sfgmres_options& o) {
+  const int p = panel_cols(o);
+  return o.lookahead > 0 ? std::max(o.lookahead, p) : 2 * p;
+}
+
 Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
-                   int32_t J, int32_t precision, int32_t adjoint) {
+                   int32_t J, int32_t precision, int32_t adjoint, int32_t panel) {
   (void)t;
   Layout L{};
   const bool f32 = precision == SFGMRES_MIXED;
   L.ld = (n + 63) / 64 * 64;
   L.ntiles_max = n / kRowTile + nnz / kTileNnz + 3;
   L.grid = kMaxGrid;
-  const int64_t E = s + kPartExtra;
   const size_t vt = f32 ? 4 : 8;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -61,9 +72,10 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.tiles = take((size_t)(L.ntiles_max + 1) * 4);
   L.tp = take((size_t)(L.ntiles_max + 1) * 4);
   L.ipart = take((size_t)(kVecGrid + 1) * 4);
-  L.part = take((size_t)kMaxGrid * E * 8);
+  L.part = take((size_t)panel * kMaxGrid * s * 8);
+  L.dpart = take((size_t)kMaxGrid * kDP * 8);
   L.vpart = take((size_t)kVecGrid * 8);
-  L.red = take((size_t)E * 8);
+  L.red = take((size_t)panel * s * 8);
   L.skp = take(packed_sketch_bytes(n, zeta));
   L.qr_V = take((size_t)s * m * 8);
   L.qr_T = take((size_t)m * m * 8);
@@ -130,6 +142,7 @@ sfgmres_options defaults() {
   o.record_true_residual = 0;
   o.profile = 0;
   o.lookahead = 0;
+  o.panel = 0;
   return o;
 }
 
@@ -152,9 +165,13 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
   if (!(tol > 0.0) || !isfinite(tol)) return fail(h, SFGMRES_ERR_INVALID, "tol must be > 0");
   if (o.precision != SFGMRES_FP64 && o.precision != SFGMRES_MIXED)
     return fail(h, SFGMRES_ERR_INVALID, "unknown precision");
+  if (o.profile < 0) return fail(h, SFGMRES_ERR_INVALID, "need profile >= 0");
   if (o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
     return fail(h, SFGMRES_ERR_INVALID, "need 1 <= max_outer <= 2000");
   if (!(o.cond_threshold > 0.0)) return fail(h, SFGMRES_ERR_INVALID, "cond_threshold must be > 0");
+  if (o.lookahead < 0 || o.lookahead > 64)
+    return fail(h, SFGMRES_ERR_INVALID, "need 0 <= lookahead <= 64");
+  if (o.panel < 0 || o.panel > kPanel) return fail(h, SFGMRES_ERR_INVALID, "need 0 <= panel <= 8");
   return SFGMRES_OK;
 }
 
@@ -206,7 +223,7 @@ int plan_tiling(sfgmres_handle h, const sfgmres_csr* A, int32_t* tiles, int32_t*
 struct Ptrs {
   DevCtl* ctl;
   int32_t *tiles, *tp, *ipart;
-  double *part, *vpart, *red, *V, *T, *R, *d, *scal, *tau, *ice_x, *ice_z, *sigma, *coef, *yin,
+  double *part, *dpart, *vpart, *red, *V, *T, *R, *d, *scal, *tau, *ice_x, *ice_z, *sigma, *coef, *yin,
       *H, *HR, *cs, *sn, *g, *yout, *Vb, *Zb, *W64, *X;
   uint2* skp;
   void* Bb;
@@ -220,6 +237,7 @@ Ptrs make_ptrs(char* base, const Layout& L) {
   p.tp = reinterpret_cast<int32_t*>(base + L.tp);
   p.ipart = reinterpret_cast<int32_t*>(base + L.ipart);
   p.part = reinterpret_cast<double*>(base + L.part);
+  p.dpart = reinterpret_cast<double*>(base + L.dpart);
   p.vpart = reinterpret_cast<double*>(base + L.vpart);
   p.red = reinterpret_cast<double*>(base + L.red);
   p.skp = reinterpret_cast<uint2*>(base + L.skp);
@@ -287,7 +305,8 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   if (rc) return rc;
   if (!A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val)) || !b || !x)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0);
+  const int pc = panel_cols(o);
+  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0, pc);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   char* base = static_cast<char*>(ws);
@@ -297,12 +316,13 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int ldh = J + 1;
   const int64_t ld = L.ld;
   const size_t vt = f32 ? 4 : 8;
-  const int E = s + kPartExtra;
   const int zb = zeta_blocks(zeta);
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu);
   const uint32_t k1 = (uint32_t)(seed >> 32);
   const double inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
-  const int lookahead = o.lookahead > 0 ? o.lookahead : 4;
+  const int lookahead = lookahead_steps(o);
+  const int64_t slot_part = (int64_t)kMaxGrid * s;  // ring slot of sketch rows
+  const int64_t slot_red = s;                       // ring slot of reduced rows
   HostStatus* hsd = h->hs_dev;
   volatile HostStatus* hsh = h->hs_host;
   auto Bcol = [&](int64_t l) -> void* { return static_cast<char*>(P.Bb) + l * ld * vt; };
@@ -349,30 +369,41 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   base_args.tp = P.tp;
   base_args.ntiles = ntiles;
   base_args.part = P.part;
-  base_args.E = E;
+  base_args.dpart = P.dpart;
   base_args.ctl = P.ctl;
   base_args.scale_val = 1.0;
   base_args.skp = P.skp;
 
-  RqArgs rq{};
-  rq.red = P.red;
-  rq.vpart = P.vpart;
-  rq.Gv = G2;
-  rq.s = s;
-  rq.m = m;
-  rq.t = t;
-  rq.inv_sqrt_zeta = inv_sqrt_zeta;
-  rq.ctl = P.ctl;
-  rq.hs = hsd;
-  rq.V = P.V;
-  rq.T = P.T;
-  rq.R = P.R;
-  rq.d = P.d;
-  rq.tau = P.tau;
-  rq.ice_x = P.ice_x;
-  rq.ice_z = P.ice_z;
-  rq.sigma = P.sigma;
-  rq.coef = P.coef;
+  QrBlockArgs qa{};
+  qa.red = P.red;
+  qa.slot_red = slot_red;
+  qa.nring = pc;
+  qa.s = s;
+  qa.m = m;
+  qa.t = t;
+  qa.inv_sqrt_zeta = inv_sqrt_zeta;
+  qa.ctl = P.ctl;
+  qa.hs = hsd;
+  qa.V = P.V;
+  qa.T = P.T;
+  qa.R = P.R;
+  qa.d = P.d;
+  qa.tau = P.tau;
+  qa.ice_x = P.ice_x;
+  qa.ice_z = P.ice_z;
+  qa.sigma = P.sigma;
+
+  // S v for the normalised vector just written: sketch rows into ring slot
+  // 0, reduced, then d0 and the cycle reset
+  auto sketch_v_and_init = [&](const double* W, const double* hptr, double* vout,
+                               int32_t forced_k) -> int {
+    SFG_HIP(launch_normalize_sketch(f32, Gn, n, W, hptr, vout, Bcol(0), s, P.skp, zb, P.part,
+                                    st));
+    SFG_HIP(launch_reduce_slots(P.part, Gn, s, s, 0, 1, pc, slot_part, slot_red, P.red, P.ctl,
+                                false, st));
+    SFG_HIP(launch_rq_init(P.red, s, inv_sqrt_zeta, forced_k, P.ctl, P.d, P.sigma, st));
+    return SFGMRES_OK;
+  };
 
   // ---- r0 = b - A x0, beta, ||b||, v_1, S v_1 -----------------------------
   {
@@ -382,16 +413,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     a.w = P.W64;
     a.b = b;
     SFG_HIP(launch_spmv(kModeResid, false, Gp, a, 0, st));
-    SFG_HIP(launch_spmv_finish(kModeResid, P.part, Gp, E, P.ctl, P.g, hsd, st));
+    SFG_HIP(launch_spmv_finish(kModeResid, P.dpart, Gp, P.ctl, P.g, hsd, st));
   }
-  SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, &P.ctl->beta, Vcol(0), Bcol(0), s, P.skp,
-                                  zb, P.part, E, st));
-  SFG_HIP(launch_reduce_rows(P.part, Gn, E, P.red, P.ctl, false, st));
-  {
-    RqArgs r = rq;
-    r.forced_k = forced ? forced[0] : 0;
-    SFG_HIP(launch_rq(kRqInit, r, st));
-  }
+  rc = sketch_v_and_init(P.W64, &P.ctl->beta, Vcol(0), forced ? forced[0] : 0);
+  if (rc) return rc;
   SFG_HIP(hipStreamSynchronize(st));
   if (hsh->error) return fail(h, hsh->error, "non-finite initial residual or right-hand side");
   const double beta = hsh->beta;
@@ -428,7 +453,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     a.x = xv;
     a.b = b;
     SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, 0, st));
-    SFG_HIP(launch_spmv_finish(kModeTrueRes, P.part, Gp, E, P.ctl, P.scal, hsd, st));
+    SFG_HIP(launch_spmv_finish(kModeTrueRes, P.dpart, Gp, P.ctl, P.scal, hsd, st));
     SFG_HIP(hipMemcpyAsync(r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
     SFG_HIP(hipStreamSynchronize(st));
     return SFGMRES_OK;
@@ -440,10 +465,13 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   double rho_last = beta;
   int total_inner = 0;
   for (int j = 0; j < J; ++j) {
-    // inner sGMRES cycle, predicated steps with a bounded lookahead
+    // inner sGMRES cycle: predicated steps, a decision launch per panel, a
+    // bounded lookahead
     hsh->stop_k = 0;
     hsh->inner_step_done = 0;
     hsh->stop_step = 0;
+    hsh->steps_run = 0;
+    int panel0 = 0;  // first column of the open panel
     for (int i = 0; i < m; ++i) {
       if (i >= lookahead) {
         const int need = i - lookahead + 1;
@@ -467,19 +495,37 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       a.ldu = ld;
       a.l0 = l0;
       a.nwin = nwin;
-      if (o.profile) SFG_HIP(hipEventRecord(h->ev[2 * i], st));
-      SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st));
-      if (o.profile) SFG_HIP(hipEventRecord(h->ev[2 * i + 1], st));
-      SFG_HIP(launch_reduce_rows(P.part, Gp, E, P.red, P.ctl, true, st));
-      RqArgs r = rq;
-      r.step = i;
-      r.nwin = nwin;
-      r.l0 = l0;
-      SFG_HIP(launch_rq(kRqStep, r, st));
-      if (t > 0) {
+      a.part = P.part + (int64_t)(i % pc) * slot_part;
+      const bool timed = o.profile > 0 && i % o.profile == o.profile - 1;
+      SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st, timed ? h->ev[2 * i] : nullptr,
+                          timed ? h->ev[2 * i + 1] : nullptr));
+      CoefArgs ca{};
+      ca.dpart = P.dpart;
+      ca.G = Gp;
+      ca.vpart = P.vpart;
+      ca.Gv = G2;
+      ca.t = t;
+      ca.nwin = nwin;
+      ca.l0 = l0;
+      ca.step = i;
+      ca.ctl = P.ctl;
+      ca.sigma = P.sigma;
+      ca.coef = P.coef;
+      SFG_HIP(launch_coef(ca, st));
+      if (t > 0 && i + 1 < m) {
         const void* Wv = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
         SFG_HIP(launch_arnoldi_update(f32, G2, n, Wv, P.Bb, ld, l0, nwin, i + 1, P.coef, P.vpart,
                                       P.ctl, st));
+      }
+      if (i + 1 - panel0 == pc || i + 1 == m) {
+        const int ncols = i + 1 - panel0;
+        SFG_HIP(launch_reduce_slots(P.part, Gp, s, s, panel0 % pc, ncols, pc, slot_part,
+                                    slot_red, P.red, P.ctl, true, st));
+        QrBlockArgs q = qa;
+        q.k0 = panel0;
+        q.ncols = ncols;
+        SFG_HIP(launch_qr_block(q, st));
+        panel0 = i + 1;
       }
     }
     // z_j = B_k y_k
@@ -493,7 +539,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       a.v0 = Vcol(0);
       a.vj = Vcol(j);
       SFG_HIP(launch_spmv(kModeOuter, false, Gp, a, 0, st));
-      SFG_HIP(launch_spmv_finish(kModeOuter, P.part, Gp, E, P.ctl, P.H + (int64_t)j * ldh, hsd,
+      SFG_HIP(launch_spmv_finish(kModeOuter, P.dpart, Gp, P.ctl, P.H + (int64_t)j * ldh, hsd,
                                  st));
     }
     for (int l = 0; l <= j; ++l) {
@@ -505,24 +551,18 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
                                 P.sn, P.g, j, ldh, hsd, st));
     }
     // v_{j+1}, its copy as the next cycle's b_1, and S v_{j+1}
-    SFG_HIP(launch_normalize_sketch(f32, Gn, n, P.W64, P.H + (int64_t)j * ldh + j + 1,
-                                    Vcol(j + 1), Bcol(0), s, P.skp, zb, P.part, E, st));
-    SFG_HIP(launch_reduce_rows(P.part, Gn, E, P.red, P.ctl, false, st));
-    {
-      RqArgs r = rq;
-      r.forced_k = (forced && j + 1 < J) ? forced[j + 1] : 0;
-      SFG_HIP(launch_rq(kRqInit, r, st));
-    }
+    rc = sketch_v_and_init(P.W64, P.H + (int64_t)j * ldh + j + 1, Vcol(j + 1),
+                           (forced && j + 1 < J) ? forced[j + 1] : 0);
+    if (rc) return rc;
     SFG_HIP(hipStreamSynchronize(st));
     const int err = hsh->error;
     const int kj = hsh->k;
     const double rho = hsh->rho;
     J_done = j + 1;
     total_inner += kj;
-    if (o.profile) {
-      const int stop_step = hsh->stop_step;
-      const int worked = std::min(stop_step, m);
-      for (int i = 0; i < worked; ++i) {
+    if (o.profile > 0) {
+      const int worked = std::min((int)hsh->steps_run, m);
+      for (int i = o.profile - 1; i < worked; i += o.profile) {
         float ms = 0.f;
         SFG_HIP(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
         if (info) {
@@ -574,7 +614,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
 
 // Workspace of the stand-alone sketch and SpMV entry points.
 struct SmallLayout {
-  size_t ctl, tiles, tp, ipart, part, red, skp, total;
+  size_t ctl, tiles, tp, ipart, part, dpart, red, skp, total;
 };
 
 SmallLayout small_layout(int64_t n, int64_t nnz, int32_t s, int32_t zeta) {
@@ -585,14 +625,14 @@ SmallLayout small_layout(int64_t n, int64_t nnz, int32_t s, int32_t zeta) {
     off = align256(off + bytes);
     return o;
   };
-  const size_t E = (size_t)s + kPartExtra;
   L.ctl = take(sizeof(DevCtl));
   const size_t ntiles_max = (size_t)(n / kRowTile + nnz / kTileNnz + 3);
   L.tiles = take((ntiles_max + 1) * 4);
   L.tp = take((ntiles_max + 1) * 4);
   L.ipart = take((size_t)(kVecGrid + 1) * 4);
-  L.part = take((size_t)kMaxGrid * E * 8);
-  L.red = take(E * 8);
+  L.part = take((size_t)kMaxGrid * s * 8);
+  L.dpart = take((size_t)kMaxGrid * kDP * 8);
+  L.red = take((size_t)s * 8);
   L.skp = take(packed_sketch_bytes(n, zeta));
   L.total = off;
   return L;
@@ -613,9 +653,12 @@ int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_
   if (!bytes) return SFGMRES_ERR_INVALID;
   const sfgmres_options o = opt ? *opt : defaults();
   if (n < 1 || nnz < 0 || m < 1 || s <= m || s > SFGMRES_MAX_S || m > SFGMRES_MAX_M || t < 0 ||
-      zeta < 1 || zeta > SFGMRES_MAX_ZETA || o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
+      zeta < 1 || zeta > SFGMRES_MAX_ZETA || o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER ||
+      o.lookahead < 0 || o.lookahead > 64 || o.panel < 0 || o.panel > kPanel)
     return SFGMRES_ERR_INVALID;
-  *bytes = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, adjoint ? 1 : 0).total;
+  *bytes = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, adjoint ? 1 : 0,
+                       panel_cols(o))
+               .total;
   return SFGMRES_OK;
 }
 
@@ -685,7 +728,8 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   if (rc) return rc;
   if ((A->nnz > 0 && (!A->col_idx || !A->val)) || !g || !lambda)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  const Layout L = make_layout(A->n, A->nnz, m, t, s, zeta, o.max_outer, o.precision, 1);
+  const Layout L = make_layout(A->n, A->nnz, m, t, s, zeta, o.max_outer, o.precision, 1,
+                               panel_cols(o));
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -776,7 +820,6 @@ int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, u
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  const int E = s + kPartExtra;
   DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
   double* part = reinterpret_cast<double*>(base + L.part);
   double* red = reinterpret_cast<double*>(base + L.red);
@@ -786,16 +829,10 @@ int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, u
   SFG_HIP(launch_sketch_pack(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32),
                              skp, st));
   SFG_HIP(launch_normalize_sketch(false, G, n, w, nullptr, nullptr, nullptr, s, skp,
-                                  zeta_blocks(zeta), part, E, st));
-  SFG_HIP(launch_reduce_rows(part, G, E, red, ctl, false, st));
-  RqArgs r{};
-  r.red = red;
-  r.s = s;
-  r.inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
-  r.ctl = ctl;
-  r.out_c = out;
-  r.nwin = 0;
-  SFG_HIP(launch_rq(kRqReduce, r, st));
+                                  zeta_blocks(zeta), part, st));
+  SFG_HIP(launch_reduce_slots(part, G, s, s, 0, 1, 1, 0, 0, red, ctl, false, st));
+  SFG_HIP(launch_sketch_out(red, s, 1.0 / sqrt((double)zeta), nullptr, 0, 0, out, nullptr,
+                            nullptr, st));
   SFG_HIP(hipStreamSynchronize(st));
   return SFGMRES_OK;
 }
@@ -821,12 +858,12 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
   char* base = static_cast<char*>(ws);
-  const int E = s + kPartExtra;
   DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
   int32_t* tiles = reinterpret_cast<int32_t*>(base + L.tiles);
   int32_t* tp = reinterpret_cast<int32_t*>(base + L.tp);
   int32_t* ipart = reinterpret_cast<int32_t*>(base + L.ipart);
   double* part = reinterpret_cast<double*>(base + L.part);
+  double* dpart = reinterpret_cast<double*>(base + L.dpart);
   double* red = reinterpret_cast<double*>(base + L.red);
   uint2* skp = reinterpret_cast<uint2*>(base + L.skp);
   Tiling tiling{};
@@ -855,20 +892,12 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   a.l0 = 0;
   a.nwin = nwin;
   a.part = part;
-  a.E = E;
+  a.dpart = dpart;
   a.ctl = ctl;
   SFG_HIP(launch_spmv(kModePlain, false, Gp, a, zeta_blocks(zeta), st));
-  SFG_HIP(launch_reduce_rows(part, Gp, E, red, ctl, false, st));
-  RqArgs r{};
-  r.red = red;
-  r.s = s;
-  r.nwin = nwin;
-  r.inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
-  r.ctl = ctl;
-  r.out_c = c;
-  r.out_dots = dots;
-  r.out_norm2 = norm2;
-  SFG_HIP(launch_rq(kRqReduce, r, st));
+  SFG_HIP(launch_reduce_slots(part, Gp, s, s, 0, 1, 1, 0, 0, red, ctl, false, st));
+  SFG_HIP(launch_sketch_out(red, s, 1.0 / sqrt((double)zeta), dpart, Gp, nwin, c, dots, norm2,
+                            st));
   SFG_HIP(hipStreamSynchronize(st));
   return SFGMRES_OK;
 }

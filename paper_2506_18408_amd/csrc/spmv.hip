@@ -17,8 +17,11 @@
 // tile's column indices and values are requested before the current tile's
 // reduction and epilogue, and the epilogue's own inputs (window vectors,
 // packed sketch) before its LDS reads, so every wave keeps memory requests
-// in flight.  Each workgroup finally writes one row of partial sums; a
-// separate kernel combines the rows in a fixed order.
+// in flight.  Each workgroup finally writes one row of sketch partials and
+// one row of scalar partials; later kernels combine the rows in a fixed
+// order.
+#include <hip/hip_ext.h>
+
 #include "kernels.hpp"
 
 namespace sfg {
@@ -283,9 +286,10 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
     }
   }
 
-  // one row of partial sums per workgroup (fixed slot = blockIdx.x)
-  double* prow = a.part + (int64_t)blockIdx.x * a.E;
+  // one sketch row and one scalar row of partial sums per workgroup (fixed
+  // slot = blockIdx.x)
   if constexpr (kSketch) {
+    double* prow = a.part + (int64_t)blockIdx.x * a.s;
     __syncthreads();
     for (int q = tid; q < a.s; q += kSpmvThreads) {
       double v = lds_sk[q];
@@ -294,95 +298,111 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
       prow[q] = v;
     }
   }
-  const int sb = kSketch ? a.s : 0;
+  double* drow = a.dpart + (int64_t)blockIdx.x * kDP;
   if constexpr (kInnerLike) {
 #pragma unroll
     for (int l = 0; l < NW; ++l) {
       if (l < nwin) {
         const double v = block_sum(dacc[l], scratch);
-        if (tid == 0) prow[sb + l] = v;
+        if (tid == 0) drow[l] = v;
       }
     }
     const double v = block_sum(n2, scratch);
-    if (tid == 0) prow[sb + kMaxT] = v;
+    if (tid == 0) drow[kMaxT] = v;
   } else {
     const double s0 = block_sum(MODE == kModeOuter ? dacc[0] : n2, scratch);
     const double s1 = block_sum(ex, scratch);
     if (tid == 0) {
-      prow[kMaxT] = s0;
-      prow[kMaxT + 1] = s1;
+      drow[kMaxT] = s0;
+      drow[kMaxT + 1] = s1;
     }
   }
 }
 
+struct LaunchCfg {
+  int grid;
+  size_t lds;
+  hipStream_t st;
+  hipEvent_t ev0, ev1;
+};
+
+template <typename VT, int ZB, int MODE, int NW>
+static void launch_one(const LaunchCfg& c, const SpmvArgs& a) {
+  if (c.ev0)
+    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), dim3(kSpmvThreads), c.lds,
+                          c.st, c.ev0, c.ev1, 0, a);
+  else
+    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), dim3(kSpmvThreads), c.lds, c.st,
+                       a);
+}
+
 template <typename VT, int MODE, int NW>
-static void launch_spmv_zb(int zb, int grid, const SpmvArgs& a, hipStream_t st) {
-  const size_t lds = zb > 0 ? (size_t)(kSpmvThreads / kWave) * a.s * sizeof(double) : 0;
+static void launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
+  c.lds = zb > 0 ? (size_t)(kSpmvThreads / kWave) * a.s * sizeof(double) : 0;
   switch (zb) {
     case 0:
-      hipLaunchKernelGGL((k_spmv<VT, 0, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      launch_one<VT, 0, MODE, NW>(c, a);
       break;
     case 1:
-      hipLaunchKernelGGL((k_spmv<VT, 1, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      launch_one<VT, 1, MODE, NW>(c, a);
       break;
     case 2:
-      hipLaunchKernelGGL((k_spmv<VT, 2, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      launch_one<VT, 2, MODE, NW>(c, a);
       break;
     case 3:
-      hipLaunchKernelGGL((k_spmv<VT, 3, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      launch_one<VT, 3, MODE, NW>(c, a);
       break;
     default:
-      hipLaunchKernelGGL((k_spmv<VT, 4, MODE, NW>), dim3(grid), dim3(kSpmvThreads), lds, st, a);
+      launch_one<VT, 4, MODE, NW>(c, a);
       break;
   }
 }
 
 template <typename VT, int MODE>
-static void launch_spmv_nw(int zb, int grid, const SpmvArgs& a, hipStream_t st) {
+static void launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) {
   if (a.nwin <= 0)
-    launch_spmv_zb<VT, MODE, 0>(zb, grid, a, st);
+    launch_spmv_zb<VT, MODE, 0>(zb, c, a);
   else if (a.nwin <= 2)
-    launch_spmv_zb<VT, MODE, 2>(zb, grid, a, st);
+    launch_spmv_zb<VT, MODE, 2>(zb, c, a);
   else if (a.nwin <= 4)
-    launch_spmv_zb<VT, MODE, 4>(zb, grid, a, st);
+    launch_spmv_zb<VT, MODE, 4>(zb, c, a);
   else
-    launch_spmv_zb<VT, MODE, kMaxT>(zb, grid, a, st);
+    launch_spmv_zb<VT, MODE, kMaxT>(zb, c, a);
 }
 
-hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st) {
+hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,
+                       hipEvent_t ev0, hipEvent_t ev1) {
+  const LaunchCfg c{grid, 0, st, ev0, ev1};
   switch (mode) {
     case kModeInner:
       if (fp32)
-        launch_spmv_nw<float, kModeInner>(zb, grid, a, st);
+        launch_spmv_nw<float, kModeInner>(zb, c, a);
       else
-        launch_spmv_nw<double, kModeInner>(zb, grid, a, st);
+        launch_spmv_nw<double, kModeInner>(zb, c, a);
       break;
     case kModePlain:
-      launch_spmv_nw<double, kModePlain>(zb, grid, a, st);
+      launch_spmv_nw<double, kModePlain>(zb, c, a);
       break;
     case kModeOuter:
-      hipLaunchKernelGGL((k_spmv<double, 0, kModeOuter, 1>), dim3(grid), dim3(kSpmvThreads), 0,
-                         st, a);
+      launch_one<double, 0, kModeOuter, 1>(c, a);
       break;
     case kModeResid:
-      hipLaunchKernelGGL((k_spmv<double, 0, kModeResid, 0>), dim3(grid), dim3(kSpmvThreads), 0,
-                         st, a);
+      launch_one<double, 0, kModeResid, 0>(c, a);
       break;
     default:
-      hipLaunchKernelGGL((k_spmv<double, 0, kModeTrueRes, 0>), dim3(grid), dim3(kSpmvThreads), 0,
-                         st, a);
+      launch_one<double, 0, kModeTrueRes, 0>(c, a);
       break;
   }
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- finisher
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv_finish(int mode, const double* part,
-                                                              int32_t G, int32_t E, DevCtl* c,
+__global__ __launch_bounds__(kSpmvThreads) void k_spmv_finish(int mode, const double* dpart,
+                                                              int32_t G, DevCtl* c,
                                                               double* out0, HostStatus* hs) {
   __shared__ double scratch[kSpmvThreads / kWave];
-  const double t0s = block_sum_strided(part + kMaxT, G, E, scratch);
-  const double t1s = block_sum_strided(part + kMaxT + 1, G, E, scratch);
+  const double t0s = block_sum_strided(dpart + kMaxT, G, kDP, scratch);
+  const double t1s = block_sum_strided(dpart + kMaxT + 1, G, kDP, scratch);
   if (threadIdx.x != 0) return;
   if (mode == kModeOuter) {
     out0[0] = t0s;  // h_{1,j}
@@ -399,15 +419,14 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv_finish(int mode, const do
     host_store_f64(&hs->beta, beta);
     host_store_f64(&hs->nb, nb);
     host_store_i32(&hs->error, c->error);
-    __threadfence_system();
   } else {
     out0[0] = t0s;
   }
 }
 
-hipError_t launch_spmv_finish(int mode, const double* part, int32_t G, int32_t E, DevCtl* ctl,
+hipError_t launch_spmv_finish(int mode, const double* dpart, int32_t G, DevCtl* ctl,
                               double* out0, HostStatus* hs, hipStream_t st) {
-  hipLaunchKernelGGL(k_spmv_finish, dim3(1), dim3(kSpmvThreads), 0, st, mode, part, G, E, ctl,
+  hipLaunchKernelGGL(k_spmv_finish, dim3(1), dim3(kSpmvThreads), 0, st, mode, dpart, G, ctl,
                      out0, hs);
   return hipGetLastError();
 }

@@ -42,8 +42,8 @@ hipError_t launch_init_ctl(DevCtl* ctl, int32_t m, int32_t t, int32_t s, double 
 
 // ------------------------------------------------ truncated Arnoldi update
 // u_{i+1} = coef_t y - sum_l coef_l u_l over the window; each workgroup writes its
-// partial ||u_{i+1}||^2 to vpart[blockIdx.x] (summed by the next decision
-// kernel into sigma_{i+1}).
+// partial ||u_{i+1}||^2 to vpart[blockIdx.x] (summed by the next
+// coefficient kernel into sigma_{i+1}).
 template <typename VT>
 __global__ __launch_bounds__(kVecThreads) void k_arnoldi(int64_t n, const VT* __restrict__ W,
                                                          VT* B, int64_t ldb, int32_t l0,
@@ -214,7 +214,6 @@ __global__ __launch_bounds__(kVecThreads) void k_mgs_finish(const double* vpart,
   host_store_f64(&hs->cond, c2 ? ctl->cond_prev : ctl->cond_cur);
   host_store_f64(&hs->rho_hat, c2 ? ctl->rho_prev : ctl->rho_cur);
   host_store_f64(&hs->rhat_true, sqrt(ctl->rhat2));
-  __threadfence_system();
 }
 
 hipError_t launch_mgs_finish(const double* vpart, int32_t G, double* hout, DevCtl* ctl, int last,
@@ -233,8 +232,7 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
                                                         double* __restrict__ Vout,
                                                         VT* __restrict__ Bout,
                                                         const uint2* __restrict__ skp,
-                                                        int32_t s, double* __restrict__ part,
-                                                        int32_t E) {
+                                                        int32_t s, double* __restrict__ part) {
   extern __shared__ double lds_sk[];  // per-wave copies of the s accumulators
   constexpr int kWaves = kVecThreads / kWave;
   const int tid = threadIdx.x;
@@ -257,7 +255,7 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
     sketch_scatter_packed<ZB>(wave_sk, skp, r, v);
   }
   __syncthreads();
-  double* prow = part + (int64_t)blockIdx.x * E;
+  double* prow = part + (int64_t)blockIdx.x * s;
   for (int q = tid; q < s; q += kVecThreads) {
     double acc = lds_sk[q];
 #pragma unroll
@@ -269,38 +267,37 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
 template <typename VT>
 static void launch_normsk_t(int zb, int grid, size_t lds, hipStream_t st, int64_t n,
                             const double* W, const double* hptr, double* Vout, VT* Bout,
-                            const uint2* skp, int32_t s, double* part, int32_t E) {
+                            const uint2* skp, int32_t s, double* part) {
   switch (zb) {
     case 1:
       hipLaunchKernelGGL((k_normsk<VT, 1>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part, E);
+                         Vout, Bout, skp, s, part);
       break;
     case 2:
       hipLaunchKernelGGL((k_normsk<VT, 2>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part, E);
+                         Vout, Bout, skp, s, part);
       break;
     case 3:
       hipLaunchKernelGGL((k_normsk<VT, 3>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part, E);
+                         Vout, Bout, skp, s, part);
       break;
     default:
       hipLaunchKernelGGL((k_normsk<VT, 4>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part, E);
+                         Vout, Bout, skp, s, part);
       break;
   }
 }
 
 hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double* W,
                                    const double* hptr, double* Vout, void* Bout, int32_t s,
-                                   const uint2* skp, int zb, double* part, int32_t E,
-                                   hipStream_t st) {
+                                   const uint2* skp, int zb, double* part, hipStream_t st) {
   const size_t lds = (size_t)(kVecThreads / kWave) * s * sizeof(double);
   if (fp32)
     launch_normsk_t<float>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<float*>(Bout), skp,
-                           s, part, E);
+                           s, part);
   else
     launch_normsk_t<double>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<double*>(Bout), skp,
-                            s, part, E);
+                            s, part);
   return hipGetLastError();
 }
 

@@ -302,6 +302,81 @@ def test_full_size_c2_first_step_and_properties():
     assert ru.inner_k[0] == int(info["inner_k"][0])
 
 
+@pytest.mark.parametrize("name", ["c1", "convdiff3d_24", "powerlaw_20k_forced12",
+                                  "cw_sketch_t0_forced8"])
+def test_panel_width_changes_rounding_only(name):
+    """The decision kernel appends `panel` columns per launch and decides after
+    every column: the chosen dimensions are the same for every panel width and
+    host lookahead, the outputs agree to rounding, and each run matches the
+    oracle replay of its dimensions."""
+    A, b, prm = _case(name)
+    fk = [prm["forced"]] * prm["max_outer"] if "forced" in prm else None
+    runs = {}
+    for panel, la in [(1, 1), (3, 0), (5, 7), (8, 0), (8, 64)]:
+        with warnings.catch_warnings():
+            warnings.simplefilter("ignore")
+            runs[(panel, la)] = _gpu(A, b, prm, forced_k=fk, panel=panel, lookahead=la)
+    x1, i1 = runs[(1, 1)]
+    rf = _oracle(A, b, prm, forced_k=list(i1["inner_k"]))
+    for key, (x, info) in runs.items():
+        assert list(info["inner_k"]) == list(i1["inner_k"]), key
+        assert info["stop_reason"] == i1["stop_reason"], key
+        hist_close(info["residual_history"], np.asarray(rf.residual_history))
+        hist_close(info["true_residual_history"], rf.true_residual_history, rtol=1e-9,
+                   atol=1e-13)
+        xs = x.cpu().numpy()
+        assert np.linalg.norm(xs - rf.x) <= 1e-9 * np.linalg.norm(rf.x), key
+
+
+@pytest.mark.parametrize("panel", [1, 8])
+def test_exact_truncated_arnoldi_breakdown(panel):
+    """A = 2 I, b = e_1: A v_1 = 2 v_1 exactly, so u_2 = 0 and the inner
+    cycle ends at k = 1 by breakdown (Section 4.1's recurrence; the oracle's
+    sketch seeds chosen where its sketched residual is a rounding residue,
+    so C3 with tol = 1e-300 does not fire first).  An invariant Krylov space
+    also makes the sketched residual zero in exact arithmetic, so C3 at the
+    same k is the other correct outcome if the device's rounding gives an
+    exact zero."""
+    n = 50
+    A = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+              np.full(n, 2.0))
+    b = np.zeros(n)
+    b[0] = 1.0
+    for seed in (2, 3):
+        prm = dict(m=5, t=2, s=20, zeta=8, tol=1e-300, seed=seed, max_outer=3)
+        ref = _oracle(A, b, prm)
+        assert ref.inner_k == [1] and ref.stop_reason == ["breakdown"]
+        x, info = _gpu(A, b, prm, panel=panel)
+        assert list(info["inner_k"]) == [1]
+        assert info["stop_reason"][0] in ("breakdown", "C3")
+        assert info["converged"]
+        assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-12
+
+
+@pytest.mark.parametrize("stride", [1, 4])
+def test_profile_counts_working_launches(stride):
+    """profile = N times the fused kernel of inner steps N-1, 2N-1, ... that
+    ran: every step up to the end of the panel holding the stopping column."""
+    A, b, prm = _case("c1")
+    x, info = _gpu(A, b, prm, profile=stride)
+    m, panel = prm["m"], 8
+    want = 0
+    for k, r in zip(info["inner_k"], info["stop_reason"]):
+        decided = int(k) + (1 if r == "C2" else 0)
+        steps = min(m, -(-decided // panel) * panel)
+        want += len(range(stride - 1, steps, stride))
+    assert info["spmv_launches"] == want
+    assert info["spmv_ms"] > 0.0
+
+
+def test_invalid_panel_and_lookahead():
+    A, b, prm = _case("c1")
+    for bad in [dict(panel=9), dict(panel=-1), dict(lookahead=65), dict(lookahead=-1)]:
+        with pytest.raises(P.SFGMRESError) as e:
+            _gpu(A, b, dict(prm, **bad))
+        assert e.value.code == L.ERR_INVALID
+
+
 # ---------------------------------------------------------------- edge cases
 def test_zero_rhs_returns_zero():
     A, b, prm = _case("c1")
