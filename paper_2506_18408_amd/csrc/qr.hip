@@ -199,40 +199,10 @@ constexpr int kQrThreads = 1024;
 static_assert(kQrThreads >= kMaxS && kQrThreads >= kMaxM, "one row per thread");
 constexpr int kQrWaves = kQrThreads / kWave;
 constexpr int kRB = 32;  // reduction entries per wave (>= kPanel (kPanel - 1) / 2)
-constexpr int kRHalf = kQrWaves * kRB + kRB;  // wave partials, then the totals
 
 size_t qr_block_lds_bytes(int32_t s, int32_t m) {
-  return sizeof(double) * ((size_t)kPanel * s + 2 * (size_t)m * kPanel + 2 * (size_t)kRHalf);
-}
-
-// Sums of NV values over the workgroup, every thread getting the NV sums:
-// wave sums, then thread i < NV adds the wave partials of entry i in wave
-// order, then every thread reads the NV totals (two barriers, NV reads per
-// thread).  Callers alternate between two buffers: a thread writes buffer b
-// only after passing the barriers of the call that used the other buffer,
-// which every thread reaches only after reading buffer b the time before.
-template <int NV>
-__device__ __forceinline__ void qr_sum(double (&v)[NV], double* rbuf, int& par) {
-  double* buf = rbuf + par * kRHalf;
-  double* tot = buf + kQrWaves * kRB;
-  par ^= 1;
-  const int lane = threadIdx.x & (kWave - 1);
-  const int wid = threadIdx.x / kWave;
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
-  if (lane == 0)
-#pragma unroll
-    for (int i = 0; i < NV; ++i) buf[wid * NV + i] = v[i];
-  __syncthreads();
-  if (threadIdx.x < NV) {
-    double r = 0.0;
-#pragma unroll
-    for (int w = 0; w < kQrWaves; ++w) r += buf[w * NV + threadIdx.x];
-    tot[threadIdx.x] = r;
-  }
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < NV; ++i) v[i] = tot[i];
+  return sizeof(double) * ((size_t)kPanel * s + s + 2 * (size_t)m + 2 * (size_t)m * kPanel +
+                           (size_t)kQrWaves * kRB);
 }
 
 // Householder reflector for a column whose entry at the pivot row is alpha
@@ -299,17 +269,28 @@ __device__ __forceinline__ void vt_panel(const double* __restrict__ V, int s, in
   }
 }
 
+// Shared scalars of the decision kernel: written by wave 0 at the end of
+// the panel, read by every thread after the following barrier.
+struct QrShared {
+  double tau[kPanel];
+  double beta[kPanel];
+  double wm[kPanel][kPanel];  // wm[x][y] = v_{k0+x}^T v_{k0+y}, x < y
+  int stopped, done;
+};
+
 __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
   extern __shared__ double lds[];
-  __shared__ double Wm[kPanel][kPanel];  // Wm[x][y] = v_{k0+x}^T v_{k0+y}, x < y
-  __shared__ double tau_sh[kPanel];
+  __shared__ QrShared sh;
   const int s = a.s;
   const int m = a.m;
-  // LDS: panel (kPanel columns of s, column-major; thread q only ever
-  // touches row q of it outside the V^T products), AU and BX (m x kPanel,
-  // row l at l * kPanel), two reduction buffers
+  // LDS: panel (kPanel columns of s, column-major), d (s), the condition
+  // estimate vectors x and z (m each), AU and BX (m x kPanel, row l at
+  // l * kPanel), two reduction buffers
   double* Cp = lds;
-  double* AU = Cp + (size_t)kPanel * s;
+  double* dv = Cp + (size_t)kPanel * s;
+  double* xv = dv + s;
+  double* zv = xv + m;
+  double* AU = zv + m;
   double* BX = AU + (size_t)m * kPanel;
   double* rbuf = BX + (size_t)m * kPanel;
 
@@ -323,7 +304,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
   const double* __restrict__ T = a.T;
   const bool row = q < s;
 
-  // ---- every input at once: panel rows, d, estimate vectors, cycle state --
+  // ---- every input at once: panel rows, d, estimate vectors --------------
 #pragma unroll
   for (int j = 0; j < kPanel; ++j) {
     const int col = k0 + j;
@@ -334,22 +315,13 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
     }
     if (row) Cp[j * s + q] = v;
   }
-  double dq = row ? a.d[q] : 0.0;
-  double xq = q < k0 ? a.ice_x[q] : 0.0;
-  double zq = q < k0 ? a.ice_z[q] : 0.0;
-  const int stop_in = ctl->stop_k;
-  const int brk_step = ctl->brk_step;
-  const int forced_k = ctl->forced_k;
-  const double cond_thr = ctl->cond_threshold;
-  const double factor = ctl->factor;
-  const double tol_abs = ctl->tol_abs;
-  double smax = ctl->ice_smax, znorm = ctl->ice_znorm;
-  double cond_cur = ctl->cond_cur, cond_prev = ctl->cond_prev;
-  double rho_cur = ctl->rho_cur, rho_prev = ctl->rho_prev;
-  int err = ctl->error;
-  if (stop_in != 0) return;
+  if (row) dv[q] = a.d[q];
+  if (q < k0) {
+    xv[q] = a.ice_x[q];
+    zv[q] = a.ice_z[q];
+  }
+  if (ctl->stop_k != 0) return;
   __syncthreads();
-  int par = 0;
 
   if (k0 > 0) {
     // A = V^T C, then B = T^T A (a wave per pair of columns of T, lanes over
@@ -404,151 +376,210 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
 #pragma unroll
       for (int j = 0; j < kPanel; ++j) Cp[j * s + q] -= acc[j];
     }
+    __syncthreads();
   }
 
-  // ---- the panel, column by column --------------------------------------
-  // column kk = k0 + j: reflector on rows >= kk; d and the later panel
+  // ---- the panel, column by column, in wave 0 ---------------------------
+  // Column kk = k0 + j: reflector on rows >= kk; d and the later panel
   // columns updated; ||d[kk+1:]|| (C3); Bischof's incremental estimate with
-  // the new column [R(0:kk, kk); beta] (C2); the decision.  The scalars are
-  // computed identically by every thread from the reduced sums.
-  double beta, tau, den;
-  {
-    const double c0 = row ? Cp[q] : 0.0;
-    double r2[2] = {(q > k0 && row) ? c0 * c0 : 0.0, q == k0 ? c0 : 0.0};
-    qr_sum<2>(r2, rbuf, par);
-    reflector(r2[1], r2[0], beta, tau, den);
-  }
-  double my_beta = 0.0, my_tau = 0.0;  // of the column whose pivot row is q
-  int stop_k = 0, stop_step = 0, stop_reason = 0, qr_k = k0;
-  bool stopped = false;
-  int done = k0;
-#pragma unroll 1
-  for (int j = 0; j < p; ++j) {
-    const int kk = k0 + j;
-    if (brk_step == kk) {
-      // this column's Arnoldi vector is zero: keep the kk columns before it
-      stop_k = kk;
-      stop_step = kk;
-      stop_reason = SFGMRES_STOP_BREAKDOWN;
-      stopped = true;
-      break;
+  // the new column [R(0:kk, kk); beta] (C2); the decision.  One wave, lane L
+  // owning rows L, L + 64, ...: every sum is a wave reduction and no barrier
+  // is needed; the other waves wait at the barrier after the panel.
+  if (wid == 0) {
+    const int forced_k = ctl->forced_k;
+    const int brk_step = ctl->brk_step;
+    const double cond_thr = ctl->cond_threshold;
+    const double factor = ctl->factor;
+    const double tol_abs = ctl->tol_abs;
+    double smax = ctl->ice_smax, znorm = ctl->ice_znorm;
+    double cond_cur = ctl->cond_cur, cond_prev = ctl->cond_prev;
+    double rho_cur = ctl->rho_cur, rho_prev = ctl->rho_prev;
+    int err = ctl->error;
+    double beta, tau, den;
+    {
+      double x2 = 0.0, al = 0.0;
+      for (int r = lane; r < s; r += kWave) {
+        const double c0 = Cp[r];
+        if (r > k0) x2 += c0 * c0;
+        if (r == k0) al = c0;
+      }
+      reflector(wave_sum(al), wave_sum(x2), beta, tau, den);
     }
-    if (q == kk) {
-      my_beta = beta;
-      my_tau = tau;
-    }
-    if (q == 0) tau_sh[j] = tau;
-    // the reflector vector replaces rows >= kk of column j (rows < kk hold
-    // R's new column)
-    double cj = row ? Cp[j * s + q] : 0.0;
-    if (q == kk)
-      cj = 1.0;
-    else if (q > kk && row)
-      cj = den != 0.0 ? cj / den : 0.0;
-    if (row) Cp[j * s + q] = cj;
-    double cl[kPanel];
+    int stop_k = 0, stop_step = 0, stop_reason = 0, qr_k = k0;
+    int stopped = 0;
+    int done = k0;
+    for (int j = 0; j < p; ++j) {
+      const int kk = k0 + j;
+      if (brk_step == kk) {
+        // this column's Arnoldi vector is zero: keep the kk columns before it
+        stop_k = kk;
+        stop_step = kk;
+        stop_reason = SFGMRES_STOP_BREAKDOWN;
+        stopped = 1;
+        break;
+      }
+      sh.tau[j] = tau;
+      sh.beta[j] = beta;
+      // v^T d, v^T C[:, j'] (j' > j) and the estimate's x^T r, z^T r with
+      // r = R's new column (rows < kk of column j); v = 1 at the pivot and
+      // c / den below it.  Read-only, so the loads of successive rows overlap.
+      double* cj = Cp + j * s;
+      const double inv = den != 0.0 ? 1.0 / den : 0.0;
+      double red[kPanel + 3];
 #pragma unroll
-    for (int jj = 0; jj < kPanel; ++jj) cl[jj] = (row && jj > j) ? Cp[jj * s + q] : 0.0;
-    double red[kPanel + 3];
+      for (int i = 0; i < kPanel + 3; ++i) red[i] = 0.0;
+      // (branch-free: every load is issued, the unused products are masked)
+#pragma unroll 2
+      for (int r = lane; r < s; r += kWave) {
+        const double c = cj[r];
+        const double dr = dv[r];
+        const int ri = r < kk ? r : 0;  // (x and z hold m entries)
+        const double xr = r < kk ? xv[ri] : 0.0;
+        const double zr = r < kk ? zv[ri] : 0.0;
+        double cc[kPanel];
 #pragma unroll
-    for (int i = 0; i < kPanel + 3; ++i) red[i] = 0.0;
-    if (q >= kk && row) {
-      red[0] = cj * dq;
+        for (int jj = 0; jj < kPanel; ++jj) cc[jj] = Cp[jj * s + r];
+        const double v = r < kk ? 0.0 : (r == kk ? 1.0 : c * inv);
+        const double rc = r < kk ? c : 0.0;
+        red[0] += v * dr;
 #pragma unroll
-      for (int jj = 0; jj < kPanel; ++jj) red[1 + jj] = cj * cl[jj];
-    }
-    if (q < kk) {
-      red[kPanel + 1] = xq * cj;
-      red[kPanel + 2] = zq * cj;
-    }
-    qr_sum<kPanel + 3>(red, rbuf, par);
-    double cn = 0.0;  // row q of the next column after this reflector
-    if (q >= kk && row) {
-      const double tv = tau * cj;
-      dq -= tv * red[0];
+        for (int jj = 0; jj < kPanel; ++jj) red[1 + jj] += v * cc[jj];
+        red[kPanel + 1] += xr * rc;
+        red[kPanel + 2] += zr * rc;
+      }
 #pragma unroll
-      for (int jj = 0; jj < kPanel; ++jj) {
-        if (jj > j) {
-          const double nv = cl[jj] - tv * red[1 + jj];
-          Cp[jj * s + q] = nv;
-          if (jj == j + 1) cn = nv;
+      for (int i = 0; i < kPanel + 3; ++i)
+        if (i == 0 || i > j + 1) red[i] = wave_sum(red[i]);  // (1..j+1 unused)
+      // the reflector replaces rows >= kk of column j (rows < kk hold R's
+      // new column); d <- H d, C[:, j'] <- H C[:, j'] for j' > j; ||d[kk+1:]||^2
+      // and the next column's squared tail and pivot.  Branch-free: columns
+      // jj < j keep their values (rm = 0), column j becomes the reflector,
+      // every column of the row is stored.
+      double rm[kPanel];
+#pragma unroll
+      for (int jj = 0; jj < kPanel; ++jj) rm[jj] = jj > j ? red[1 + jj] : 0.0;
+      double r3[3] = {0.0, 0.0, 0.0};
+      const int rs = kk + ((lane - kk) % kWave + kWave) % kWave;  // first row >= kk of this lane
+      for (int r = rs; r < s; r += kWave) {
+        double x[kPanel];
+#pragma unroll
+        for (int jj = 0; jj < kPanel; ++jj) x[jj] = Cp[jj * s + r];
+        const double dr = dv[r];
+        double v = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kPanel; ++jj)
+          if (jj == j) v = r == kk ? 1.0 : x[jj] * inv;
+        const double tv = tau * v;
+        const double dn = dr - tv * red[0];
+        double nn = 0.0;
+#pragma unroll
+        for (int jj = 0; jj < kPanel; ++jj) {
+          x[jj] = jj == j ? v : x[jj] - tv * rm[jj];
+          if (jj == j + 1) nn = x[jj];
+        }
+        dv[r] = dn;
+#pragma unroll
+        for (int jj = 0; jj < kPanel; ++jj) Cp[jj * s + r] = x[jj];
+        if (r > kk) r3[0] += dn * dn;
+        if (r > kk + 1) r3[1] += nn * nn;
+        if (r == kk + 1) r3[2] = nn;
+      }
+#pragma unroll
+      for (int i = 0; i < 3; ++i) r3[i] = wave_sum(r3[i]);
+      const double rho_hat = sqrt(r3[0]);
+      const double ax = red[kPanel + 1], bz = red[kPanel + 2];
+      const double gam = beta;
+      double kappa;
+      if (gam == 0.0 || smax < 0.0) {
+        smax = -1.0;  // singular from here on
+        kappa = INFINITY;
+      } else if (kk == 0) {
+        smax = fabs(gam);
+        znorm = 1.0 / fabs(gam);
+        kappa = smax * znorm;
+        if (lane == 0) {
+          xv[0] = 1.0;
+          zv[0] = 1.0 / gam;
+        }
+      } else {
+        double lam, s1, c1, s2, c2;
+        top_eig2(smax * smax + ax * ax, ax * gam, gam * gam, lam, s1, c1);
+        smax = sqrt(lam);
+        const double g2 = gam * gam;
+        top_eig2(znorm * znorm + bz * bz / g2, -bz / g2, 1.0 / g2, lam, s2, c2);
+        znorm = sqrt(lam);
+        kappa = smax * znorm;
+        for (int r = lane; r < kk; r += kWave) {
+          xv[r] *= s1;
+          zv[r] *= s2;
+        }
+        if (lane == 0) {
+          xv[kk] = c1;
+          zv[kk] = (c2 - s2 * bz) / gam;
         }
       }
-    } else if (j + 1 < kPanel && row) {
-      cn = Cp[(j + 1) * s + q];
-    }
-    // ||d[kk+1:]||^2 and the next column's squared tail and pivot
-    double r3[3] = {(q > kk && row) ? dq * dq : 0.0, (q > kk + 1 && row) ? cn * cn : 0.0,
-                    q == kk + 1 ? cn : 0.0};
-    qr_sum<3>(r3, rbuf, par);
-    const double rho_hat = sqrt(r3[0]);
-    const double ax = red[kPanel + 1], bz = red[kPanel + 2];
-    const double gam = beta;
-    double kappa;
-    if (gam == 0.0 || smax < 0.0) {
-      smax = -1.0;  // singular from here on
-      kappa = INFINITY;
-    } else if (kk == 0) {
-      smax = fabs(gam);
-      znorm = 1.0 / fabs(gam);
-      kappa = smax * znorm;
-      if (q == 0) {
-        xq = 1.0;
-        zq = 1.0 / gam;
+      const int ncols = kk + 1;
+      qr_k = ncols;
+      cond_prev = cond_cur;
+      rho_prev = rho_cur;
+      cond_cur = kappa;
+      rho_cur = rho_hat;
+      int stop = 0, reason = 0;
+      if (ncols == 1 && beta == 0.0) {
+        err = SFGMRES_ERR_BREAKDOWN;
+        stop = 1;
+        reason = SFGMRES_STOP_BREAKDOWN;
+      } else if (forced_k > 0) {
+        if (ncols >= forced_k) {
+          stop = forced_k;
+          reason = SFGMRES_STOP_FORCED;
+        }
+      } else if (ncols > 1 && kappa > cond_thr) {
+        stop = ncols - 1;
+        reason = SFGMRES_STOP_C2;
+      } else if (factor * rho_hat <= tol_abs) {
+        stop = ncols;
+        reason = SFGMRES_STOP_C3;
+      } else if (ncols >= m) {
+        stop = m;
+        reason = SFGMRES_STOP_C1;
       }
-    } else {
-      double lam, s1, c1, s2, c2;
-      top_eig2(smax * smax + ax * ax, ax * gam, gam * gam, lam, s1, c1);
-      smax = sqrt(lam);
-      const double g2 = gam * gam;
-      top_eig2(znorm * znorm + bz * bz / g2, -bz / g2, 1.0 / g2, lam, s2, c2);
-      znorm = sqrt(lam);
-      kappa = smax * znorm;
-      if (q < kk) {
-        xq *= s1;
-        zq *= s2;
-      } else if (q == kk) {
-        xq = c1;
-        zq = (c2 - s2 * bz) / gam;
+      if (!isfinite(rho_hat) && err == 0) err = SFGMRES_ERR_NONFINITE;
+      done = ncols;
+      if (stop) {
+        stop_k = stop;
+        stop_step = ncols;
+        stop_reason = reason;
+        stopped = 1;
+        break;
       }
+      reflector(r3[2], r3[1], beta, tau, den);
     }
-    const int ncols = kk + 1;
-    qr_k = ncols;
-    cond_prev = cond_cur;
-    rho_prev = rho_cur;
-    cond_cur = kappa;
-    rho_cur = rho_hat;
-    int stop = 0, reason = 0;
-    if (ncols == 1 && beta == 0.0) {
-      err = SFGMRES_ERR_BREAKDOWN;
-      stop = 1;
-      reason = SFGMRES_STOP_BREAKDOWN;
-    } else if (forced_k > 0) {
-      if (ncols >= forced_k) {
-        stop = forced_k;
-        reason = SFGMRES_STOP_FORCED;
-      }
-    } else if (ncols > 1 && kappa > cond_thr) {
-      stop = ncols - 1;
-      reason = SFGMRES_STOP_C2;
-    } else if (factor * rho_hat <= tol_abs) {
-      stop = ncols;
-      reason = SFGMRES_STOP_C3;
-    } else if (ncols >= m) {
-      stop = m;
-      reason = SFGMRES_STOP_C1;
+    if (lane == 0) {
+      sh.stopped = stopped;
+      sh.done = done;
+      ctl->stop_k = stop_k;
+      ctl->stop_step = stop_step;
+      ctl->stop_reason = stop_reason;
+      ctl->qr_k = qr_k;
+      ctl->error = err;
+      ctl->ice_smax = smax;
+      ctl->ice_znorm = znorm;
+      ctl->cond_cur = cond_cur;
+      ctl->cond_prev = cond_prev;
+      ctl->rho_cur = rho_cur;
+      ctl->rho_prev = rho_prev;
+      host_store_i32(&a.hs->stop_k, stop_k);
+      host_store_i32(&a.hs->stop_step, stop_step);
+      host_store_i32(&a.hs->stop_reason, stop_reason);
+      host_store_i32(&a.hs->error, err);
+      host_store_i32(&a.hs->steps_run, k0 + p);
+      host_store_i32(&a.hs->inner_step_done, done);
     }
-    if (!isfinite(rho_hat) && err == 0) err = SFGMRES_ERR_NONFINITE;
-    done = ncols;
-    if (stop) {
-      stop_k = stop;
-      stop_step = ncols;
-      stop_reason = reason;
-      stopped = true;
-      break;
-    }
-    reflector(r3[2], r3[1], beta, tau, den);
   }
+  __syncthreads();
+  const bool stopped = sh.stopped != 0;
+  const int done = sh.done;
   const int ndone = done - k0;  // columns whose reflector was formed
 
   // ---- T extended by the p new reflectors (only if the cycle goes on) ----
@@ -558,15 +589,13 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
 #pragma unroll
   for (int j = 0; j < kPanel; ++j) tn[j] = 0.0;
   if (!stopped) {
-    __syncthreads();  // the panel rows are read across threads below
     // U = V_old^T V_new (rows >= k0; the new vectors vanish above their unit)
     vt_panel(V, s, k0, k0, Cp, true, AU);
     {
       // wave sums of the products, column y of Wm at a time, into the
       // reduction buffer (entry y (y - 1) / 2 + x), then one thread per entry
       // sums the waves in wave order
-      double* buf = rbuf + par * kRHalf;
-      par ^= 1;
+      double* buf = rbuf;
 #pragma unroll
       for (int y = 1; y < kPanel; ++y) {
         const double cy = (q >= k0 + y && row) ? Cp[y * s + q] : 0.0;
@@ -583,7 +612,7 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
         const int x = q - y * (y - 1) / 2;
         double r = 0.0;
         for (int w = 0; w < kQrWaves; ++w) r += buf[w * kRB + q];
-        Wm[x][y] = r;
+        sh.wm[x][y] = r;
       }
     }
     __syncthreads();
@@ -616,10 +645,10 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
         double acc = xr[j];
 #pragma unroll
         for (int jj = 0; jj < j; ++jj)
-          if (q <= k0 + jj) acc += tn[jj] * Wm[jj][j];
-        tn[j] = -tau_sh[j] * acc;
+          if (q <= k0 + jj) acc += tn[jj] * sh.wm[jj][j];
+        tn[j] = -sh.tau[j] * acc;
       } else if (q == kk) {
-        tn[j] = tau_sh[j];
+        tn[j] = sh.tau[j];
       }
     }
   }
@@ -632,37 +661,18 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
     if (q < kk) a.R[(int64_t)kk * m + q] = cj;
   }
   if (q >= k0 && q < done) {
-    a.R[(int64_t)q * m + q] = my_beta;
-    a.tau[q] = my_tau;
+    a.R[(int64_t)q * m + q] = sh.beta[q - k0];
+    a.tau[q] = sh.tau[q - k0];
   }
   if (!stopped) {
 #pragma unroll
     for (int j = 0; j < kPanel; ++j)
       if (j < p && q <= k0 + j) a.T[(int64_t)(k0 + j) * m + q] = tn[j];
   }
-  if (row) a.d[q] = dq;
+  if (row) a.d[q] = dv[q];
   if (q < done) {
-    a.ice_x[q] = xq;
-    a.ice_z[q] = zq;
-  }
-  if (q == 0) {
-    ctl->stop_k = stop_k;
-    ctl->stop_step = stop_step;
-    ctl->stop_reason = stop_reason;
-    ctl->qr_k = qr_k;
-    ctl->error = err;
-    ctl->ice_smax = smax;
-    ctl->ice_znorm = znorm;
-    ctl->cond_cur = cond_cur;
-    ctl->cond_prev = cond_prev;
-    ctl->rho_cur = rho_cur;
-    ctl->rho_prev = rho_prev;
-    host_store_i32(&a.hs->stop_k, stop_k);
-    host_store_i32(&a.hs->stop_step, stop_step);
-    host_store_i32(&a.hs->stop_reason, stop_reason);
-    host_store_i32(&a.hs->error, err);
-    host_store_i32(&a.hs->steps_run, k0 + p);
-    host_store_i32(&a.hs->inner_step_done, done);
+    a.ice_x[q] = xv[q];
+    a.ice_z[q] = zv[q];
   }
 }
 
