@@ -16,9 +16,10 @@ sketch accumulation, QR, outer loop) is timed after it and reported with its
 speedup and its solution error against the FP64 solution.
 
 Output: one JSON line (rank 0).  ``roofline`` is for the fused inner
-SpMV+sketch kernel: algorithmic bytes per launch, 12 nnz + 20 n + 8 n nwin
-(values and column indices, row pointers, the input vector, the output
-vector, and the nwin Arnoldi window vectors its fused dot products read),
+SpMV+sketch kernel: algorithmic bytes per launch,
+12 nnz + 20 n + 8 n nwin + 8 ceil(zeta/4) n (values and column indices, row
+pointers, the input vector, the output vector, the nwin Arnoldi window
+vectors its fused dot products read, and the packed sketch columns),
 divided by the kernel's mean duration measured with HIP events on the
 library's stream over the timed solves (every 8th inner step's launch, the
 events being recorded by the launch itself at the kernel's start and end).  ``cpu_baseline`` times the CPU
@@ -159,7 +160,8 @@ def main():
     if wl != launches:
         raise RuntimeError(f"launch count mismatch {wl} vs {launches}")
     avg_s = spmv_ms * 1e-3 / launches
-    bytes_per_launch = 12 * A.nnz + 20 * A.n + 8 * A.n * (win / launches)
+    zb = (zeta + 3) // 4
+    bytes_per_launch = 12 * A.nnz + 20 * A.n + 8 * A.n * (win / launches) + 8 * zb * A.n
     achieved = bytes_per_launch / avg_s / 1e9
     log(f"fused spmv+sketch: {launches} launches, mean {avg_s * 1e6:.2f} us, "
         f"{bytes_per_launch / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
@@ -207,7 +209,7 @@ def main():
         ml = sum(i["spmv_launches"] for i in ims)
         mms = sum(i["spmv_ms"] for i in ims)
         mwin = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in ims)
-        mbytes = 8 * A.nnz + 12 * A.n + 4 * A.n * (mwin / ml)
+        mbytes = 8 * A.nnz + 12 * A.n + 4 * A.n * (mwin / ml) + 8 * zb * A.n
         mavg = mms * 1e-3 / ml
         result["mixed"] = {
             "time_to_tol_s": msec, "speedup_vs_fp64": sec / msec,

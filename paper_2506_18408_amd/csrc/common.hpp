@@ -24,16 +24,21 @@ constexpr int kMaxZeta = SFGMRES_MAX_ZETA;
 constexpr int kMaxS = SFGMRES_MAX_S;
 constexpr int kMaxM = SFGMRES_MAX_M;
 
-// Fused SpMV: threads per workgroup, nonzeros staged per tile (registers,
-// then LDS), the tiling (256-row tiles when every row has at most
-// kShortRow nonzeros, else tiles of kTileNnz nonzeros, which with rows of at
-// most kStage - kTileNnz + 1 nonzeros always fit the stage) and the
-// persistent-grid cap (4 workgroups per CU).
-constexpr int kSpmvThreads = 256;
-constexpr int kStage = 2048;
-constexpr int kShortRow = kStage / kSpmvThreads;
-constexpr int kRowTile = kSpmvThreads;
-constexpr int kTileNnz = 1024;
+// Fused SpMV: a persistent grid of at most kSpmvGrid workgroups (one per
+// CU) of up to kSpmvMaxWaves waves; every wave walks its own range of tiles
+// with no workgroup barrier.  A tile holds at most kWStage nonzeros: kRowTile
+// rows (one per lane) when every row has at most kShortRow nonzeros, else
+// about kTileNnz nonzeros, which with rows of at most kWStage - kTileNnz + 1
+// nonzeros always fit the stage (longer rows take a slower per-row path).
+constexpr int kSpmvMaxWaves = 16;
+constexpr int kSpmvMaxThreads = kSpmvMaxWaves * 64;
+constexpr int kSpmvGrid = 256;
+constexpr int kWStage = 512;
+constexpr int kShortRow = 8;
+constexpr int kRowTile = kWStage / kShortRow;
+constexpr int kTileNnz = kWStage / 2;
+constexpr int kSpmvLdsMax = 150 * 1024;  // dynamic LDS of one SpMV workgroup (bytes)
+// Bound on the number of partial rows any multi-workgroup kernel writes.
 constexpr int kMaxGrid = 1024;
 // Vector kernels: threads per workgroup and grid cap (one partial per
 // workgroup in the vector partial buffer).

@@ -50,6 +50,8 @@ hipError_t launch_tiles(const int32_t* row_ptr, int64_t n, int32_t wt, int32_t r
                         int32_t* tiles, int32_t* tp, int32_t ntiles, hipStream_t st);
 hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, int32_t* out,
                              hipStream_t st);
+// Waves per SpMV workgroup for an s-row sketch (0: none), bounded by LDS.
+int spmv_waves(int s);
 // ev0/ev1 non-null: the launch records them at the kernel's own start and
 // end (timing of the kernel alone).
 hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,

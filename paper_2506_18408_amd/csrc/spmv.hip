@@ -5,21 +5,21 @@
 // first Gram-Schmidt dot; the initial residual b - A x0; a true residual),
 // and the generation of the packed sketch.
 //
-// Design (gfx950): a persistent grid of 256-thread workgroups walks row
-// tiles (256 rows each when every row has at most 8 nonzeros, else tiles of
-// about 1024 nonzeros); each XCD gets a contiguous range of tiles.  A tile's
-// nonzeros (at most kStage) are loaded with coalesced loads into registers,
-// multiplied by the gathered x[col] and staged in LDS; groups of 1..64 lanes
-// then reduce one row each from LDS, and the row leader runs the epilogue:
-// store, scatter +-y_r into its wave's LDS sketch accumulators (the zeta rows
-// and signs of column r of S come from the packed sketch) and accumulate the
-// dot products in registers.  The loop is software-pipelined: the next
-// tile's column indices and values are requested before the current tile's
-// reduction and epilogue, and the epilogue's own inputs (window vectors,
-// packed sketch) before its LDS reads, so every wave keeps memory requests
-// in flight.  Each workgroup finally writes one row of sketch partials and
-// one row of scalar partials; later kernels combine the rows in a fixed
-// order.
+// Design (gfx950): a persistent grid of one workgroup per CU, of 16 waves
+// (8 when the sketch is large); every wave walks its own contiguous range of
+// tiles without any workgroup barrier, so the waves of a CU keep independent
+// streams of memory requests in flight.  A tile (64 rows, one per lane, when
+// every row has at most 8 nonzeros; else about 256 nonzeros) has its column
+// indices and values loaded with coalesced loads one tile ahead, its x
+// entries gathered, the products staged in the wave's own LDS region, and
+// its rows reduced from LDS by groups of 1..64 lanes; the row leader then
+// runs the epilogue: store, scatter +-y_r into the wave's own LDS sketch
+// accumulators (the zeta rows and signs of column r of S come from the
+// packed sketch) and accumulate the dot products in registers.  The
+// epilogue's inputs are requested together with the gathers.  At the end
+// the workgroup adds its wave copies in wave order and writes one row of
+// sketch partials and one row of scalar partials; later kernels combine the
+// rows in a fixed order.
 #include <hip/hip_ext.h>
 
 #include "kernels.hpp"
@@ -107,23 +107,40 @@ hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, i
   return hipGetLastError();
 }
 
+// Ordering of a wave's own LDS accesses across lanes (the hardware runs a
+// wave's LDS instructions in order; this keeps the compiler from moving
+// accesses across the point).
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+}
+
 template <typename VT, int ZB, int MODE, int NW>
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
+__global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   constexpr bool kSketch = ZB > 0;
   constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain);
-  constexpr int kWaves = kSpmvThreads / kWave;
-  constexpr int kU = kStage / kSpmvThreads;
-  __shared__ double prod[kStage];
-  extern __shared__ double lds_sk[];  // kWaves x s doubles when sketching (per-wave copies)
-  __shared__ double scratch[kWaves];
+  constexpr int kU = kWStage / kWave;
+  // per wave: the products of its tile, then (sketching) its s accumulators
+  extern __shared__ double lds[];
+  __shared__ double scratch[kSpmvMaxWaves];
 
   if (MODE == kModeInner && a.ctl->stop_k != 0) return;
 
   const int tid = threadIdx.x;
+  const int lane = tid & (kWave - 1);
+  const int wv = tid / kWave;
+  const int nw = blockDim.x / kWave;
+  const int S = kSketch ? a.s : 0;
+  double* const prod = lds + (size_t)wv * (kWStage + S);
+  double* const wave_sk = prod + kWStage;
+  // this wave's tiles: workgroups take contiguous ranges (XCD-grouped),
+  // waves split their workgroup's range
   const int G = gridDim.x;
   const int g = xcd_logical_block(blockIdx.x, G);
-  const int t0 = (int)(((int64_t)a.ntiles * g) / G);
-  const int t1 = (int)(((int64_t)a.ntiles * (g + 1)) / G);
+  const int64_t W = (int64_t)G * nw;
+  const int64_t me = (int64_t)g * nw + wv;
+  const int t0 = (int)(((int64_t)a.ntiles * me) / W);
+  const int t1 = (int)(((int64_t)a.ntiles * (me + 1)) / W);
 
   const int32_t* __restrict__ row_ptr = a.row_ptr;
   const int32_t* __restrict__ col_idx = a.col_idx;
@@ -137,9 +154,8 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
                                               : 1.0;
   const int nwin = NW < a.nwin ? NW : a.nwin;
 
-  double* const wave_sk = lds_sk + (tid / kWave) * a.s;
   if (kSketch)
-    for (int q = tid; q < kWaves * a.s; q += kSpmvThreads) lds_sk[q] = 0.0;
+    for (int q = lane; q < S; q += kWave) wave_sk[q] = 0.0;
 
   double dacc[NW > 0 ? NW : 1];
 #pragma unroll
@@ -148,7 +164,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
 
   // inputs of the epilogue of row r, independent of the row sum
   struct Pre {
-    double u[NW > 0 ? NW : 1];
+    VT u[NW > 0 ? NW : 1];  // (converted at use, so the loads stay in flight)
     uint2 sk[ZB > 0 ? ZB : 1];
     double b0, b1;
   };
@@ -156,7 +172,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
     if constexpr (kInnerLike) {
 #pragma unroll
       for (int l = 0; l < NW; ++l)
-        p.u[l] = l < nwin ? static_cast<double>(U[(int64_t)(a.l0 + l) * a.ldu + r]) : 0.0;
+        p.u[l] = l < nwin ? U[(int64_t)(a.l0 + l) * a.ldu + r] : VT(0);
 #pragma unroll
       for (int b = 0; b < ZB; ++b) p.sk[b] = a.skp[(int64_t)r * ZB + b];
     } else if constexpr (MODE == kModeOuter) {
@@ -168,9 +184,9 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
   };
   auto epilogue = [&](int r, double y, const Pre& p) {
     if constexpr (kInnerLike) {
-      const VT wv = static_cast<VT>(scale * y);
-      if (w) w[r] = wv;
-      const double wd = static_cast<double>(wv);
+      const VT wvv = static_cast<VT>(scale * y);
+      if (w) w[r] = wvv;
+      const double wd = static_cast<double>(wvv);
       if constexpr (kSketch) {
 #pragma unroll
         for (int b = 0; b < ZB; ++b) {
@@ -187,7 +203,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
         }
       }
 #pragma unroll
-      for (int l = 0; l < NW; ++l) dacc[l] += wd * p.u[l];
+      for (int l = 0; l < NW; ++l) dacc[l] += wd * static_cast<double>(p.u[l]);
       n2 += wd * wd;
     } else if constexpr (MODE == kModeOuter) {
       w[r] = static_cast<VT>(y);
@@ -206,95 +222,120 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
     }
   };
 
-  // staged nonzeros of the tile being loaded
+  // Per tile: the x entries of its nonzeros, its row bounds and the epilogue
+  // inputs of its rows are requested together, while the column indices and
+  // values of the next tile are already on their way (raw VT values stay in
+  // registers until use, so no load is waited for before it is needed).
+  // With wide windows or sketch columns the registers do not hold the next
+  // tile's values as well: then they are loaded with the gathers.
+  constexpr bool kAhead = sizeof(VT) == 4 ? (NW <= 4 || ZB <= 2) : (NW <= 2 && ZB <= 2);
   int ci[kU];
-  double vv[kU];
-  int c_r0 = 0, c_r1 = 0, c_p0 = 0, c_L = 0;
+  VT vn[kU];
+  int f_r0 = 0, f_r1 = 0, f_p0 = 0, f_L = 0;
   auto fetch = [&](int tl) {
-    c_r0 = a.tiles[tl];
-    c_r1 = a.tiles[tl + 1];
-    c_p0 = a.tp[tl];
-    c_L = a.tp[tl + 1] - c_p0;
-    if (has_x && c_L <= kStage) {
+    f_r0 = a.tiles[tl];
+    f_r1 = a.tiles[tl + 1];
+    f_p0 = a.tp[tl];
+    f_L = a.tp[tl + 1] - f_p0;
+    if (has_x && f_L <= kWStage) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
-        const int q = u * kSpmvThreads + tid;
-        if (q < c_L) {
-          ci[u] = __builtin_nontemporal_load(&col_idx[c_p0 + q]);
-          vv[u] = static_cast<double>(__builtin_nontemporal_load(&val[c_p0 + q]));
+        const int q = u * kWave + lane;
+        if (q < f_L) {
+          ci[u] = __builtin_nontemporal_load(&col_idx[f_p0 + q]);
+          if (kAhead) vn[u] = __builtin_nontemporal_load(&val[f_p0 + q]);
         }
       }
     }
   };
 
   if (t0 < t1) fetch(t0);
-  __syncthreads();
   for (int tl = t0; tl < t1; ++tl) {
-    const int r0 = c_r0, r1 = c_r1, p0 = c_p0, L = c_L;
-    if (r0 >= r1) {
-      if (tl + 1 < t1) fetch(tl + 1);
-      continue;
-    }
-    if (L <= kStage) {
-      if (has_x) {
+    const int r0 = f_r0, r1 = f_r1, p0 = f_p0, L = f_L;
+    const bool staged = has_x && L <= kWStage;
+    VT vc[kU], xg[kU];
+    if (staged) {
 #pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int q = u * kSpmvThreads + tid;
-          if (q < L) prod[q] = vv[u] * static_cast<double>(x[ci[u]]);
+      for (int u = 0; u < kU; ++u) {
+        const int q = u * kWave + lane;
+        if (q < L) {
+          vc[u] = kAhead ? vn[u] : __builtin_nontemporal_load(&val[p0 + q]);
+          xg[u] = x[ci[u]];
         }
       }
-      __syncthreads();
-      if (tl + 1 < t1) fetch(tl + 1);  // in flight during this tile's reduction
+    }
+    if (tl + 1 < t1) fetch(tl + 1);
+    if (r0 >= r1) continue;
+    if (L <= kWStage) {
       const int nrows = r1 - r0;
-      int gsz = 1;
-      while (gsz < kWave && nrows * gsz * 2 <= kSpmvThreads) gsz <<= 1;
-      const int ngroups = kSpmvThreads / gsz;
-      const int grp = tid / gsz;
-      const int gl = tid & (gsz - 1);
-      for (int rr = grp; rr < nrows; rr += ngroups) {
+      int gsz = 1;  // lanes per row
+      while (gsz < kWave && nrows * gsz * 2 <= kWave) gsz <<= 1;
+      const int ngroups = kWave / gsz;
+      const int grp = lane / gsz;
+      const int gl = lane & (gsz - 1);
+      Pre pre0;
+      int qa0 = 0, qe0 = 0;
+      if (grp < nrows) {
+        const int r = r0 + grp;
+        qa0 = row_ptr[r] - p0;
+        qe0 = row_ptr[r + 1] - p0;
+        if (gl == 0) load_pre(r, pre0);
+      }
+      if (staged) {
+#pragma unroll
+        for (int u = 0; u < kU; ++u) {
+          const int q = u * kWave + lane;
+          if (q < L) prod[q] = static_cast<double>(vc[u]) * static_cast<double>(xg[u]);
+        }
+      }
+      wave_sync();
+      auto row_sum = [&](int qa, int qe) {
+        double acc = 0.0;
+        if (has_x)
+          for (int q = qa + gl; q < qe; q += gsz) acc += prod[q];
+        for (int off = gsz >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        return acc;
+      };
+      if (grp < nrows) {
+        const double acc = row_sum(qa0, qe0);
+        if (gl == 0) epilogue(r0 + grp, acc, pre0);
+      }
+      for (int rr = grp + ngroups; rr < nrows; rr += ngroups) {  // (only with > 64 rows)
         const int r = r0 + rr;
         Pre pre;
         if (gl == 0) load_pre(r, pre);
-        double acc = 0.0;
-        if (has_x) {
-          const int qa = row_ptr[r] - p0;
-          const int qe = row_ptr[r + 1] - p0;
-          for (int q = qa + gl; q < qe; q += gsz) acc += prod[q];
-        }
-        for (int off = gsz >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+        const double acc = row_sum(row_ptr[r] - p0, row_ptr[r + 1] - p0);
         if (gl == 0) epilogue(r, acc, pre);
       }
-      __syncthreads();
+      wave_sync();
     } else {
-      // a tile whose rows exceed the stage: the whole workgroup per row
+      // a tile whose rows exceed the stage: the whole wave per row
       for (int r = r0; r < r1; ++r) {
         double acc = 0.0;
         if (has_x) {
           const int qa = row_ptr[r];
           const int qe = row_ptr[r + 1];
-          for (int q = qa + tid; q < qe; q += kSpmvThreads)
+          for (int q = qa + lane; q < qe; q += kWave)
             acc += static_cast<double>(val[q]) * static_cast<double>(x[col_idx[q]]);
         }
-        acc = block_sum(acc, scratch);
-        if (tid == 0) {
+        acc = wave_sum(acc);
+        if (lane == 0) {
           Pre pre;
           load_pre(r, pre);
           epilogue(r, acc, pre);
         }
       }
-      if (tl + 1 < t1) fetch(tl + 1);
     }
   }
 
   // one sketch row and one scalar row of partial sums per workgroup (fixed
-  // slot = blockIdx.x)
+  // slot = blockIdx.x); the wave copies are added in wave order
+  __syncthreads();
   if constexpr (kSketch) {
-    double* prow = a.part + (int64_t)blockIdx.x * a.s;
-    __syncthreads();
-    for (int q = tid; q < a.s; q += kSpmvThreads) {
-      double v = lds_sk[q];
-#pragma unroll
-      for (int wv = 1; wv < kWaves; ++wv) v += lds_sk[wv * a.s + q];
+    double* prow = a.part + (int64_t)blockIdx.x * S;
+    for (int q = tid; q < S; q += blockDim.x) {
+      double v = lds[kWStage + q];
+      for (int k = 1; k < nw; ++k) v += lds[(size_t)k * (kWStage + S) + kWStage + q];
       prow[q] = v;
     }
   }
@@ -321,86 +362,90 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv(SpmvArgs a) {
 
 struct LaunchCfg {
   int grid;
+  int waves;
   size_t lds;
   hipStream_t st;
   hipEvent_t ev0, ev1;
 };
 
 template <typename VT, int ZB, int MODE, int NW>
-static void launch_one(const LaunchCfg& c, const SpmvArgs& a) {
+static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
+  static bool attr_set = false;  // dynamic LDS above the default limit
+  if (!attr_set) {
+    const hipError_t e =
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<VT, ZB, MODE, NW>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  const dim3 block(c.waves * kWave);
   if (c.ev0)
-    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), dim3(kSpmvThreads), c.lds,
-                          c.st, c.ev0, c.ev1, 0, a);
+    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), block, c.lds, c.st, c.ev0,
+                          c.ev1, 0, a);
   else
-    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), dim3(kSpmvThreads), c.lds, c.st,
-                       a);
+    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), block, c.lds, c.st, a);
+  return hipGetLastError();
 }
 
 template <typename VT, int MODE, int NW>
-static void launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
-  c.lds = zb > 0 ? (size_t)(kSpmvThreads / kWave) * a.s * sizeof(double) : 0;
+static hipError_t launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
+  const size_t per_wave = (size_t)(kWStage + (zb > 0 ? a.s : 0)) * sizeof(double);
+  c.waves = spmv_waves(zb > 0 ? a.s : 0);
+  c.lds = per_wave * c.waves;
   switch (zb) {
     case 0:
-      launch_one<VT, 0, MODE, NW>(c, a);
-      break;
+      return launch_one<VT, 0, MODE, NW>(c, a);
     case 1:
-      launch_one<VT, 1, MODE, NW>(c, a);
-      break;
+      return launch_one<VT, 1, MODE, NW>(c, a);
     case 2:
-      launch_one<VT, 2, MODE, NW>(c, a);
-      break;
+      return launch_one<VT, 2, MODE, NW>(c, a);
     case 3:
-      launch_one<VT, 3, MODE, NW>(c, a);
-      break;
+      return launch_one<VT, 3, MODE, NW>(c, a);
     default:
-      launch_one<VT, 4, MODE, NW>(c, a);
-      break;
+      return launch_one<VT, 4, MODE, NW>(c, a);
   }
 }
 
 template <typename VT, int MODE>
-static void launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) {
-  if (a.nwin <= 0)
-    launch_spmv_zb<VT, MODE, 0>(zb, c, a);
-  else if (a.nwin <= 2)
-    launch_spmv_zb<VT, MODE, 2>(zb, c, a);
-  else if (a.nwin <= 4)
-    launch_spmv_zb<VT, MODE, 4>(zb, c, a);
-  else
-    launch_spmv_zb<VT, MODE, kMaxT>(zb, c, a);
+static hipError_t launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) {
+  if (a.nwin <= 0) return launch_spmv_zb<VT, MODE, 0>(zb, c, a);
+  if (a.nwin <= 2) return launch_spmv_zb<VT, MODE, 2>(zb, c, a);
+  if (a.nwin <= 4) return launch_spmv_zb<VT, MODE, 4>(zb, c, a);
+  return launch_spmv_zb<VT, MODE, kMaxT>(zb, c, a);
+}
+
+int spmv_waves(int s) {
+  const size_t per_wave = (size_t)(kWStage + s) * sizeof(double);
+  int nw = kSpmvMaxWaves;
+  while (nw > 1 && per_wave * nw > (size_t)kSpmvLdsMax) nw >>= 1;
+  return nw;
 }
 
 hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,
                        hipEvent_t ev0, hipEvent_t ev1) {
-  const LaunchCfg c{grid, 0, st, ev0, ev1};
+  const LaunchCfg c{grid, 0, 0, st, ev0, ev1};
   switch (mode) {
     case kModeInner:
-      if (fp32)
-        launch_spmv_nw<float, kModeInner>(zb, c, a);
-      else
-        launch_spmv_nw<double, kModeInner>(zb, c, a);
-      break;
+      return fp32 ? launch_spmv_nw<float, kModeInner>(zb, c, a)
+                  : launch_spmv_nw<double, kModeInner>(zb, c, a);
     case kModePlain:
-      launch_spmv_nw<double, kModePlain>(zb, c, a);
-      break;
+      return launch_spmv_nw<double, kModePlain>(zb, c, a);
     case kModeOuter:
-      launch_one<double, 0, kModeOuter, 1>(c, a);
-      break;
+      return launch_spmv_zb<double, kModeOuter, 1>(0, c, a);
     case kModeResid:
-      launch_one<double, 0, kModeResid, 0>(c, a);
-      break;
+      return launch_spmv_zb<double, kModeResid, 0>(0, c, a);
     default:
-      launch_one<double, 0, kModeTrueRes, 0>(c, a);
-      break;
+      return launch_spmv_zb<double, kModeTrueRes, 0>(0, c, a);
   }
-  return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- finisher
-__global__ __launch_bounds__(kSpmvThreads) void k_spmv_finish(int mode, const double* dpart,
+constexpr int kFinishThreads = 256;
+
+__global__ __launch_bounds__(kFinishThreads) void k_spmv_finish(int mode, const double* dpart,
                                                               int32_t G, DevCtl* c,
                                                               double* out0, HostStatus* hs) {
-  __shared__ double scratch[kSpmvThreads / kWave];
+  __shared__ double scratch[kFinishThreads / kWave];
   const double t0s = block_sum_strided(dpart + kMaxT, G, kDP, scratch);
   const double t1s = block_sum_strided(dpart + kMaxT + 1, G, kDP, scratch);
   if (threadIdx.x != 0) return;
@@ -426,7 +471,7 @@ __global__ __launch_bounds__(kSpmvThreads) void k_spmv_finish(int mode, const do
 
 hipError_t launch_spmv_finish(int mode, const double* dpart, int32_t G, DevCtl* ctl,
                               double* out0, HostStatus* hs, hipStream_t st) {
-  hipLaunchKernelGGL(k_spmv_finish, dim3(1), dim3(kSpmvThreads), 0, st, mode, dpart, G, ctl,
+  hipLaunchKernelGGL(k_spmv_finish, dim3(1), dim3(kFinishThreads), 0, st, mode, dpart, G, ctl,
                      out0, hs);
   return hipGetLastError();
 }

@@ -243,9 +243,12 @@ def test_condition_estimates(run):
     p = run["strict"]
     lim = np.log1p(1e-6 + 1e3 * U64 * np.maximum(g[:p], r[:p]))
     assert np.all(np.abs(np.log(g[:p] / r[:p])) <= lim), (g, r)
-    # beyond the strict prefix: same order of magnitude
-    J = min(len(g), len(r))
-    assert np.all(np.abs(np.log(g[p:J] / r[p:J])) <= np.log(10.0)), (g, r)
+    # beyond the strict prefix the two runs work on different, equally valid
+    # vectors and their inner problems differ; what the C2 rule fixes there is
+    # that the estimate kept at every stop lies in [1, threshold] (C2 is tested
+    # before C3 and C1, and drops the column that crosses the threshold)
+    thr = run["prm"].get("cond_threshold", 1e15)
+    assert np.all((g[p:] >= 1.0 - 1e-12) & (g[p:] <= thr * (1.0 + 1e-12))), g
 
 
 def test_invariants_on_gpu_output(run):
