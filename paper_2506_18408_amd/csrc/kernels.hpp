@@ -131,10 +131,23 @@ hipError_t launch_sketch_out(const double* red, int32_t s, double inv_sqrt_zeta,
 // Vector kernels (vec.hip).
 hipError_t launch_init_ctl(DevCtl* ctl, int32_t m, int32_t t, int32_t s, double cond_threshold,
                            double tol, hipStream_t st);
-hipError_t launch_arnoldi_update(bool fp32, int grid, int64_t n, const void* W, void* B,
-                                 int64_t ldb, int32_t l0, int32_t nwin, int32_t inext,
-                                 const double* coef, double* vpart, const DevCtl* ctl,
-                                 hipStream_t st);
+// Truncated-Arnoldi update of inner step `step` (t > 0) with its own
+// coefficients (vec.hip).
+struct ArnoldiArgs {
+  int64_t n;
+  const void* W;            // y = A u_step (same type as the basis)
+  void* B;                  // basis, column-major, leading dimension ldb
+  int64_t ldb;
+  int32_t l0, nwin, inext, step;
+  const double* dpart;      // scalar rows of the fused SpMV (Gd rows of kDP)
+  int32_t Gd;
+  const double* vprev;      // norm partials of u_step (Gv entries; unused at step 0)
+  int32_t Gv;
+  double* vnext;            // norm partials of u_{step+1} (one per workgroup)
+  double* sigma;
+  DevCtl* ctl;
+};
+hipError_t launch_arnoldi_update(bool fp32, int grid, const ArnoldiArgs& a, hipStream_t st);
 hipError_t launch_mgs_pass(int grid, int64_t n, double* W, const double* Vcur,
                            const double* Vnext, const double* hcur, double* vpart, int last,
                            hipStream_t st);

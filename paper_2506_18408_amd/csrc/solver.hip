@@ -74,7 +74,7 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.ipart = take((size_t)(kVecGrid + 1) * 4);
   L.part = take((size_t)panel * kMaxGrid * s * 8);
   L.dpart = take((size_t)kMaxGrid * kDP * 8);
-  L.vpart = take((size_t)kVecGrid * 8);
+  L.vpart = take((size_t)2 * kVecGrid * 8);  // two: read by one Arnoldi update, written by it
   L.red = take((size_t)panel * s * 8);
   L.skp = take(packed_sketch_bytes(n, zeta));
   L.qr_V = take((size_t)s * m * 8);
@@ -500,23 +500,43 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       const bool timed = o.profile > 0 && i % o.profile == o.profile - 1;
       SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st, timed ? h->ev[2 * i] : nullptr,
                           timed ? h->ev[2 * i + 1] : nullptr));
-      CoefArgs ca{};
-      ca.dpart = P.dpart;
-      ca.G = Gp;
-      ca.vpart = P.vpart;
-      ca.Gv = G2;
-      ca.t = t;
-      ca.nwin = nwin;
-      ca.l0 = l0;
-      ca.step = i;
-      ca.ctl = P.ctl;
-      ca.sigma = P.sigma;
-      ca.coef = P.coef;
-      SFG_HIP(launch_coef(ca, st));
+      // sigma and the window coefficients: inside the Arnoldi update for
+      // t > 0 (norm partials alternate between two buffers), else (t = 0, or
+      // the cycle's last step) a one-workgroup kernel
+      double* vprev = P.vpart + (int64_t)(i & 1) * kVecGrid;
+      double* vnext = P.vpart + (int64_t)((i + 1) & 1) * kVecGrid;
       if (t > 0 && i + 1 < m) {
-        const void* Wv = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
-        SFG_HIP(launch_arnoldi_update(f32, G2, n, Wv, P.Bb, ld, l0, nwin, i + 1, P.coef, P.vpart,
-                                      P.ctl, st));
+        ArnoldiArgs aa{};
+        aa.n = n;
+        aa.W = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
+        aa.B = P.Bb;
+        aa.ldb = ld;
+        aa.l0 = l0;
+        aa.nwin = nwin;
+        aa.inext = i + 1;
+        aa.step = i;
+        aa.dpart = P.dpart;
+        aa.Gd = Gp;
+        aa.vprev = vprev;
+        aa.Gv = G2;
+        aa.vnext = vnext;
+        aa.sigma = P.sigma;
+        aa.ctl = P.ctl;
+        SFG_HIP(launch_arnoldi_update(f32, G2, aa, st));
+      } else {
+        CoefArgs ca{};
+        ca.dpart = P.dpart;
+        ca.G = Gp;
+        ca.vpart = vprev;
+        ca.Gv = G2;
+        ca.t = t;
+        ca.nwin = nwin;
+        ca.l0 = l0;
+        ca.step = i;
+        ca.ctl = P.ctl;
+        ca.sigma = P.sigma;
+        ca.coef = P.coef;
+        SFG_HIP(launch_coef(ca, st));
       }
       if (i + 1 - panel0 == pc || i + 1 == m) {
         const int ncols = i + 1 - panel0;

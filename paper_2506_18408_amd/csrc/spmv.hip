@@ -6,9 +6,10 @@
 // and the generation of the packed sketch.
 //
 // Design (gfx950): a persistent grid of one workgroup per CU, of 16 waves
-// (8 when the sketch is large); every wave walks its own contiguous range of
-// tiles without any workgroup barrier, so the waves of a CU keep independent
-// streams of memory requests in flight.  A tile (64 rows, one per lane, when
+// (8 when the sketch is large); every wave walks its own sequence of tiles
+// (every 16th tile of its workgroup's contiguous range) without any
+// workgroup barrier, so the waves of a CU keep independent streams of memory
+// requests in flight on neighbouring tiles.  A tile (64 rows, one per lane, when
 // every row has at most 8 nonzeros; else about 256 nonzeros) has its column
 // indices and values loaded with coalesced loads one tile ahead, its x
 // entries gathered, the products staged in the wave's own LDS region, and
@@ -133,14 +134,14 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   const int S = kSketch ? a.s : 0;
   double* const prod = lds + (size_t)wv * (kWStage + S);
   double* const wave_sk = prod + kWStage;
-  // this wave's tiles: workgroups take contiguous ranges (XCD-grouped),
-  // waves split their workgroup's range
+  // this wave's tiles: workgroups take contiguous ranges (XCD-grouped);
+  // inside a range the waves take every nw-th tile, so the waves of a CU
+  // work on neighbouring tiles at the same time (shared DRAM pages and
+  // cached x entries)
   const int G = gridDim.x;
   const int g = xcd_logical_block(blockIdx.x, G);
-  const int64_t W = (int64_t)G * nw;
-  const int64_t me = (int64_t)g * nw + wv;
-  const int t0 = (int)(((int64_t)a.ntiles * me) / W);
-  const int t1 = (int)(((int64_t)a.ntiles * (me + 1)) / W);
+  const int t0 = (int)(((int64_t)a.ntiles * g) / G) + wv;
+  const int t1 = (int)(((int64_t)a.ntiles * (g + 1)) / G);
 
   const int32_t* __restrict__ row_ptr = a.row_ptr;
   const int32_t* __restrict__ col_idx = a.col_idx;
@@ -226,12 +227,13 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   // inputs of its rows are requested together, while the column indices and
   // values of the next tile are already on their way (raw VT values stay in
   // registers until use, so no load is waited for before it is needed).
-  // With wide windows or sketch columns the registers do not hold the next
-  // tile's values as well: then they are loaded with the gathers.
+  // With wide windows or sketch columns the next tile's values are loaded
+  // with its gathers instead of with its indices (!kAhead).
   constexpr bool kAhead = sizeof(VT) == 4 ? (NW <= 4 || ZB <= 2) : (NW <= 2 && ZB <= 2);
   int ci[kU];
-  VT vn[kU];
-  int f_r0 = 0, f_r1 = 0, f_p0 = 0, f_L = 0;
+  VT vn[kU], vg[kU], xg[kU];
+  int f_r0 = 0, f_r1 = 0, f_p0 = 0, f_L = 0;  // fetched tile
+  int g_r0 = 0, g_r1 = 0, g_p0 = 0, g_L = 0;  // gathered tile
   auto fetch = [&](int tl) {
     f_r0 = a.tiles[tl];
     f_r1 = a.tiles[tl + 1];
@@ -248,47 +250,67 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
       }
     }
   };
-
-  if (t0 < t1) fetch(t0);
-  for (int tl = t0; tl < t1; ++tl) {
-    const int r0 = f_r0, r1 = f_r1, p0 = f_p0, L = f_L;
-    const bool staged = has_x && L <= kWStage;
-    VT vc[kU], xg[kU];
-    if (staged) {
+  auto gather = [&]() {  // fetched -> gathered: values and x entries
+    g_r0 = f_r0;
+    g_r1 = f_r1;
+    g_p0 = f_p0;
+    g_L = f_L;
+    if (has_x && g_L <= kWStage) {
 #pragma unroll
       for (int u = 0; u < kU; ++u) {
         const int q = u * kWave + lane;
-        if (q < L) {
-          vc[u] = kAhead ? vn[u] : __builtin_nontemporal_load(&val[p0 + q]);
+        if (q < g_L) {
+          vg[u] = kAhead ? vn[u] : __builtin_nontemporal_load(&val[g_p0 + q]);
           xg[u] = x[ci[u]];
         }
       }
     }
-    if (tl + 1 < t1) fetch(tl + 1);
+  };
+  // rows of a tile: groups of gsz lanes, one row per group at a time
+  auto group_size = [&](int nrows) {
+    int gsz = 1;
+    while (gsz < kWave && nrows * gsz * 2 <= kWave) gsz <<= 1;
+    return gsz;
+  };
+  // epilogue inputs of the first row of this lane's group in the gathered tile
+  struct Epi {
+    Pre pre;
+    int q0, q1;
+  };
+  Epi cur{};
+  auto epi_load = [&](Epi& e) {
+    const int nrows = g_r1 - g_r0;
+    if (nrows <= 0 || g_L > kWStage) return;
+    const int gsz = group_size(nrows);
+    const int grp = lane / gsz;
+    if (grp < nrows) {
+      const int r = g_r0 + grp;
+      e.q0 = row_ptr[r];
+      e.q1 = row_ptr[r + 1];
+      if ((lane & (gsz - 1)) == 0) load_pre(r, e.pre);
+    }
+  };
+  if (t0 < t1) fetch(t0);
+  for (int tl = t0; tl < t1; tl += nw) {
+    gather();
+    if (tl + nw < t1) fetch(tl + nw);
+    epi_load(cur);
+    const int r0 = g_r0, r1 = g_r1, p0 = g_p0, L = g_L;
     if (r0 >= r1) continue;
     if (L <= kWStage) {
-      const int nrows = r1 - r0;
-      int gsz = 1;  // lanes per row
-      while (gsz < kWave && nrows * gsz * 2 <= kWave) gsz <<= 1;
-      const int ngroups = kWave / gsz;
-      const int grp = lane / gsz;
-      const int gl = lane & (gsz - 1);
-      Pre pre0;
-      int qa0 = 0, qe0 = 0;
-      if (grp < nrows) {
-        const int r = r0 + grp;
-        qa0 = row_ptr[r] - p0;
-        qe0 = row_ptr[r + 1] - p0;
-        if (gl == 0) load_pre(r, pre0);
-      }
-      if (staged) {
+      if (has_x) {
 #pragma unroll
         for (int u = 0; u < kU; ++u) {
           const int q = u * kWave + lane;
-          if (q < L) prod[q] = static_cast<double>(vc[u]) * static_cast<double>(xg[u]);
+          if (q < L) prod[q] = static_cast<double>(vg[u]) * static_cast<double>(xg[u]);
         }
       }
       wave_sync();
+      const int nrows = r1 - r0;
+      const int gsz = group_size(nrows);
+      const int ngroups = kWave / gsz;
+      const int grp = lane / gsz;
+      const int gl = lane & (gsz - 1);
       auto row_sum = [&](int qa, int qe) {
         double acc = 0.0;
         if (has_x)
@@ -297,8 +319,8 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
         return acc;
       };
       if (grp < nrows) {
-        const double acc = row_sum(qa0, qe0);
-        if (gl == 0) epilogue(r0 + grp, acc, pre0);
+        const double acc = row_sum(cur.q0 - p0, cur.q1 - p0);
+        if (gl == 0) epilogue(r0 + grp, acc, cur.pre);
       }
       for (int rr = grp + ngroups; rr < nrows; rr += ngroups) {  // (only with > 64 rows)
         const int r = r0 + rr;

@@ -41,71 +41,140 @@ hipError_t launch_init_ctl(DevCtl* ctl, int32_t m, int32_t t, int32_t s, double 
 }
 
 // ------------------------------------------------ truncated Arnoldi update
-// u_{i+1} = coef_t y - sum_l coef_l u_l over the window; each workgroup writes its
-// partial ||u_{i+1}||^2 to vpart[blockIdx.x] (summed by the next
-// coefficient kernel into sigma_{i+1}).
-template <typename VT>
-__global__ __launch_bounds__(kVecThreads) void k_arnoldi(int64_t n, const VT* __restrict__ W,
-                                                         VT* B, int64_t ldb, int32_t l0,
-                                                         int32_t nwin, int32_t inext,
-                                                         const double* __restrict__ coef,
-                                                         double* __restrict__ vpart,
-                                                         const DevCtl* ctl) {
+// u_{i+1} = sigma_i y - sum_l sigma_i sigma_l^2 <y, u_l> u_l over the window,
+// with y = A u_i and sigma_i = 1/||u_i|| (Section 4.1 with an unnormalised
+// basis).  Every workgroup first forms the coefficients itself: the window
+// dots from the fused SpMV's scalar rows and ||u_i||^2 from the previous
+// update's norm partials, summed in the same fixed order, so all workgroups
+// use bit-identical values; workgroup 0 records sigma_i, and a zero u_i as a
+// truncated-Arnoldi breakdown (first one only, zero coefficients).  The
+// first stretch of the vectors is requested before that reduction.  Each
+// workgroup writes its partial ||u_{i+1}||^2 to vnext[blockIdx.x].
+template <typename VT, int NW>
+__global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
+  constexpr int kNV = kMaxT + 1;  // window dots, then ||u_i||^2
+  __shared__ double buf[(kVecThreads / kWave) * kNV];
   __shared__ double scratch[kVecThreads / kWave];
   __shared__ double cf[kMaxT + 1];
-  if (ctl->stop_k != 0) return;
+  DevCtl* ctl = a.ctl;
   const int tid = threadIdx.x;
-  if (tid <= kMaxT) cf[tid] = (tid < nwin || tid == kMaxT) ? coef[tid] : 0.0;
+  const int step = a.step;
+  const int nwin = a.nwin < NW ? a.nwin : NW;
+  const int64_t n = a.n;
+  const VT* __restrict__ W = static_cast<const VT*>(a.W);
+  VT* B = static_cast<VT*>(a.B);
+  VT* out = B + (int64_t)a.inext * a.ldb;
+  const VT* win = B + (int64_t)a.l0 * a.ldb;
+  const int64_t stride = (int64_t)gridDim.x * kVecThreads * kUnroll;
+  const int64_t base0 = (int64_t)blockIdx.x * kVecThreads * kUnroll + tid;
+
+  // first stretch of y and the window (independent of the coefficients)
+  VT y0[kUnroll], b0[NW][kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) {
+    const int64_t r = base0 + u * kVecThreads;
+    y0[u] = r < n ? W[r] : VT(0);
+#pragma unroll
+    for (int l = 0; l < NW; ++l)
+      b0[l][u] = (l < nwin && r < n) ? win[(int64_t)l * a.ldb + r] : VT(0);
+  }
+  // the coefficients
+  double v[kNV];
+#pragma unroll
+  for (int l = 0; l < kNV; ++l) v[l] = 0.0;
+#pragma unroll
+  for (int u = 0; u < kMaxGrid / kVecThreads; ++u) {
+    const int g = tid + u * kVecThreads;
+    if (g < a.Gd) {
+      const double* row = a.dpart + (int64_t)g * kDP;
+#pragma unroll
+      for (int l = 0; l < kMaxT; ++l)
+        if (l < nwin) v[l] += row[l];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < kVecGrid / kVecThreads; ++u) {
+    const int g = tid + u * kVecThreads;
+    if (step > 0 && g < a.Gv) v[kMaxT] += a.vprev[g];
+  }
+  double sgw[kMaxT];
+#pragma unroll
+  for (int l = 0; l < kMaxT; ++l)
+    sgw[l] = (tid == 0 && l < nwin && a.l0 + l < step) ? a.sigma[a.l0 + l] : 0.0;
+  const int stopped = ctl->stop_k;
+  block_sum_vec<kNV>(v, buf);
+  if (stopped != 0) return;
+  if (tid == 0) {
+    bool brk = false;
+    double sig = 1.0;
+    if (step > 0) {
+      brk = v[kMaxT] == 0.0;
+      sig = brk ? 0.0 : 1.0 / sqrt(v[kMaxT]);
+    }
+    for (int l = 0; l < kMaxT; ++l) {
+      const double sg = (a.l0 + l == step) ? sig : sgw[l];
+      cf[l] = l < nwin ? sig * sg * sg * v[l] : 0.0;
+    }
+    cf[kMaxT] = sig;
+    if (blockIdx.x == 0) {
+      a.sigma[step] = sig;
+      if (brk && ctl->brk_step < 0) ctl->brk_step = step;  // u_step = 0
+    }
+  }
   __syncthreads();
   const double ys = cf[kMaxT];
-  VT* out = B + (int64_t)inext * ldb;
-  const VT* win = B + (int64_t)l0 * ldb;
   double n2 = 0.0;
-  const int64_t step = (int64_t)gridDim.x * kVecThreads * kUnroll;
-  for (int64_t base = (int64_t)blockIdx.x * kVecThreads * kUnroll + tid; base < n; base += step) {
+  auto update = [&](int64_t base, const VT (&yv)[kUnroll], const VT (&bv)[NW][kUnroll]) {
     double acc[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t r = base + u * kVecThreads;
-      acc[u] = r < n ? ys * static_cast<double>(W[r]) : 0.0;
-    }
-    for (int l = 0; l < nwin; ++l) {
-      double bl[kUnroll];
+    for (int u = 0; u < kUnroll; ++u) acc[u] = ys * static_cast<double>(yv[u]);
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) {
-        const int64_t r = base + u * kVecThreads;
-        bl[u] = r < n ? static_cast<double>(win[(int64_t)l * ldb + r]) : 0.0;
-      }
+    for (int l = 0; l < NW; ++l)
+      if (l < nwin)
 #pragma unroll
-      for (int u = 0; u < kUnroll; ++u) acc[u] -= cf[l] * bl[u];
-    }
+        for (int u = 0; u < kUnroll; ++u) acc[u] -= cf[l] * static_cast<double>(bv[l][u]);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t r = base + u * kVecThreads;
       if (r < n) {
-        const VT v = static_cast<VT>(acc[u]);
-        out[r] = v;
-        const double vd = static_cast<double>(v);
-        n2 += vd * vd;
+        const VT o = static_cast<VT>(acc[u]);
+        out[r] = o;
+        const double od = static_cast<double>(o);
+        n2 += od * od;
       }
     }
+  };
+  update(base0, y0, b0);
+  for (int64_t base = base0 + stride; base < n; base += stride) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = base + u * kVecThreads;
+      y0[u] = r < n ? W[r] : VT(0);
+#pragma unroll
+      for (int l = 0; l < NW; ++l)
+        b0[l][u] = (l < nwin && r < n) ? win[(int64_t)l * a.ldb + r] : VT(0);
+    }
+    update(base, y0, b0);
   }
   n2 = block_sum(n2, scratch);
-  if (tid == 0) vpart[blockIdx.x] = n2;
+  if (tid == 0) a.vnext[blockIdx.x] = n2;
 }
 
-hipError_t launch_arnoldi_update(bool fp32, int grid, int64_t n, const void* W, void* B,
-                                 int64_t ldb, int32_t l0, int32_t nwin, int32_t inext,
-                                 const double* coef, double* vpart, const DevCtl* ctl,
-                                 hipStream_t st) {
-  if (fp32)
-    hipLaunchKernelGGL(k_arnoldi<float>, dim3(grid), dim3(kVecThreads), 0, st, n,
-                       static_cast<const float*>(W), static_cast<float*>(B), ldb, l0, nwin,
-                       inext, coef, vpart, ctl);
+template <typename VT>
+static void launch_arnoldi_t(int grid, const ArnoldiArgs& a, hipStream_t st) {
+  if (a.nwin <= 2)
+    hipLaunchKernelGGL((k_arnoldi<VT, 2>), dim3(grid), dim3(kVecThreads), 0, st, a);
+  else if (a.nwin <= 4)
+    hipLaunchKernelGGL((k_arnoldi<VT, 4>), dim3(grid), dim3(kVecThreads), 0, st, a);
   else
-    hipLaunchKernelGGL(k_arnoldi<double>, dim3(grid), dim3(kVecThreads), 0, st, n,
-                       static_cast<const double*>(W), static_cast<double*>(B), ldb, l0, nwin,
-                       inext, coef, vpart, ctl);
+    hipLaunchKernelGGL((k_arnoldi<VT, kMaxT>), dim3(grid), dim3(kVecThreads), 0, st, a);
+}
+
+hipError_t launch_arnoldi_update(bool fp32, int grid, const ArnoldiArgs& a, hipStream_t st) {
+  if (fp32)
+    launch_arnoldi_t<float>(grid, a, st);
+  else
+    launch_arnoldi_t<double>(grid, a, st);
   return hipGetLastError();
 }
 
