@@ -103,6 +103,7 @@ struct QrBlockArgs {
   int32_t nring;
   int32_t s, m, t;
   int32_t k0, ncols;        // first column, columns in this launch (1..kPanel)
+  int32_t pprev;            // columns of the previous panel whose T columns are still to form
   double inv_sqrt_zeta;
   DevCtl* ctl;
   HostStatus* hs;

@@ -221,62 +221,91 @@ __device__ __forceinline__ void reflector(double alpha, double x2, double& beta,
   }
 }
 
+// Sum over the 16 lanes of a row of the wave (quad exchanges, then the
+// values 4 and 8 lanes along); lane 0 of the row holds the sum.
+__device__ __forceinline__ double row16_sum(double v) {
+  v += dpp_move<0xB1>(v);   // quad_perm [1,0,3,2]
+  v += dpp_move<0x4E>(v);   // quad_perm [2,3,0,1]
+  v += dpp_move<0x124>(v);  // row_ror:4
+  v += dpp_move<0x128>(v);  // row_ror:8
+  return v;
+}
+
 // y = V^T X over rows >= q0 for the k0 reflectors V (global, column-major,
 // s rows) and the kPanel columns X (LDS, column-major), masked to rows
-// >= q0 + j in column j when `masked`: a wave per pair of reflectors, lanes
-// over rows, kVtChunks row chunks in flight.  Output y[l * kPanel + j] (LDS).
-constexpr int kVtChunks = 4;  // row chunks of 64 in flight per lane
-
+// >= q0 + j in column j when `masked` (columns j >= ncol read as zero).  X
+// may be in LDS or in global memory.  A wave takes four reflectors at
+// once, 16 lanes along the rows of each (coalesced 128-byte segments), so
+// each output needs only a 16-lane reduction.  Output y[j * ldy + l] (LDS).
 __device__ __forceinline__ void vt_panel(const double* __restrict__ V, int s, int k0, int q0,
-                                         const double* X, bool masked, double* y) {
+                                         const double* X, int ncol, bool masked, double* y,
+                                         int ldy) {
   const int lane = threadIdx.x & (kWave - 1);
   const int wid = threadIdx.x / kWave;
-  for (int lb = wid * 2; lb < k0; lb += kQrWaves * 2) {
-    const bool has1 = lb + 1 < k0;
-    double acc0[kPanel], acc1[kPanel];
+  const int c = lane >> 4;
+  const int ql = lane & 15;
+  for (int lb = wid * 4; lb < k0; lb += kQrWaves * 4) {
+    const int l = lb + c;
+    const bool has = l < k0;
+    const double* Vl = V + (int64_t)(has ? l : 0) * s;
+    double acc[kPanel];
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j) acc0[j] = acc1[j] = 0.0;
-    for (int qb = q0; qb < s; qb += kWave * kVtChunks) {
-      double v0[kVtChunks], v1[kVtChunks];
+    for (int j = 0; j < kPanel; ++j) acc[j] = 0.0;
+#pragma unroll 4
+    for (int q = q0 + ql; q < s; q += 16) {
+      const double v = has ? Vl[q] : 0.0;
 #pragma unroll
-      for (int u = 0; u < kVtChunks; ++u) {
-        const int q = qb + u * kWave + lane;
-        v0[u] = q < s ? V[(int64_t)lb * s + q] : 0.0;
-        v1[u] = (q < s && has1) ? V[(int64_t)(lb + 1) * s + q] : 0.0;
-      }
-#pragma unroll
-      for (int u = 0; u < kVtChunks; ++u) {
-        const int q = qb + u * kWave + lane;
-        if (q < s) {
-#pragma unroll
-          for (int j = 0; j < kPanel; ++j) {
-            const double xq = (!masked || q >= q0 + j) ? X[j * s + q] : 0.0;
-            acc0[j] += v0[u] * xq;
-            acc1[j] += v1[u] * xq;
-          }
-        }
+      for (int j = 0; j < kPanel; ++j) {
+        const double xq = (j < ncol && (!masked || q >= q0 + j)) ? X[j * s + q] : 0.0;
+        acc[j] += v * xq;
       }
     }
 #pragma unroll
     for (int j = 0; j < kPanel; ++j) {
-      const double r0 = wave_sum(acc0[j]);
-      const double r1 = wave_sum(acc1[j]);
-      if (lane == 0) {
-        y[lb * kPanel + j] = r0;
-        if (has1) y[(lb + 1) * kPanel + j] = r1;
-      }
+      const double r = row16_sum(acc[j]);
+      if (ql == 0 && has) y[j * ldy + l] = r;
     }
   }
 }
 
-// Shared scalars of the decision kernel: written by wave 0 at the end of
-// the panel, read by every thread after the following barrier.
+// Shared scalars of the decision kernel.
 struct QrShared {
   double tau[kPanel];
   double beta[kPanel];
-  double wm[kPanel][kPanel];  // wm[x][y] = v_{k0+x}^T v_{k0+y}, x < y
+  double wm[kPanel][kPanel];  // wm[x][y] = v_{kb+x}^T v_{kb+y}, x < y
   int stopped, done;
 };
+
+constexpr int kPanelWaves = 4;  // waves that factorise the panel (one per SIMD)
+constexpr int kPanelThreads = kPanelWaves * kWave;
+constexpr int kRowsPT = (kMaxS + kPanelThreads - 1) / kPanelThreads;  // rows per panel thread
+
+// Sums of NV values over the kPanelWaves panel waves; every one of their
+// threads gets the NV sums (wave sums, one barrier, the wave partials added
+// in wave order).  Only the panel waves are alive when it is called.
+// Callers alternate two buffers: a thread writes buffer b only after the
+// barrier of the call that used the other one, which every thread reaches
+// only after reading buffer b the time before.
+template <int NV>
+__device__ __forceinline__ void panel_sum(double (&v)[NV], double* rbuf, int& par) {
+  double* buf = rbuf + par * (kPanelWaves * 16);
+  par ^= 1;
+  const int lane = threadIdx.x & (kWave - 1);
+  const int wid = threadIdx.x / kWave;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  if (lane == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) buf[wid * 16 + i] = v[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    double r = 0.0;
+#pragma unroll
+    for (int w = 0; w < kPanelWaves; ++w) r += buf[w * 16 + i];
+    v[i] = r;
+  }
+}
 
 __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
   extern __shared__ double lds[];
@@ -284,8 +313,8 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
   const int s = a.s;
   const int m = a.m;
   // LDS: panel (kPanel columns of s, column-major), d (s), the condition
-  // estimate vectors x and z (m each), AU and BX (m x kPanel, row l at
-  // l * kPanel), two reduction buffers
+  // estimate vectors x and z (m each), AU and BX (m x kPanel, column-major),
+  // reduction buffer
   double* Cp = lds;
   double* dv = Cp + (size_t)kPanel * s;
   double* xv = dv + s;
@@ -295,13 +324,12 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
   double* rbuf = BX + (size_t)m * kPanel;
 
   DevCtl* ctl = a.ctl;
-  const int q = threadIdx.x;  // this thread's sketch row (and row of T / R)
+  const int q = threadIdx.x;
   const int lane = q & (kWave - 1);
   const int wid = q / kWave;
   const int k0 = a.k0;
   const int p = a.ncols;
   const double* __restrict__ V = a.V;
-  const double* __restrict__ T = a.T;
   const bool row = q < s;
 
   // ---- every input at once: panel rows, d, estimate vectors --------------
@@ -323,33 +351,108 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
   if (ctl->stop_k != 0) return;
   __syncthreads();
 
-  if (k0 > 0) {
-    // A = V^T C, then B = T^T A (a wave per pair of columns of T, lanes over
-    // its rows), then C <- C - V B (a thread per row)
-    vt_panel(V, s, k0, 0, Cp, false, AU);
-    __syncthreads();
-    for (int lb = wid * 2; lb < k0; lb += kQrWaves * 2) {
-      const bool has1 = lb + 1 < k0;
-      double acc0[kPanel], acc1[kPanel];
+  // ---- T extended by the previous panel's reflectors kb .. k0-1 ----------
+  // (deferred to this launch, where all waves are present; a cycle's last
+  // panel never needs it)
+  const int pp = a.pprev;
+  if (pp > 0) {
+    const int kb = k0 - pp;
+    const double* Vn = V + (int64_t)kb * s;  // the new reflectors, zero above their units
+    // U = V_old^T V_new over rows >= kb
+    vt_panel(V, s, kb, kb, Vn, pp, true, AU, m);
+    // wm[x][y] = v_{kb+x}^T v_{kb+y} (x < y): wave sums, column y at a time,
+    // into the reduction buffer (entry y (y - 1) / 2 + x), then one thread
+    // per entry adds the waves in wave order
+    {
+      double cr[kPanel];
 #pragma unroll
-      for (int j = 0; j < kPanel; ++j) acc0[j] = acc1[j] = 0.0;
-      for (int r = lane; r <= lb + 1 && r < k0; r += kWave) {
-        const double t0 = r <= lb ? T[(int64_t)lb * m + r] : 0.0;
-        const double t1 = has1 ? T[(int64_t)(lb + 1) * m + r] : 0.0;
+      for (int x = 0; x < kPanel; ++x) cr[x] = (row && x < pp && q >= kb + x) ? Vn[(int64_t)x * s + q] : 0.0;
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j) {
-          const double av = AU[r * kPanel + j];
-          acc0[j] += t0 * av;
-          acc1[j] += t1 * av;
+      for (int y = 1; y < kPanel; ++y)
+#pragma unroll
+        for (int x = 0; x < y; ++x) {
+          const double w = wave_sum(cr[x] * cr[y]);
+          if (lane == 0) rbuf[wid * kRB + y * (y - 1) / 2 + x] = w;
+        }
+      __syncthreads();  // also publishes AU
+      if (q < kPanel * (kPanel - 1) / 2) {
+        int y = 1;
+        while (y * (y + 1) / 2 <= q) ++y;
+        const int x = q - y * (y - 1) / 2;
+        double r = 0.0;
+        for (int w = 0; w < kQrWaves; ++w) r += rbuf[w * kRB + q];
+        sh.wm[x][y] = r;
+      }
+      if (q < kPanel) sh.tau[q] = q < pp ? a.tau[kb + q] : 0.0;
+      __syncthreads();
+    }
+    // row r = q of X = T_old U, then of the new columns:
+    // T(0:kk, kk) = -tau_kk T(0:kk, 0:kk) [U(:, j); wm(0:j, j)], T(kk, kk) = tau_kk
+    if (q < k0) {
+      double xr[kPanel], tn[kPanel];
+#pragma unroll
+      for (int j = 0; j < kPanel; ++j) xr[j] = 0.0;
+      if (q < kb) {
+        int l = q;
+        for (; l + 8 <= kb; l += 8) {
+          double tv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) tv[u] = a.T[(int64_t)(l + u) * m + q];
+#pragma unroll
+          for (int u = 0; u < 8; ++u)
+#pragma unroll
+            for (int j = 0; j < kPanel; ++j) xr[j] += tv[u] * AU[j * m + l + u];
+        }
+        for (; l < kb; ++l) {
+          const double tv = a.T[(int64_t)l * m + q];
+#pragma unroll
+          for (int j = 0; j < kPanel; ++j) xr[j] += tv * AU[j * m + l];
         }
       }
 #pragma unroll
       for (int j = 0; j < kPanel; ++j) {
-        const double r0 = wave_sum(acc0[j]);
-        const double r1 = wave_sum(acc1[j]);
-        if (lane == 0) {
-          BX[lb * kPanel + j] = r0;
-          if (has1) BX[(lb + 1) * kPanel + j] = r1;
+        const int kk = kb + j;
+        tn[j] = 0.0;
+        if (q < kk) {
+          double acc = xr[j];
+#pragma unroll
+          for (int jj = 0; jj < j; ++jj)
+            if (q <= kb + jj) acc += tn[jj] * sh.wm[jj][j];
+          tn[j] = -sh.tau[j] * acc;
+        } else if (q == kk) {
+          tn[j] = sh.tau[j];
+        }
+        if (j < pp && q <= kk) a.T[(int64_t)kk * m + q] = tn[j];
+      }
+    }
+    __syncthreads();  // T complete for B = T^T A below
+  }
+  const double* __restrict__ T = a.T;
+
+  if (k0 > 0) {
+    // A = V^T C, then B = T^T A (four columns of T per wave, 16 lanes over
+    // its rows), then C <- C - V B (a thread per row)
+    vt_panel(V, s, k0, 0, Cp, kPanel, false, AU, m);
+    __syncthreads();
+    {
+      const int c = lane >> 4;
+      const int rl = lane & 15;
+      for (int lb = wid * 4; lb < k0; lb += kQrWaves * 4) {
+        const int l = lb + c;
+        const bool has = l < k0;
+        double acc[kPanel];
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) acc[j] = 0.0;
+        const int rmax = lb + 3 < k0 ? lb + 3 : k0 - 1;  // rows of the wave's last column
+        for (int r = rl; r <= rmax; r += 16) {
+          const double tv = (has && r <= l) ? T[(int64_t)l * m + r] : 0.0;
+#pragma unroll
+          for (int j = 0; j < kPanel; ++j) acc[j] += tv * AU[j * m + r];
+        }
+#pragma unroll
+        for (int j = 0; j < kPanel; ++j) {
+          const double rr = row16_sum(acc[j]);
+          if (rl == 0 && has) BX[j * m + l] = rr;
         }
       }
     }
@@ -366,12 +469,12 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
 #pragma unroll
         for (int u = 0; u < 8; ++u)
 #pragma unroll
-          for (int j = 0; j < kPanel; ++j) acc[j] += vl[u] * BX[(l + u) * kPanel + j];
+          for (int j = 0; j < kPanel; ++j) acc[j] += vl[u] * BX[j * m + l + u];
       }
       for (; l < k0; ++l) {
         const double vl = V[(int64_t)l * s + q];
 #pragma unroll
-        for (int j = 0; j < kPanel; ++j) acc[j] += vl * BX[l * kPanel + j];
+        for (int j = 0; j < kPanel; ++j) acc[j] += vl * BX[j * m + l];
       }
 #pragma unroll
       for (int j = 0; j < kPanel; ++j) Cp[j * s + q] -= acc[j];
@@ -379,58 +482,68 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
     __syncthreads();
   }
 
-  // ---- the panel, column by column, in wave 0 ---------------------------
+  // ---- the panel, column by column, in the first kPanelWaves waves --------
   // Column kk = k0 + j: reflector on rows >= kk; d and the later panel
   // columns updated; ||d[kk+1:]|| (C3); Bischof's incremental estimate with
-  // the new column [R(0:kk, kk); beta] (C2); the decision.  One wave, lane L
-  // owning rows L, L + 64, ...: every sum is a wave reduction and no barrier
-  // is needed; the other waves wait at the barrier after the panel.
-  if (wid == 0) {
-    const int forced_k = ctl->forced_k;
-    const int brk_step = ctl->brk_step;
-    const double cond_thr = ctl->cond_threshold;
-    const double factor = ctl->factor;
-    const double tol_abs = ctl->tol_abs;
-    double smax = ctl->ice_smax, znorm = ctl->ice_znorm;
-    double cond_cur = ctl->cond_cur, cond_prev = ctl->cond_prev;
-    double rho_cur = ctl->rho_cur, rho_prev = ctl->rho_prev;
-    int err = ctl->error;
-    double beta, tau, den;
-    {
-      double x2 = 0.0, al = 0.0;
-      for (int r = lane; r < s; r += kWave) {
+  // the new column [R(0:kk, kk); beta] (C2); the decision.  Thread t owns
+  // rows t, t + 256, ... (of the panel, d, x and z); the scalars are computed
+  // identically by every panel thread from the reduced sums.  The other
+  // waves are done.
+  if (wid >= kPanelWaves) return;
+  const int t = q;
+  const int forced_k = ctl->forced_k;
+  const int brk_step = ctl->brk_step;
+  const double cond_thr = ctl->cond_threshold;
+  const double factor = ctl->factor;
+  const double tol_abs = ctl->tol_abs;
+  double smax = ctl->ice_smax, znorm = ctl->ice_znorm;
+  double cond_cur = ctl->cond_cur, cond_prev = ctl->cond_prev;
+  double rho_cur = ctl->rho_cur, rho_prev = ctl->rho_prev;
+  int err = ctl->error;
+  int par = 0;
+  double beta, tau, den;
+  {
+    double r2[2] = {0.0, 0.0};
+#pragma unroll
+    for (int u = 0; u < kRowsPT; ++u) {
+      const int r = t + u * kPanelThreads;
+      if (r < s) {
         const double c0 = Cp[r];
-        if (r > k0) x2 += c0 * c0;
-        if (r == k0) al = c0;
+        if (r > k0) r2[0] += c0 * c0;
+        if (r == k0) r2[1] = c0;
       }
-      reflector(wave_sum(al), wave_sum(x2), beta, tau, den);
     }
-    int stop_k = 0, stop_step = 0, stop_reason = 0, qr_k = k0;
-    int stopped = 0;
-    int done = k0;
-    for (int j = 0; j < p; ++j) {
-      const int kk = k0 + j;
-      if (brk_step == kk) {
-        // this column's Arnoldi vector is zero: keep the kk columns before it
-        stop_k = kk;
-        stop_step = kk;
-        stop_reason = SFGMRES_STOP_BREAKDOWN;
-        stopped = 1;
-        break;
-      }
+    panel_sum<2>(r2, rbuf, par);
+    reflector(r2[1], r2[0], beta, tau, den);
+  }
+  int stop_k = 0, stop_step = 0, stop_reason = 0, qr_k = k0;
+  int stopped = 0;
+  int done = k0;
+  for (int j = 0; j < p; ++j) {
+    const int kk = k0 + j;
+    if (brk_step == kk) {
+      // this column's Arnoldi vector is zero: keep the kk columns before it
+      stop_k = kk;
+      stop_step = kk;
+      stop_reason = SFGMRES_STOP_BREAKDOWN;
+      stopped = 1;
+      break;
+    }
+    if (t == 0) {
       sh.tau[j] = tau;
       sh.beta[j] = beta;
-      // v^T d, v^T C[:, j'] (j' > j) and the estimate's x^T r, z^T r with
-      // r = R's new column (rows < kk of column j); v = 1 at the pivot and
-      // c / den below it.  Read-only, so the loads of successive rows overlap.
-      double* cj = Cp + j * s;
-      const double inv = den != 0.0 ? 1.0 / den : 0.0;
-      double red[kPanel + 3];
+    }
+    double* cj = Cp + j * s;
+    const double inv = den != 0.0 ? 1.0 / den : 0.0;
+    // v^T d, v^T C[:, j'] (j' > j; the others masked below) and the
+    // estimate's x^T r, z^T r with r = R's new column (rows < kk of column j)
+    double red[kPanel + 3];
 #pragma unroll
-      for (int i = 0; i < kPanel + 3; ++i) red[i] = 0.0;
-      // (branch-free: every load is issued, the unused products are masked)
-#pragma unroll 2
-      for (int r = lane; r < s; r += kWave) {
+    for (int i = 0; i < kPanel + 3; ++i) red[i] = 0.0;
+#pragma unroll
+    for (int u = 0; u < kRowsPT; ++u) {
+      const int r = t + u * kPanelThreads;
+      if (r < s) {
         const double c = cj[r];
         const double dr = dv[r];
         const int ri = r < kk ? r : 0;  // (x and z hold m entries)
@@ -447,20 +560,20 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
         red[kPanel + 1] += xr * rc;
         red[kPanel + 2] += zr * rc;
       }
+    }
+    panel_sum<kPanel + 3>(red, rbuf, par);
+    // the reflector replaces rows >= kk of column j (rows < kk hold R's new
+    // column); d <- H d, C[:, j'] <- H C[:, j'] for j' > j; ||d[kk+1:]||^2
+    // and the next column's squared tail and pivot (branch-free: columns
+    // jj < j keep their values, every column of the row is stored)
+    double rm[kPanel];
 #pragma unroll
-      for (int i = 0; i < kPanel + 3; ++i)
-        if (i == 0 || i > j + 1) red[i] = wave_sum(red[i]);  // (1..j+1 unused)
-      // the reflector replaces rows >= kk of column j (rows < kk hold R's
-      // new column); d <- H d, C[:, j'] <- H C[:, j'] for j' > j; ||d[kk+1:]||^2
-      // and the next column's squared tail and pivot.  Branch-free: columns
-      // jj < j keep their values (rm = 0), column j becomes the reflector,
-      // every column of the row is stored.
-      double rm[kPanel];
+    for (int jj = 0; jj < kPanel; ++jj) rm[jj] = jj > j ? red[1 + jj] : 0.0;
+    double r3[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-      for (int jj = 0; jj < kPanel; ++jj) rm[jj] = jj > j ? red[1 + jj] : 0.0;
-      double r3[3] = {0.0, 0.0, 0.0};
-      const int rs = kk + ((lane - kk) % kWave + kWave) % kWave;  // first row >= kk of this lane
-      for (int r = rs; r < s; r += kWave) {
+    for (int u = 0; u < kRowsPT; ++u) {
+      const int r = t + u * kPanelThreads;
+      if (r < s && r >= kk) {
         double x[kPanel];
 #pragma unroll
         for (int jj = 0; jj < kPanel; ++jj) x[jj] = Cp[jj * s + r];
@@ -484,195 +597,130 @@ __global__ __launch_bounds__(kQrThreads) void k_qr_block(QrBlockArgs a) {
         if (r > kk + 1) r3[1] += nn * nn;
         if (r == kk + 1) r3[2] = nn;
       }
+    }
+    panel_sum<3>(r3, rbuf, par);
+    const double rho_hat = sqrt(r3[0]);
+    const double ax = red[kPanel + 1], bz = red[kPanel + 2];
+    const double gam = beta;
+    double kappa;
+    if (gam == 0.0 || smax < 0.0) {
+      smax = -1.0;  // singular from here on
+      kappa = INFINITY;
+    } else if (kk == 0) {
+      smax = fabs(gam);
+      znorm = 1.0 / fabs(gam);
+      kappa = smax * znorm;
+      if (t == 0) {
+        xv[0] = 1.0;
+        zv[0] = 1.0 / gam;
+      }
+    } else {
+      double lam, s1, c1, s2, c2;
+      top_eig2(smax * smax + ax * ax, ax * gam, gam * gam, lam, s1, c1);
+      smax = sqrt(lam);
+      const double g2 = gam * gam;
+      top_eig2(znorm * znorm + bz * bz / g2, -bz / g2, 1.0 / g2, lam, s2, c2);
+      znorm = sqrt(lam);
+      kappa = smax * znorm;
 #pragma unroll
-      for (int i = 0; i < 3; ++i) r3[i] = wave_sum(r3[i]);
-      const double rho_hat = sqrt(r3[0]);
-      const double ax = red[kPanel + 1], bz = red[kPanel + 2];
-      const double gam = beta;
-      double kappa;
-      if (gam == 0.0 || smax < 0.0) {
-        smax = -1.0;  // singular from here on
-        kappa = INFINITY;
-      } else if (kk == 0) {
-        smax = fabs(gam);
-        znorm = 1.0 / fabs(gam);
-        kappa = smax * znorm;
-        if (lane == 0) {
-          xv[0] = 1.0;
-          zv[0] = 1.0 / gam;
-        }
-      } else {
-        double lam, s1, c1, s2, c2;
-        top_eig2(smax * smax + ax * ax, ax * gam, gam * gam, lam, s1, c1);
-        smax = sqrt(lam);
-        const double g2 = gam * gam;
-        top_eig2(znorm * znorm + bz * bz / g2, -bz / g2, 1.0 / g2, lam, s2, c2);
-        znorm = sqrt(lam);
-        kappa = smax * znorm;
-        for (int r = lane; r < kk; r += kWave) {
+      for (int u = 0; u < kRowsPT; ++u) {
+        const int r = t + u * kPanelThreads;
+        if (r < kk) {
           xv[r] *= s1;
           zv[r] *= s2;
-        }
-        if (lane == 0) {
+        } else if (r == kk) {
           xv[kk] = c1;
           zv[kk] = (c2 - s2 * bz) / gam;
         }
       }
-      const int ncols = kk + 1;
-      qr_k = ncols;
-      cond_prev = cond_cur;
-      rho_prev = rho_cur;
-      cond_cur = kappa;
-      rho_cur = rho_hat;
-      int stop = 0, reason = 0;
-      if (ncols == 1 && beta == 0.0) {
-        err = SFGMRES_ERR_BREAKDOWN;
-        stop = 1;
-        reason = SFGMRES_STOP_BREAKDOWN;
-      } else if (forced_k > 0) {
-        if (ncols >= forced_k) {
-          stop = forced_k;
-          reason = SFGMRES_STOP_FORCED;
-        }
-      } else if (ncols > 1 && kappa > cond_thr) {
-        stop = ncols - 1;
-        reason = SFGMRES_STOP_C2;
-      } else if (factor * rho_hat <= tol_abs) {
-        stop = ncols;
-        reason = SFGMRES_STOP_C3;
-      } else if (ncols >= m) {
-        stop = m;
-        reason = SFGMRES_STOP_C1;
-      }
-      if (!isfinite(rho_hat) && err == 0) err = SFGMRES_ERR_NONFINITE;
-      done = ncols;
-      if (stop) {
-        stop_k = stop;
-        stop_step = ncols;
-        stop_reason = reason;
-        stopped = 1;
-        break;
-      }
-      reflector(r3[2], r3[1], beta, tau, den);
     }
-    if (lane == 0) {
-      sh.stopped = stopped;
-      sh.done = done;
-      ctl->stop_k = stop_k;
-      ctl->stop_step = stop_step;
-      ctl->stop_reason = stop_reason;
-      ctl->qr_k = qr_k;
-      ctl->error = err;
-      ctl->ice_smax = smax;
-      ctl->ice_znorm = znorm;
-      ctl->cond_cur = cond_cur;
-      ctl->cond_prev = cond_prev;
-      ctl->rho_cur = rho_cur;
-      ctl->rho_prev = rho_prev;
-      host_store_i32(&a.hs->stop_k, stop_k);
-      host_store_i32(&a.hs->stop_step, stop_step);
-      host_store_i32(&a.hs->stop_reason, stop_reason);
-      host_store_i32(&a.hs->error, err);
-      host_store_i32(&a.hs->steps_run, k0 + p);
-      host_store_i32(&a.hs->inner_step_done, done);
+    const int ncols = kk + 1;
+    qr_k = ncols;
+    cond_prev = cond_cur;
+    rho_prev = rho_cur;
+    cond_cur = kappa;
+    rho_cur = rho_hat;
+    int stop = 0, reason = 0;
+    if (ncols == 1 && beta == 0.0) {
+      err = SFGMRES_ERR_BREAKDOWN;
+      stop = 1;
+      reason = SFGMRES_STOP_BREAKDOWN;
+    } else if (forced_k > 0) {
+      if (ncols >= forced_k) {
+        stop = forced_k;
+        reason = SFGMRES_STOP_FORCED;
+      }
+    } else if (ncols > 1 && kappa > cond_thr) {
+      stop = ncols - 1;
+      reason = SFGMRES_STOP_C2;
+    } else if (factor * rho_hat <= tol_abs) {
+      stop = ncols;
+      reason = SFGMRES_STOP_C3;
+    } else if (ncols >= m) {
+      stop = m;
+      reason = SFGMRES_STOP_C1;
     }
+    if (!isfinite(rho_hat) && err == 0) err = SFGMRES_ERR_NONFINITE;
+    done = ncols;
+    if (stop) {
+      stop_k = stop;
+      stop_step = ncols;
+      stop_reason = reason;
+      stopped = 1;
+      break;
+    }
+    reflector(r3[2], r3[1], beta, tau, den);
   }
-  __syncthreads();
-  const bool stopped = sh.stopped != 0;
-  const int done = sh.done;
   const int ndone = done - k0;  // columns whose reflector was formed
-
-  // ---- T extended by the p new reflectors (only if the cycle goes on) ----
-  // (Cp holds the new reflectors on rows >= their pivot, R's new columns
-  // above; rows of V above the pivot are zero)
-  double tn[kPanel];
-#pragma unroll
-  for (int j = 0; j < kPanel; ++j) tn[j] = 0.0;
-  if (!stopped) {
-    // U = V_old^T V_new (rows >= k0; the new vectors vanish above their unit)
-    vt_panel(V, s, k0, k0, Cp, true, AU);
-    {
-      // wave sums of the products, column y of Wm at a time, into the
-      // reduction buffer (entry y (y - 1) / 2 + x), then one thread per entry
-      // sums the waves in wave order
-      double* buf = rbuf;
-#pragma unroll
-      for (int y = 1; y < kPanel; ++y) {
-        const double cy = (q >= k0 + y && row) ? Cp[y * s + q] : 0.0;
-#pragma unroll
-        for (int x = 0; x < y; ++x) {
-          const double w = wave_sum(cy * (row ? Cp[x * s + q] : 0.0));
-          if (lane == 0) buf[wid * kRB + y * (y - 1) / 2 + x] = w;
-        }
-      }
-      __syncthreads();  // also publishes AU
-      if (q < kPanel * (kPanel - 1) / 2) {
-        int y = 1;
-        while (y * (y + 1) / 2 <= q) ++y;
-        const int x = q - y * (y - 1) / 2;
-        double r = 0.0;
-        for (int w = 0; w < kQrWaves; ++w) r += buf[w * kRB + q];
-        sh.wm[x][y] = r;
-      }
-    }
-    __syncthreads();
-    // row r = q of X = T_old U, then of the new columns:
-    // T(0:kk, kk) = -tau_kk T(0:kk, 0:kk) [U(:, j); Wm(0:j, j)], T(kk, kk) = tau_kk
-    double xr[kPanel];
-#pragma unroll
-    for (int j = 0; j < kPanel; ++j) xr[j] = 0.0;
-    if (q < k0) {
-      int l = q;
-      for (; l + 8 <= k0; l += 8) {
-        double tv[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u) tv[u] = T[(int64_t)(l + u) * m + q];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-#pragma unroll
-          for (int j = 0; j < kPanel; ++j) xr[j] += tv[u] * AU[(l + u) * kPanel + j];
-      }
-      for (; l < k0; ++l) {
-        const double tv = T[(int64_t)l * m + q];
-#pragma unroll
-        for (int j = 0; j < kPanel; ++j) xr[j] += tv * AU[l * kPanel + j];
-      }
-    }
-#pragma unroll
-    for (int j = 0; j < kPanel; ++j) {
-      const int kk = k0 + j;
-      if (q < kk) {
-        double acc = xr[j];
-#pragma unroll
-        for (int jj = 0; jj < j; ++jj)
-          if (q <= k0 + jj) acc += tn[jj] * sh.wm[jj][j];
-        tn[j] = -sh.tau[j] * acc;
-      } else if (q == kk) {
-        tn[j] = sh.tau[j];
-      }
-    }
+  if (t == 0) {
+    ctl->stop_k = stop_k;
+    ctl->stop_step = stop_step;
+    ctl->stop_reason = stop_reason;
+    ctl->qr_k = qr_k;
+    ctl->error = err;
+    ctl->ice_smax = smax;
+    ctl->ice_znorm = znorm;
+    ctl->cond_cur = cond_cur;
+    ctl->cond_prev = cond_prev;
+    ctl->rho_cur = rho_cur;
+    ctl->rho_prev = rho_prev;
   }
+  __syncthreads();  // sh.tau, sh.beta and the panel rows for the write-back
 
-  // ---- write back ---------------------------------------------------------
+  // ---- write back (V, R and tau of the formed columns; d; x and z) --------
   for (int j = 0; j < ndone; ++j) {
     const int kk = k0 + j;
-    const double cj = row ? Cp[j * s + q] : 0.0;
-    if (row) a.V[(int64_t)kk * s + q] = q < kk ? 0.0 : cj;
-    if (q < kk) a.R[(int64_t)kk * m + q] = cj;
-  }
-  if (q >= k0 && q < done) {
-    a.R[(int64_t)q * m + q] = sh.beta[q - k0];
-    a.tau[q] = sh.tau[q - k0];
-  }
-  if (!stopped) {
 #pragma unroll
-    for (int j = 0; j < kPanel; ++j)
-      if (j < p && q <= k0 + j) a.T[(int64_t)(k0 + j) * m + q] = tn[j];
+    for (int u = 0; u < kRowsPT; ++u) {
+      const int r = t + u * kPanelThreads;
+      if (r < s) {
+        const double cjr = Cp[j * s + r];
+        a.V[(int64_t)kk * s + r] = r < kk ? 0.0 : cjr;
+        if (r < kk) a.R[(int64_t)kk * m + r] = cjr;
+      }
+    }
   }
-  if (row) a.d[q] = dv[q];
-  if (q < done) {
-    a.ice_x[q] = xv[q];
-    a.ice_z[q] = zv[q];
+#pragma unroll
+  for (int u = 0; u < kRowsPT; ++u) {
+    const int r = t + u * kPanelThreads;
+    if (r < s) a.d[r] = dv[r];
+    if (r >= k0 && r < done) {
+      a.R[(int64_t)r * m + r] = sh.beta[r - k0];
+      a.tau[r] = sh.tau[r - k0];
+    }
+    if (r < done) {
+      a.ice_x[r] = xv[r];
+      a.ice_z[r] = zv[r];
+    }
+  }
+  if (t == 0) {
+    (void)stopped;
+    host_store_i32(&a.hs->stop_k, stop_k);
+    host_store_i32(&a.hs->stop_step, stop_step);
+    host_store_i32(&a.hs->stop_reason, stop_reason);
+    host_store_i32(&a.hs->error, err);
+    host_store_i32(&a.hs->steps_run, k0 + p);
+    host_store_i32(&a.hs->inner_step_done, done);
   }
 }
 

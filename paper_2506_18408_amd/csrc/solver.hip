@@ -545,6 +545,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
         QrBlockArgs q = qa;
         q.k0 = panel0;
         q.ncols = ncols;
+        q.pprev = panel0 > 0 ? pc : 0;  // every panel before the last is full
         SFG_HIP(launch_qr_block(q, st));
         panel0 = i + 1;
       }

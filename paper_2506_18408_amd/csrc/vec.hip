@@ -373,10 +373,15 @@ hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double*
 // ----------------------------------------------- small triangular solves
 // y = R^{-1} d[0:k] for the inner dimension k chosen on the device, then
 // y_l * sigma_l so that z_j = sum_l y_l u_l over the unnormalised vectors.
-// Columns of R are staged into LDS kFinChunk at a time, so their loads
-// overlap; the substitution itself is one column per barrier.
+// When the upper triangle of R_k fits in LDS it is loaded there at once by
+// the whole workgroup and wave 0 substitutes alone (lane p owning rows p,
+// p + 64, ...; the right-hand side stays in registers, no barrier per
+// column); otherwise columns are staged kFinChunk at a time with one
+// barrier per column.
 constexpr int kFinThreads = 256;
 constexpr int kFinChunk = 8;
+constexpr int kFinRows = kMaxM / kWave;
+constexpr int kFinLds = 12288;  // doubles of R held in LDS (k x k block: k <= 110)
 
 __global__ __launch_bounds__(kFinThreads) void k_finalize(const DevCtl* ctl, const double* R,
                                                           const double* d, const double* sigma,
@@ -384,9 +389,59 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const DevCtl* ctl, con
   __shared__ double rhs[kMaxM];
   __shared__ double ys[kMaxM];
   __shared__ double col[kFinChunk][kMaxM];
+  __shared__ double tri[kFinLds];  // R[0:k, 0:k], column l at l * k
   const int k = ctl->stop_k;
   if (k <= 0 || k > m) return;
   const int tid = threadIdx.x;
+  if (k * k <= kFinLds) {
+    // the k x k block at once (entries below the diagonal are read, unused)
+    constexpr int kB = 8;
+    for (int i0 = 0; i0 < k * k; i0 += kFinThreads * kB) {
+      double v[kB];
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        const int i = i0 + b * kFinThreads + tid;
+        v[b] = i < k * k ? R[(int64_t)(i / k) * m + i % k] : 0.0;
+      }
+#pragma unroll
+      for (int b = 0; b < kB; ++b) {
+        const int i = i0 + b * kFinThreads + tid;
+        if (i < k * k) tri[i] = v[b];
+      }
+    }
+    __syncthreads();
+    if (tid >= kWave) return;
+    const int lane = tid;
+    double r[kFinRows], yv[kFinRows];
+#pragma unroll
+    for (int u = 0; u < kFinRows; ++u) {
+      const int p = lane + u * kWave;
+      r[u] = p < k ? d[p] : 0.0;
+      yv[u] = 0.0;
+    }
+    for (int l = k - 1; l >= 0; --l) {
+      const double* cl = tri + l * k;
+      const int ul = l / kWave;
+      double dl = 0.0, rl = 0.0;
+#pragma unroll
+      for (int u = 0; u < kFinRows; ++u)
+        if (u == ul) rl = r[u];
+      dl = cl[l];  // (same address in every lane)
+      const double yl = read_lane(rl, l % kWave) / dl;
+#pragma unroll
+      for (int u = 0; u < kFinRows; ++u) {
+        const int p = lane + u * kWave;
+        if (p == l) yv[u] = yl;
+        if (p < l) r[u] -= cl[p] * yl;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kFinRows; ++u) {
+      const int p = lane + u * kWave;
+      if (p < k) y[p] = yv[u] * sigma[p];
+    }
+    return;
+  }
   for (int p = tid; p < k; p += kFinThreads) rhs[p] = d[p];
   for (int hi = k - 1; hi >= 0; hi -= kFinChunk) {
     const int lo = hi - kFinChunk + 1 > 0 ? hi - kFinChunk + 1 : 0;
