@@ -44,9 +44,10 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # HBM bytes per dispatch of the fused kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (KiB), each scaled by the factor measured on a plain device copy
-# of known size (bench.py --copy-calibration).  None until measured for the
-# current kernel.
-PMC_TRAFFIC_BYTES = None
+# of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 + WRITE_SIZE x
+# 1.0, averaged over the working dispatches of one FP64 solve.  Valid only for
+# the kernel source it was measured on; None whenever that kernel changes.
+PMC_TRAFFIC_BYTES = 274997248
 
 
 def log(*a):
