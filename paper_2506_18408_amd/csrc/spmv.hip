@@ -108,6 +108,18 @@ hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, i
   return hipGetLastError();
 }
 
+// Doubles of LDS per wave: the staged products (padded so that a row's
+// first kShortRow products can be read without a bound), then, when
+// sketching, the s sketch accumulators and one slot that absorbs the empty
+// entries of the packed sketch.
+__host__ __device__ constexpr int wave_lds_doubles(int s) {
+  return kWStage + kShortRow + (s > 0 ? s + 1 : 0);
+}
+
+// s_waitcnt operand that waits for every outstanding vector memory access
+// only (gfx9 encoding: vmcnt 0, expcnt 7, lgkmcnt 15).
+constexpr int kWaitVmem0 = 0x0F70;
+
 // Ordering of a wave's own LDS accesses across lanes (the hardware runs a
 // wave's LDS instructions in order; this keeps the compiler from moving
 // accesses across the point).
@@ -129,11 +141,12 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
-  const int wv = tid / kWave;
+  const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);  // (uniform: scalar loop control)
   const int nw = blockDim.x / kWave;
   const int S = kSketch ? a.s : 0;
-  double* const prod = lds + (size_t)wv * (kWStage + S);
-  double* const wave_sk = prod + kWStage;
+  const int wstride = wave_lds_doubles(S);
+  double* const prod = lds + (size_t)wv * wstride;
+  double* const wave_sk = prod + kWStage + kShortRow;
   // this wave's tiles: workgroups take contiguous ranges (XCD-grouped);
   // inside a range the waves take every nw-th tile, so the waves of a CU
   // work on neighbouring tiles at the same time (shared DRAM pages and
@@ -156,7 +169,7 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   const int nwin = NW < a.nwin ? NW : a.nwin;
 
   if (kSketch)
-    for (int q = lane; q < S; q += kWave) wave_sk[q] = 0.0;
+    for (int q = lane; q <= S; q += kWave) wave_sk[q] = 0.0;
 
   double dacc[NW > 0 ? NW : 1];
 #pragma unroll
@@ -195,11 +208,11 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
                                  p.sk[b].y >> 16};
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            if (f[e] != kSkEmpty) {
-              const double av = (f[e] & 0x8000u) ? -wd : wd;
-              __hip_atomic_fetch_add(&wave_sk[f[e] & 0x7FFFu], av, __ATOMIC_RELAXED,
-                                     __HIP_MEMORY_SCOPE_WORKGROUP);
-            }
+            // (an empty entry lands in the spare slot S)
+            const int row = f[e] == kSkEmpty ? S : (int)(f[e] & 0x7FFFu);
+            const double av = (f[e] & 0x8000u) ? -wd : wd;
+            __hip_atomic_fetch_add(&wave_sk[row], av, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_WORKGROUP);
           }
         }
       }
@@ -223,46 +236,69 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
     }
   };
 
-  // Per tile: the x entries of its nonzeros, its row bounds and the epilogue
-  // inputs of its rows are requested together, while the column indices and
-  // values of the next tile are already on their way (raw VT values stay in
-  // registers until use, so no load is waited for before it is needed).
-  // With wide windows or sketch columns the next tile's values are loaded
-  // with its gathers instead of with its indices (!kAhead).
-  constexpr bool kAhead = sizeof(VT) == 4 ? (NW <= 4 || ZB <= 2) : (NW <= 2 && ZB <= 2);
+  // Software pipeline over this wave's tiles; iteration i reduces tile i
+  // while the column indices of tile i+2, the values and x entries of tile
+  // i+1 and the epilogue inputs of tile i+1 are in flight.  Every request is made a whole iteration before its first use,
+  // so a wave waits once per tile.  All lanes load (indices clamped into the
+  // tile), so no load sits behind a lane-divergent branch.
+  struct TileB {
+    int r0, r1, p0, L;
+  };
+  // the bounds of this wave's tiles, 64 at a time: lane j holds those of its
+  // tile 64 c + j; taken with readlane.  A chunk is loaded where nothing else
+  // is outstanding and waited for at once, so the common path never waits.
+  int ch_r0 = 0, ch_r1 = 0, ch_p0 = 0, ch_p1 = 0;
+  const int nt = t0 < t1 ? (t1 - t0 + nw - 1) / nw : 0;
+  auto load_chunk = [&](int c) {
+    int tj = t0 + (c * kWave + lane) * nw;
+    tj = tj < t1 ? tj : t1 - 1;
+    ch_r0 = a.tiles[tj];
+    ch_r1 = a.tiles[tj + 1];
+    ch_p0 = a.tp[tj];
+    ch_p1 = a.tp[tj + 1];
+    __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+  };
+  auto tile_bounds = [&](int j) {
+    TileB bt;
+    bt.r0 = __builtin_amdgcn_readlane(ch_r0, j & 63);
+    bt.r1 = __builtin_amdgcn_readlane(ch_r1, j & 63);
+    bt.p0 = __builtin_amdgcn_readlane(ch_p0, j & 63);
+    bt.L = __builtin_amdgcn_readlane(ch_p1, j & 63) - bt.p0;
+    return bt;
+  };
+  auto staged = [&](const TileB& bt) { return has_x && bt.L > 0 && bt.L <= kWStage; };
   int ci[kU];
-  VT vn[kU], vg[kU], xg[kU];
-  int f_r0 = 0, f_r1 = 0, f_p0 = 0, f_L = 0;  // fetched tile
-  int g_r0 = 0, g_r1 = 0, g_p0 = 0, g_L = 0;  // gathered tile
-  auto fetch = [&](int tl) {
-    f_r0 = a.tiles[tl];
-    f_r1 = a.tiles[tl + 1];
-    f_p0 = a.tp[tl];
-    f_L = a.tp[tl + 1] - f_p0;
-    if (has_x && f_L <= kWStage) {
+  VT vg[kU], xg[kU];
+  // (full blocks of 64 entries at fixed offsets from one address; the last,
+  // partial block with its index clamped into the tile).  Ordinary loads: the
+  // matrix is read again by every inner step, and the chip's last-level
+  // cache keeps much of it between steps; streaming (non-temporal) loads
+  // made each FP64 step ~10% slower.
+  auto fetch = [&](const TileB& bt) {  // column indices
+    if (!staged(bt)) return;
+    const int32_t* cb = col_idx + bt.p0 + lane;
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kU; ++u) {
+      if ((u + 1) * kWave <= bt.L) {
+        ci[u] = *(cb + u * kWave);
+      } else if (u * kWave < bt.L) {
         const int q = u * kWave + lane;
-        if (q < f_L) {
-          ci[u] = __builtin_nontemporal_load(&col_idx[f_p0 + q]);
-          if (kAhead) vn[u] = __builtin_nontemporal_load(&val[f_p0 + q]);
-        }
+        ci[u] = col_idx[bt.p0 + (q < bt.L ? q : bt.L - 1)];
       }
     }
   };
-  auto gather = [&]() {  // fetched -> gathered: values and x entries
-    g_r0 = f_r0;
-    g_r1 = f_r1;
-    g_p0 = f_p0;
-    g_L = f_L;
-    if (has_x && g_L <= kWStage) {
+  auto gather = [&](const TileB& bt) {  // values and x entries
+    if (!staged(bt)) return;
+    const VT* vb = val + bt.p0 + lane;
 #pragma unroll
-      for (int u = 0; u < kU; ++u) {
+    for (int u = 0; u < kU; ++u) {
+      if ((u + 1) * kWave <= bt.L) {
+        vg[u] = *(vb + u * kWave);
+        xg[u] = x[ci[u]];
+      } else if (u * kWave < bt.L) {
         const int q = u * kWave + lane;
-        if (q < g_L) {
-          vg[u] = kAhead ? vn[u] : __builtin_nontemporal_load(&val[g_p0 + q]);
-          xg[u] = x[ci[u]];
-        }
+        vg[u] = val[bt.p0 + (q < bt.L ? q : bt.L - 1)];
+        xg[u] = x[ci[u]];
       }
     }
   };
@@ -272,40 +308,25 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
     while (gsz < kWave && nrows * gsz * 2 <= kWave) gsz <<= 1;
     return gsz;
   };
-  // epilogue inputs of the first row of this lane's group in the gathered tile
+  // epilogue inputs of the first row of this lane's group
   struct Epi {
     Pre pre;
     int q0, q1;
   };
-  Epi cur{};
-  auto epi_load = [&](Epi& e) {
-    const int nrows = g_r1 - g_r0;
-    if (nrows <= 0 || g_L > kWStage) return;
-    const int gsz = group_size(nrows);
-    const int grp = lane / gsz;
-    if (grp < nrows) {
-      const int r = g_r0 + grp;
-      e.q0 = row_ptr[r];
-      e.q1 = row_ptr[r + 1];
-      if ((lane & (gsz - 1)) == 0) load_pre(r, e.pre);
-    }
+  Epi ecur{};
+  auto epi_load = [&](const TileB& bt) {
+    const int nrows = bt.r1 - bt.r0;
+    if (nrows <= 0 || bt.L > kWStage) return;
+    const int grp = lane / group_size(nrows);
+    const int r = bt.r0 + (grp < nrows ? grp : nrows - 1);
+    ecur.q0 = row_ptr[r];
+    ecur.q1 = row_ptr[r + 1];
+    load_pre(r, ecur.pre);
   };
-  if (t0 < t1) fetch(t0);
-  for (int tl = t0; tl < t1; tl += nw) {
-    gather();
-    if (tl + nw < t1) fetch(tl + nw);
-    epi_load(cur);
-    const int r0 = g_r0, r1 = g_r1, p0 = g_p0, L = g_L;
-    if (r0 >= r1) continue;
+  auto reduce = [&](const TileB& bt) {
+    const int r0 = bt.r0, r1 = bt.r1, p0 = bt.p0, L = bt.L;
+    if (r0 >= r1) return;
     if (L <= kWStage) {
-      if (has_x) {
-#pragma unroll
-        for (int u = 0; u < kU; ++u) {
-          const int q = u * kWave + lane;
-          if (q < L) prod[q] = static_cast<double>(vg[u]) * static_cast<double>(xg[u]);
-        }
-      }
-      wave_sync();
       const int nrows = r1 - r0;
       const int gsz = group_size(nrows);
       const int ngroups = kWave / gsz;
@@ -313,14 +334,26 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
       const int gl = lane & (gsz - 1);
       auto row_sum = [&](int qa, int qe) {
         double acc = 0.0;
-        if (has_x)
-          for (int q = qa + gl; q < qe; q += gsz) acc += prod[q];
+        if (!has_x) return acc;
+        if (gsz == 1) {
+          // the first kShortRow products requested together (the stage is
+          // padded by kShortRow), added in order
+          double v[kShortRow];
+#pragma unroll
+          for (int k = 0; k < kShortRow; ++k) v[k] = prod[qa + k];
+#pragma unroll
+          for (int k = 0; k < kShortRow; ++k)
+            if (qa + k < qe) acc += v[k];
+          for (int q = qa + kShortRow; q < qe; ++q) acc += prod[q];
+          return acc;
+        }
+        for (int q = qa + gl; q < qe; q += gsz) acc += prod[q];
         for (int off = gsz >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
         return acc;
       };
       if (grp < nrows) {
-        const double acc = row_sum(cur.q0 - p0, cur.q1 - p0);
-        if (gl == 0) epilogue(r0 + grp, acc, cur.pre);
+        const double acc = row_sum(ecur.q0 - p0, ecur.q1 - p0);
+        if (gl == 0) epilogue(r0 + grp, acc, ecur.pre);
       }
       for (int rr = grp + ngroups; rr < nrows; rr += ngroups) {  // (only with > 64 rows)
         const int r = r0 + rr;
@@ -329,7 +362,6 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
         const double acc = row_sum(row_ptr[r] - p0, row_ptr[r + 1] - p0);
         if (gl == 0) epilogue(r, acc, pre);
       }
-      wave_sync();
     } else {
       // a tile whose rows exceed the stage: the whole wave per row
       for (int r = r0; r < r1; ++r) {
@@ -348,6 +380,44 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
         }
       }
     }
+  };
+
+  TileB bc{}, bg{}, bf{};
+  if (nt > 0) {
+    load_chunk(0);
+    bg = tile_bounds(0);
+    fetch(bg);
+    gather(bg);
+    epi_load(bg);
+  }
+  if (nt > 1) {
+    bf = tile_bounds(1);
+    fetch(bf);
+  }
+  for (int i = 0; i < nt; ++i) {
+    // the one wait of the iteration: every request of the previous one
+    // (vector memory count 0; export and LDS/scalar counts left alone)
+    __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+    if (i + 2 < nt && ((i + 2) & 63) == 0) load_chunk((i + 2) >> 6);
+    bc = bg;
+    if (staged(bc)) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u)
+        if (u * kWave < bc.L)
+          prod[u * kWave + lane] = static_cast<double>(vg[u]) * static_cast<double>(xg[u]);
+    }
+    if (i + 1 < nt) {
+      bg = bf;
+      gather(bg);
+    }
+    if (i + 2 < nt) {
+      bf = tile_bounds(i + 2);
+      fetch(bf);
+    }
+    wave_sync();
+    reduce(bc);
+    if (i + 1 < nt) epi_load(bg);
+    wave_sync();
   }
 
   // one sketch row and one scalar row of partial sums per workgroup (fixed
@@ -356,8 +426,9 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   if constexpr (kSketch) {
     double* prow = a.part + (int64_t)blockIdx.x * S;
     for (int q = tid; q < S; q += blockDim.x) {
-      double v = lds[kWStage + q];
-      for (int k = 1; k < nw; ++k) v += lds[(size_t)k * (kWStage + S) + kWStage + q];
+      const double* sk0 = lds + kWStage + kShortRow + q;  // wave 0's copy
+      double v = sk0[0];
+      for (int k = 1; k < nw; ++k) v += sk0[(size_t)k * wstride];
       prow[q] = v;
     }
   }
@@ -411,7 +482,7 @@ static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
 
 template <typename VT, int MODE, int NW>
 static hipError_t launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
-  const size_t per_wave = (size_t)(kWStage + (zb > 0 ? a.s : 0)) * sizeof(double);
+  const size_t per_wave = (size_t)wave_lds_doubles(zb > 0 ? a.s : 0) * sizeof(double);
   c.waves = spmv_waves(zb > 0 ? a.s : 0);
   c.lds = per_wave * c.waves;
   switch (zb) {
@@ -437,7 +508,7 @@ static hipError_t launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) 
 }
 
 int spmv_waves(int s) {
-  const size_t per_wave = (size_t)(kWStage + s) * sizeof(double);
+  const size_t per_wave = (size_t)wave_lds_doubles(s) * sizeof(double);
   int nw = kSpmvMaxWaves;
   while (nw > 1 && per_wave * nw > (size_t)kSpmvLdsMax) nw >>= 1;
   return nw;
