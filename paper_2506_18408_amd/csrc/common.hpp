@@ -32,7 +32,7 @@ constexpr int kMaxM = SFGMRES_MAX_M;
 // nonzeros always fit the stage (longer rows take a slower per-row path).
 constexpr int kSpmvMaxWaves = 16;
 constexpr int kSpmvMaxThreads = kSpmvMaxWaves * 64;
-constexpr int kSpmvGrid = 256;
+constexpr int kSpmvGrid = 248;  // one CU per XCD left for the decision kernel
 constexpr int kWStage = 512;
 constexpr int kShortRow = 8;
 constexpr int kRowTile = kWStage / kShortRow;

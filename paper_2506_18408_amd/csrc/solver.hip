@@ -7,13 +7,16 @@
 // normalised v_{j+1} with its sketch.
 //
 // The inner steps run on the caller's stream.  Step i is the fused SpMV
-// y = A u_i (+ S y as per-workgroup partial rows in ring slot i mod p, the
-// window dots and ||y||^2 as scalar rows), the one-workgroup coefficient
-// kernel (sigma_i and the window coefficients) and, for t > 0, the
-// truncated-Arnoldi update u_{i+1}.  After every p steps (a panel), one
-// reduction sums the panel's sketch rows and one decision kernel appends its
-// p columns to the sketched QR and decides after each column (C1-C3);
-// only it ends the cycle, so up to p - 1 steps past the stop are computed
+// y = A u_i (+ S y as per-workgroup partial rows in ring slot i mod 2p, the
+// window dots and ||y||^2 as scalar rows) and, for t > 0, the
+// truncated-Arnoldi update u_{i+1} with its own coefficients (else a
+// one-workgroup coefficient kernel).  After every p steps (a panel), a
+// second stream reduces the panel's sketch rows and runs one decision
+// kernel that appends its p columns to the sketched QR and decides after
+// each column (C1-C3), while the caller's stream goes on with the next
+// steps; the SpMV grid leaves a CU per XCD free for it.  Only the decision
+// ends the cycle, so the steps between the stop and the moment the flag is
+// seen (up to p - 1 inside the panel, and about one past it) are computed
 // and discarded.  The inner basis is kept unnormalised (u_i = the
 // orthogonalised A b_{i-1}, of norm h_{i,i-1}, with sigma_i = 1/||u_i|| held
 // on the device), so no kernel waits for a scalar its predecessor has just
@@ -40,6 +43,8 @@ struct sfgmres_ctx {
   sfg::HostStatus* hs_dev = nullptr;
   std::string err;
   std::vector<hipEvent_t> ev;  // timing events (profile option)
+  hipStream_t dec = nullptr;    // the decision stream (slot reductions, sketched QR)
+  std::vector<hipEvent_t> sync; // panel hand-over events (no timing)
 };
 
 namespace sfg {
@@ -72,10 +77,10 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.tiles = take((size_t)(L.ntiles_max + 1) * 4);
   L.tp = take((size_t)(L.ntiles_max + 1) * 4);
   L.ipart = take((size_t)(kVecGrid + 1) * 4);
-  L.part = take((size_t)panel * kMaxGrid * s * 8);
+  L.part = take((size_t)2 * panel * kMaxGrid * s * 8);  // two panels of sketch rows
   L.dpart = take((size_t)kMaxGrid * kDP * 8);
   L.vpart = take((size_t)2 * kVecGrid * 8);  // two: read by one Arnoldi update, written by it
-  L.red = take((size_t)panel * s * 8);
+  L.red = take((size_t)2 * panel * s * 8);
   L.skp = take(packed_sketch_bytes(n, zeta));
   L.qr_V = take((size_t)s * m * 8);
   L.qr_T = take((size_t)m * m * 8);
@@ -322,6 +327,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const uint32_t k1 = (uint32_t)(seed >> 32);
   const double inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
   const int lookahead = lookahead_steps(o);
+  const int nring = 2 * pc;                         // ring of two panels
   const int64_t slot_part = (int64_t)kMaxGrid * s;  // ring slot of sketch rows
   const int64_t slot_red = s;                       // ring slot of reduced rows
   HostStatus* hsd = h->hs_dev;
@@ -340,6 +346,17 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     info->spmv_ms = 0.0;
     info->spmv_launches = 0;
   }
+  // hand-over events: per panel, "its steps are enqueued" and "its rows are
+  // reduced", then one for the last decision
+  const int npanels = (m + pc - 1) / pc;
+  while ((int)h->sync.size() < 2 * npanels + 1) {
+    hipEvent_t e;
+    SFG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    h->sync.push_back(e);
+  }
+  hipEvent_t* ev_steps = h->sync.data();
+  hipEvent_t* ev_red = h->sync.data() + npanels;
+  hipEvent_t ev_dec = h->sync[2 * npanels];
   if (o.profile && (int)h->ev.size() < 2 * m) {
     for (int i = (int)h->ev.size(); i < 2 * m; ++i) {
       hipEvent_t e;
@@ -378,7 +395,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   QrBlockArgs qa{};
   qa.red = P.red;
   qa.slot_red = slot_red;
-  qa.nring = pc;
+  qa.nring = nring;
   qa.s = s;
   qa.m = m;
   qa.t = t;
@@ -400,7 +417,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
                                int32_t forced_k) -> int {
     SFG_HIP(launch_normalize_sketch(f32, Gn, n, W, hptr, vout, Bcol(0), s, P.skp, zb, P.part,
                                     st));
-    SFG_HIP(launch_reduce_slots(P.part, Gn, s, s, 0, 1, pc, slot_part, slot_red, P.red, P.ctl,
+    SFG_HIP(launch_reduce_slots(P.part, Gn, s, s, 0, 1, nring, slot_part, slot_red, P.red, P.ctl,
                                 false, st));
     SFG_HIP(launch_rq_init(P.red, s, inv_sqrt_zeta, forced_k, P.ctl, P.d, P.sigma, st));
     return SFGMRES_OK;
@@ -484,6 +501,9 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       if (hsh->stop_k != 0 || hsh->error != 0) break;
       const int nwin = std::min(t, i + 1);
       const int l0 = i + 1 - nwin;
+      // this step's ring slot was read by the reduction of the panel two
+      // panels back
+      if (i % pc == 0 && i >= nring) SFG_HIP(hipStreamWaitEvent(st, ev_red[i / pc - 2], 0));
       SpmvArgs a = base_args;
       a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
       a.x = Bcol(i);
@@ -496,7 +516,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       a.ldu = ld;
       a.l0 = l0;
       a.nwin = nwin;
-      a.part = P.part + (int64_t)(i % pc) * slot_part;
+      a.part = P.part + (int64_t)(i % nring) * slot_part;
       const bool timed = o.profile > 0 && i % o.profile == o.profile - 1;
       SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st, timed ? h->ev[2 * i] : nullptr,
                           timed ? h->ev[2 * i + 1] : nullptr));
@@ -539,17 +559,28 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
         SFG_HIP(launch_coef(ca, st));
       }
       if (i + 1 - panel0 == pc || i + 1 == m) {
+        // the panel's reduction and decision on the decision stream, after
+        // its steps; the inner steps go on meanwhile (they read the stop
+        // flag at their start, so a decision seen late costs a discarded
+        // step, never a wrong result)
         const int ncols = i + 1 - panel0;
-        SFG_HIP(launch_reduce_slots(P.part, Gp, s, s, panel0 % pc, ncols, pc, slot_part,
-                                    slot_red, P.red, P.ctl, true, st));
+        const int pidx = panel0 / pc;
+        SFG_HIP(hipEventRecord(ev_steps[pidx], st));
+        SFG_HIP(hipStreamWaitEvent(h->dec, ev_steps[pidx], 0));
+        SFG_HIP(launch_reduce_slots(P.part, Gp, s, s, panel0 % nring, ncols, nring, slot_part,
+                                    slot_red, P.red, P.ctl, true, h->dec));
+        SFG_HIP(hipEventRecord(ev_red[pidx], h->dec));
         QrBlockArgs q = qa;
         q.k0 = panel0;
         q.ncols = ncols;
         q.pprev = panel0 > 0 ? pc : 0;  // every panel before the last is full
-        SFG_HIP(launch_qr_block(q, st));
+        SFG_HIP(launch_qr_block(q, h->dec));
+        SFG_HIP(hipEventRecord(ev_dec, h->dec));
         panel0 = i + 1;
       }
     }
+    // the cycle's last decision (and every earlier one) before its results
+    SFG_HIP(hipStreamWaitEvent(st, ev_dec, 0));
     // z_j = B_k y_k
     SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
     SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
@@ -708,6 +739,13 @@ int sfgmres_create(sfgmres_handle* out) {
     return SFGMRES_ERR_HIP;
   }
   c->hs_dev = static_cast<HostStatus*>(dp);
+  // the decision stream: default priority, no implicit ordering with the
+  // null stream
+  if (hipStreamCreateWithFlags(&c->dec, hipStreamNonBlocking) != hipSuccess) {
+    (void)hipHostFree(p);
+    delete c;
+    return SFGMRES_ERR_HIP;
+  }
   *out = c;
   return SFGMRES_OK;
 }
@@ -715,6 +753,8 @@ int sfgmres_create(sfgmres_handle* out) {
 void sfgmres_destroy(sfgmres_handle h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->sync) (void)hipEventDestroy(e);
+  if (h->dec) (void)hipStreamDestroy(h->dec);
   if (h->hs_host) (void)hipHostFree(h->hs_host);
   delete h;
 }

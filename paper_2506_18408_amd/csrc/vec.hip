@@ -68,15 +68,18 @@ __global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
   const int64_t stride = (int64_t)gridDim.x * kVecThreads * kUnroll;
   const int64_t base0 = (int64_t)blockIdx.x * kVecThreads * kUnroll + tid;
 
-  // first stretch of y and the window (independent of the coefficients)
+  // first stretch of y and the window (independent of the coefficients).
+  // y and the oldest window column are read for the last time in the inner
+  // step: streaming loads, so they do not displace the matrix from the
+  // last-level cache
   VT y0[kUnroll], b0[NW][kUnroll];
 #pragma unroll
   for (int u = 0; u < kUnroll; ++u) {
     const int64_t r = base0 + u * kVecThreads;
-    y0[u] = r < n ? W[r] : VT(0);
+    y0[u] = r < n ? __builtin_nontemporal_load(&W[r]) : VT(0);
 #pragma unroll
     for (int l = 0; l < NW; ++l)
-      b0[l][u] = (l < nwin && r < n) ? win[(int64_t)l * a.ldb + r] : VT(0);
+      b0[l][u] = (l < nwin && r < n) ? (l == 0 ? __builtin_nontemporal_load(&win[r]) : win[(int64_t)l * a.ldb + r]) : VT(0);
   }
   // the coefficients
   double v[kNV];
@@ -149,10 +152,10 @@ __global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
       const int64_t r = base + u * kVecThreads;
-      y0[u] = r < n ? W[r] : VT(0);
+      y0[u] = r < n ? __builtin_nontemporal_load(&W[r]) : VT(0);
 #pragma unroll
       for (int l = 0; l < NW; ++l)
-        b0[l][u] = (l < nwin && r < n) ? win[(int64_t)l * a.ldb + r] : VT(0);
+        b0[l][u] = (l < nwin && r < n) ? (l == 0 ? __builtin_nontemporal_load(&win[r]) : win[(int64_t)l * a.ldb + r]) : VT(0);
     }
     update(base, y0, b0);
   }
