@@ -41,12 +41,19 @@ class CSR:
         return sp.csr_matrix((self.val, self.col_idx, self.row_ptr), shape=(self.n, self.n))
 
 
+def _row_col_order(r: np.ndarray, c: np.ndarray, n: int) -> np.ndarray:
+    """Stable permutation that sorts entries by row, then column (the order
+    of np.lexsort((c, r)), from one integer key: an order of magnitude faster
+    at 10^7-10^8 entries)."""
+    return np.argsort(r * np.int64(n) + c, kind="stable")
+
+
 def _assemble(n: int, rows: list, cols: list, vals: list) -> CSR:
     """Assemble CSR from per-offset (row, col, value) arrays; sorts columns."""
     r = np.concatenate(rows).astype(np.int64)
     c = np.concatenate(cols).astype(np.int64)
     v = np.concatenate(vals).astype(np.float64)
-    order = np.lexsort((c, r))
+    order = _row_col_order(r, c, n)
     r, c, v = r[order], c[order], v[order]
     counts = np.bincount(r, minlength=n)
     row_ptr = np.zeros(n + 1, dtype=np.int64)
@@ -167,7 +174,7 @@ def powerlaw_random(n: int, rng: np.random.Generator, Lmin=4, Lmax=256, mean=32.
     cols = cols + (cols >= rows)  # skip the diagonal
     # redraw duplicate (row, col) pairs until every row's columns are distinct
     while True:
-        order = np.lexsort((cols, rows))
+        order = _row_col_order(rows, cols, n)
         rows, cols = rows[order], cols[order]
         dup = np.zeros(rows.shape[0], dtype=bool)
         dup[1:] = (rows[1:] == rows[:-1]) & (cols[1:] == cols[:-1])
