@@ -1,0 +1,185 @@
+"""Full-size runs of the power-law, parameterised-adjoint and 256^3 workloads
+in the launch configuration of the library's defaults (panel width 8,
+lookahead 16), checked against what the oracle or the mathematics fixes at
+that size:
+
+- the first outer step of the 1M power-law system against the oracle (with
+  k_1 = 12, well conditioned, and with the solver's own k_1), residuals
+  recomputed on the CPU, mixed vs FP64 solutions;
+- dL/dtheta and dL/db of the 512^2 parameterised operator through
+  torch.autograd against central differences (FP64 and mixed);
+- the 256^3 variable-coefficient system in mixed precision, forward and
+  adjoint: both true residuals recomputed on the CPU, the duality identity
+  g^T x = lambda^T b within the bound its residuals give, and every entry of
+  dL/dA_ij = -lambda_i x_j, bit-exact.
+"""
+import warnings
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2506_18408_amd as P
+import workloads as W
+from tests.gpu_common import requires_gpu, to_dev, tvec, hist_close
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+@pytest.fixture(scope="module")
+def c3():
+    A, b, p = W.make_workload(3)
+    return A, b, p, A.to_scipy()
+
+
+def _params(p, **kw):
+    prm = dict(m=p["m"], t=p["t"], s=p["s"], zeta=p["zeta"], tol=p["tol"], seed=p["seed"],
+               max_outer=p["max_outer"])
+    prm.update(kw)
+    return prm
+
+
+def _true_rel(As, b, x):
+    return float(np.linalg.norm(b - As @ x) / np.linalg.norm(b))
+
+
+KAPPA_STRICT = 1e7  # u * KAPPA_STRICT ~ 2e-9: rounding of y stays below the parity bar
+
+
+def _replay(A, As, b, p, k):
+    """The first outer step with k_1 = k on both sides."""
+    r = oracle.sfgmres(As, b, m=p["m"], t=p["t"], s=p["s"], zeta=p["zeta"], tol=p["tol"],
+                       seed=p["seed"], max_outer=1, forced_k=[k], record_true_residual=False)
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        x, info = P.solve(*to_dev(A), tvec(b), forced_k=[k], **_params(p, max_outer=1))
+    return x.cpu().numpy(), info, r
+
+
+def test_full_size_c3_fp64_first_step_and_properties(c3):
+    A, b, p, As = c3
+    x, info = P.solve(*to_dev(A), tvec(b), **_params(p))
+    assert info["converged"]
+    xn = x.cpu().numpy()
+    tr = _true_rel(As, b, xn)
+    assert tr <= p["tol"] * (1 + 1e-4)
+    assert abs(tr - info["true_rel_residual"]) <= 1e-6 * tr
+    h = info["residual_history"]
+    assert np.all(h[1:] <= h[:-1])
+    g = np.asarray(info["cond_at_stop"])
+    assert np.all((g >= 1.0 - 1e-12) & (g <= 1e15 * (1.0 + 1e-12))), g
+    # strict parity at full size where the inner least-squares problem is
+    # well conditioned: the first outer step with k_1 = 12
+    x12, i12, r12 = _replay(A, As, b, p, 12)
+    assert max(i12["cond_at_stop"][0], r12.cond_at_stop[0]) <= KAPPA_STRICT
+    hist_close(i12["residual_history"], r12.residual_history)
+    assert np.linalg.norm(x12 - r12.x) <= 1e-9 * np.linalg.norm(r12.x)
+    # the solver's own first cycle (k_1 as the GPU chose it): strict while its
+    # problem is well conditioned, else the same curve within an order of
+    # magnitude (the two sides then precondition with different, equally
+    # valid vectors)
+    k1 = int(info["inner_k"][0])
+    x1, i1, r1 = _replay(A, As, b, p, k1)
+    if max(i1["cond_at_stop"][0], r1.cond_at_stop[0]) <= KAPPA_STRICT:
+        hist_close(i1["residual_history"], r1.residual_history)
+        assert np.linalg.norm(x1 - r1.x) <= 1e-9 * np.linalg.norm(r1.x)
+    else:
+        assert abs(np.log(i1["residual_history"][1] / r1.residual_history[1])) <= np.log(10.0)
+
+
+def test_full_size_c3_mixed_vs_fp64(c3):
+    """Mixed precision (FP32 matrix values, basis and inner SpMV; FP64 sketch
+    accumulation, QR and outer loop) reaches the same tolerance on the true
+    residual.  Both solutions satisfy ||b - A x|| <= tol ||b||, so they differ
+    by at most 2 tol ||A^-1|| ||b||; with the smallest singular value of this
+    strictly diagonally dominant matrix bounded below by one (diagonal =
+    off-diagonal row sum + 1, so ||A^-1||_inf <= 1 and ||A^-1||_2 <= sqrt(n)),
+    ||x_mixed - x_fp64|| <= 2 tol sqrt(n) ||b||."""
+    A, b, p, As = c3
+    prm = _params(p)
+    dA = to_dev(A)
+    x64, _ = P.solve(*dA, tvec(b), **prm)
+    xm, im = P.solve(*dA, tvec(b), precision="mixed", **prm)
+    assert im["converged"]
+    xmn = xm.cpu().numpy()
+    tr = _true_rel(As, b, xmn)
+    assert tr <= p["tol"] * (1 + 1e-4)
+    diff = np.linalg.norm(xmn - x64.cpu().numpy())
+    assert diff <= 2 * p["tol"] * (1 + 1e-4) * np.sqrt(A.n) * np.linalg.norm(b)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_full_size_c4_autograd_finite_differences(precision):
+    """The 512^2 operator A(theta): dL/dtheta (through the matrix values) and
+    dL/db of L = ||x - x_target||^2 against central differences.  The solves
+    run at tol 1e-12 so that the differences resolve the derivative (the
+    workload's 1e-8 would leave errors of about tol / h).  L is quadratic in
+    b, so its central difference in b is exact for any step: a step of 1
+    keeps the solves' own errors small against the difference; in theta the
+    step 1e-3 leaves a truncation error of order 1e-6 relative."""
+    A, b, p = W.make_workload(4)
+    lap, ux, uy, patch = p["parts"]
+    d = torch.device("cuda:0")
+    rp = torch.from_numpy(A.row_ptr).to(d)
+    ci = torch.from_numpy(A.col_idx).to(d)
+    lapt, uxt, uyt = (torch.from_numpy(a).to(d) for a in (lap, ux, uy))
+    pt = torch.from_numpy(patch).to(d)
+    theta0 = torch.from_numpy(p["theta"]).to(d)
+    bt = tvec(b)
+    xt = tvec(p["x_target"])
+    prm = P.SolveParams(m=p["m"], t=p["t"], s=p["s"], zeta=p["zeta"], tol=1e-12, seed=p["seed"],
+                        max_outer=300, precision=precision)
+
+    def loss(theta, bb):
+        val = W.theta_convdiff2d_values(theta, lapt, uxt, uyt, pt)
+        x = P.sfgmres_solve(rp, ci, val, bb, prm)
+        return ((x - xt) ** 2).sum()
+
+    th = theta0.clone().requires_grad_(True)
+    bb = bt.clone().requires_grad_(True)
+    loss(th, bb).backward()
+    gth = th.grad.cpu().numpy()
+    gb = bb.grad.cpu().numpy()
+    h = 1e-3
+    for k in [0, 27, 63]:
+        e = torch.zeros_like(theta0)
+        e[k] = h
+        with torch.no_grad():
+            fd = (loss(theta0 + e, bt) - loss(theta0 - e, bt)).item() / (2 * h)
+        assert abs(fd - gth[k]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gth).max())
+    for i in [0, 131_071, A.n - 1]:
+        e = torch.zeros_like(bt)
+        e[i] = 1.0
+        with torch.no_grad():
+            fd = (loss(theta0, bt + e) - loss(theta0, bt - e)).item() / 2.0
+        assert abs(fd - gb[i]) <= 1e-5 * max(abs(fd), 1e-3 * np.abs(gb).max())
+
+
+def test_full_size_c5_mixed_forward_and_adjoint():
+    A, b, p = W.make_workload(5)
+    As = A.to_scipy()
+    prm = _params(p, precision="mixed")
+    dA = to_dev(A)
+    x, info = P.solve(*dA, tvec(b), **prm)
+    assert info["converged"]
+    xn = x.cpu().numpy()
+    rx = b - As @ xn
+    assert np.linalg.norm(rx) <= p["tol"] * (1 + 1e-4) * np.linalg.norm(b)
+    assert np.all(info["residual_history"][1:] <= info["residual_history"][:-1])
+    # adjoint with the gradient of ||x - x_target||^2
+    xt = np.random.default_rng([5, 3]).uniform(-1.0, 1.0, A.n)
+    g = 2.0 * (xn - xt)
+    lam, gv, ia = P.solve_adjoint(*dA, tvec(g), x, **prm)
+    assert ia["converged"]
+    ln = lam.cpu().numpy()
+    rl = g - As.T @ ln
+    assert np.linalg.norm(rl) <= p["tol"] * (1 + 1e-4) * np.linalg.norm(g)
+    # g^T x - lambda^T b = r_lambda^T x - lambda^T r_x exactly, so its size is
+    # bounded by the two residuals (plus the rounding of the two n-term dots)
+    lhs = abs(float(g @ xn) - float(ln @ b))
+    bound = np.linalg.norm(rl) * np.linalg.norm(xn) + np.linalg.norm(ln) * np.linalg.norm(rx)
+    eps_dot = 4 * A.n * np.finfo(float).eps * (np.abs(g) @ np.abs(xn) + np.abs(ln) @ np.abs(b))
+    assert lhs <= 1.01 * bound + eps_dot
+    # dL/dA_ij = -lambda_i x_j on all 117M nonzeros, bit-exact
+    assert np.array_equal(gv.cpu().numpy(), oracle.adjoint_gradient(A.row_ptr, A.col_idx, ln, xn))
