@@ -62,6 +62,10 @@ def parse():
     ap.add_argument("--grid", type=int, default=128, help="grid points per axis (128 = the benchmark workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
+    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
+                    help="2 = the benchmark line (128^3); 3 = 1M power-law (FP64 and mixed), "
+                         "4 = 512^2 parameterised operator and 5 = 256^3 variable coefficients "
+                         "(forward and adjoint): informational timings of the other workloads")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -100,6 +104,83 @@ def window_sum(inner_k, stop_reason, t, m, panel=8, stride=PROFILE_STRIDE):
     return tot, launches
 
 
+def fused_rate(infos, A, t, m, zeta, fp32):
+    """Mean duration of the timed working fused launches and their algorithmic
+    bytes (matrix, row pointers, x, y, window, packed sketch)."""
+    launches = sum(i["spmv_launches"] for i in infos)
+    ms = sum(i["spmv_ms"] for i in infos)
+    win = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in infos)
+    vb = 4 if fp32 else 8
+    zb = (zeta + 3) // 4
+    nbytes = (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches) + 8 * zb * A.n
+    avg = ms * 1e-3 / launches
+    return avg, nbytes
+
+
+def other_workload(args):
+    """Solve times of one of the other workloads (not the benchmark line)."""
+    import torch
+    import paper_2506_18408_amd as P
+    import workloads as W
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    dev = torch.device("cuda:0")
+    t0 = time.time()
+    A, b, p = W.make_workload(args.workload)
+    log(f"workload {p['name']}: n={A.n} nnz={A.nnz} generated in {time.time() - t0:.1f}s")
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.val))
+    bt = torch.from_numpy(b).to(dev)
+    m, t, zeta = p["m"], p["t"], p["zeta"]
+    precs = ["mixed"] if args.workload == 5 else ["fp64", "mixed"]
+    adjoint = args.workload in (4, 5)
+    out = {"metric": "time-to-1e-8 rel. residual (s) per solve", "unit": "s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
+           "data": "synthetic",
+           "config": {"workload": p["name"], "n": A.n, "nnz": A.nnz, "m": m, "t": t, "s": p["s"],
+                      "zeta": zeta, "tol": p["tol"]}}
+    for prec in precs:
+        prm = P.SolveParams(m=m, t=t, s=p["s"], zeta=zeta, tol=p["tol"], seed=p["seed"],
+                            max_outer=p["max_outer"], precision=prec)
+        x = torch.empty_like(bt)
+        for _ in range(args.warmup):
+            P.solve(rp, ci, va, bt, params=prm, out=x)
+        torch.cuda.synchronize()
+        ts = time.perf_counter()
+        infos = [P.solve(rp, ci, va, bt, params=prm, out=x, profile=PROFILE_STRIDE)[1]
+                 for _ in range(args.steps)]
+        torch.cuda.synchronize()
+        sec = (time.perf_counter() - ts) / args.steps
+        inf = infos[-1]
+        avg, nbytes = fused_rate(infos, A, t, m, zeta, prec == "mixed")
+        rec = {"time_to_tol_s": sec, "converged": bool(inf["converged"]),
+               "true_rel_residual": inf["true_rel_residual"], "outer_iters": inf["outer_iters"],
+               "total_inner": inf["total_inner"], "spmv_mean_launch_us": avg * 1e6,
+               "spmv_bytes_per_launch": nbytes, "spmv_achieved_gbs": nbytes / avg / 1e9}
+        log(f"{prec}: {sec * 1e3:.2f} ms/solve outer={inf['outer_iters']} "
+            f"inner={inf['total_inner']} true_rel_res={inf['true_rel_residual']:.3e} "
+            f"fused {avg * 1e6:.1f} us ({nbytes / avg / 1e9:.0f} GB/s)")
+        if adjoint:
+            g = 2.0 * (x - bt)  # any right-hand side of the adjoint solve
+            for _ in range(args.warmup):
+                P.solve_adjoint(rp, ci, va, g, x, params=prm)
+            torch.cuda.synchronize()
+            ts = time.perf_counter()
+            for _ in range(args.steps):
+                _, _, ia = P.solve_adjoint(rp, ci, va, g, x, params=prm)
+            torch.cuda.synchronize()
+            asec = (time.perf_counter() - ts) / args.steps
+            rec["adjoint_time_s"] = asec
+            rec["adjoint_outer_iters"] = ia["outer_iters"]
+            rec["adjoint_converged"] = bool(ia["converged"])
+            log(f"{prec} adjoint (transpose + solve + dL/dA): {asec * 1e3:.2f} ms "
+                f"outer={ia['outer_iters']}")
+        out[prec] = rec
+    out["value"] = out[precs[0]]["time_to_tol_s"]
+    out["dtype"] = "f64" if precs[0] == "fp64" else "f32+f64"
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -108,6 +189,9 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload != 2:
+        other_workload(args)
         return
 
     import torch

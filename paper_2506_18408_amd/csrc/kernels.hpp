@@ -23,6 +23,7 @@ struct SpmvArgs {
   const int32_t* tiles;     // ntiles+1 row boundaries
   const int32_t* tp;        // ntiles+1 first nonzero of each tile
   int32_t ntiles;
+  int32_t short_tiles;      // 1: tiles of kRowTile rows, every row at most kShortRow nonzeros
   int32_t has_x;            // kModeResid: 0 means x = 0
   const void* x;            // input vector, same type as val
   const double* scale_ptr;  // kModeInner: device scalar sigma (NULL: 1)
@@ -51,7 +52,7 @@ hipError_t launch_tiles(const int32_t* row_ptr, int64_t n, int32_t wt, int32_t r
 hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, int32_t* out,
                              hipStream_t st);
 // Waves per SpMV workgroup for an s-row sketch (0: none), bounded by LDS.
-int spmv_waves(int s);
+int spmv_waves(int s, bool short_tiles);
 // ev0/ev1 non-null: the launch records them at the kernel's own start and
 // end (timing of the kernel alone).
 hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,

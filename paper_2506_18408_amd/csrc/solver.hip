@@ -386,6 +386,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   base_args.tiles = P.tiles;
   base_args.tp = P.tp;
   base_args.ntiles = ntiles;
+  base_args.short_tiles = tiling.max_row <= kShortRow;
   base_args.part = P.part;
   base_args.dpart = P.dpart;
   base_args.ctl = P.ctl;
@@ -944,6 +945,7 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   a.tiles = tiles;
   a.tp = tp;
   a.ntiles = ntiles;
+  a.short_tiles = tiling.max_row <= kShortRow;
   a.x = u;
   a.scale_val = scale;
   a.w = w;

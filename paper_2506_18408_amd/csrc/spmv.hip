@@ -108,12 +108,20 @@ hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, i
   return hipGetLastError();
 }
 
-// Doubles of LDS per wave: the staged products (padded so that a row's
-// first kShortRow products can be read without a bound), then, when
-// sketching, the s sketch accumulators and one slot that absorbs the empty
-// entries of the packed sketch.
-__host__ __device__ constexpr int wave_lds_doubles(int s) {
-  return kWStage + kShortRow + (s > 0 ? s + 1 : 0);
+// LDS stage of one wave, in doubles.  General tiles: the staged products
+// (padded so that a row's first kShortRow products can be read without a
+// bound).  Short-row tiles (FP32 values): the column indices, then the
+// values, each padded the same way.
+constexpr int kGenStage = kWStage + kShortRow;
+constexpr int kShortStage = (kGenStage * 4 + kGenStage * 4) / 8;
+__host__ __device__ constexpr int stage_doubles(bool short_tiles) {
+  return short_tiles ? kShortStage : kGenStage;
+}
+// Doubles of LDS per wave: the stage, then, when sketching, the s sketch
+// accumulators and one slot that absorbs the empty entries of the packed
+// sketch.
+__host__ __device__ constexpr int wave_lds_doubles(int s, bool short_tiles) {
+  return stage_doubles(short_tiles) + (s > 0 ? s + 1 : 0);
 }
 
 // s_waitcnt operand that waits for every outstanding vector memory access
@@ -144,9 +152,13 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);  // (uniform: scalar loop control)
   const int nw = blockDim.x / kWave;
   const int S = kSketch ? a.s : 0;
-  const int wstride = wave_lds_doubles(S);
+  // (the short-row path pays for itself with FP32 values only: staging FP64
+  // values doubles its LDS traffic, and their row-wise reads conflict)
+  const bool short_tiles = sizeof(VT) == 4 && a.short_tiles != 0;
+  const int stage = stage_doubles(short_tiles);
+  const int wstride = wave_lds_doubles(S, short_tiles);
   double* const prod = lds + (size_t)wv * wstride;
-  double* const wave_sk = prod + kWStage + kShortRow;
+  double* const wave_sk = prod + stage;
   // this wave's tiles: workgroups take contiguous ranges (XCD-grouped);
   // inside a range the waves take every nw-th tile, so the waves of a CU
   // work on neighbouring tiles at the same time (shared DRAM pages and
@@ -382,42 +394,156 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
     }
   };
 
-  TileB bc{}, bg{}, bf{};
-  if (nt > 0) {
-    load_chunk(0);
-    bg = tile_bounds(0);
-    fetch(bg);
-    gather(bg);
-    epi_load(bg);
-  }
-  if (nt > 1) {
-    bf = tile_bounds(1);
-    fetch(bf);
-  }
-  for (int i = 0; i < nt; ++i) {
-    // the one wait of the iteration: every request of the previous one
-    // (vector memory count 0; export and LDS/scalar counts left alone)
-    __builtin_amdgcn_s_waitcnt(kWaitVmem0);
-    if (i + 2 < nt && ((i + 2) & 63) == 0) load_chunk((i + 2) >> 6);
-    bc = bg;
-    if (staged(bc)) {
+  if (short_tiles && has_x) {
+    // Short-row tiles (at most kRowTile rows of at most kShortRow nonzeros):
+    // the column indices and values arrive coalesced, in nonzero order, and
+    // are staged in LDS; every lane then reads its own row back and gathers
+    // x for it, so gather k of the wave fetches entry k of 64 consecutive
+    // rows (for a stencil, one contiguous run of x per offset).  The row sum
+    // is formed in registers in nonzero order.  Pipeline as in the general
+    // case: the indices, values and row bounds of tile i+2, the x entries
+    // and epilogue inputs of tile i+1 are in flight while tile i finishes.
+    int* const cis = reinterpret_cast<int*>(prod);
+    VT* const vls = reinterpret_cast<VT*>(cis + kGenStage);
+    int fq0 = 0, fq1 = 0;       // row bounds of this lane's row, fetched tile
+    int q0c = 0, q1c = 0;       // ... of the tile being gathered / reduced
+    int lmax = 0;               // longest row of the gathered tile (uniform)
+    Pre epre{};                 // epilogue inputs of this lane's row
+    auto pre_load = [&](const TileB& bt) {
+      const int nrows = bt.r1 - bt.r0;
+      load_pre(bt.r0 + (lane < nrows ? lane : nrows - 1), epre);
+    };
+    auto fetch_s = [&](const TileB& bt) {
+      const int32_t* cb = col_idx + bt.p0 + lane;
+      const VT* vb = val + bt.p0 + lane;
 #pragma unroll
-      for (int u = 0; u < kU; ++u)
-        if (u * kWave < bc.L)
-          prod[u * kWave + lane] = static_cast<double>(vg[u]) * static_cast<double>(xg[u]);
+      for (int u = 0; u < kU; ++u) {
+        if ((u + 1) * kWave <= bt.L) {
+          ci[u] = *(cb + u * kWave);
+          vg[u] = *(vb + u * kWave);
+        } else if (u * kWave < bt.L) {
+          const int q = u * kWave + lane;
+          const int e = bt.p0 + (q < bt.L ? q : bt.L - 1);
+          ci[u] = col_idx[e];
+          vg[u] = val[e];
+        }
+      }
+      const int nrows = bt.r1 - bt.r0;
+      const int r = bt.r0 + (lane < nrows ? lane : nrows - 1);
+      fq0 = row_ptr[r];
+      fq1 = row_ptr[r + 1];
+    };
+    // fetched registers -> LDS (nonzero order), then this lane's row back
+    // and its x gathers; the row bounds move along with the tile
+    auto stage_gather = [&](const TileB& bt) {
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        if (u * kWave < bt.L) {
+          cis[u * kWave + lane] = ci[u];
+          vls[u * kWave + lane] = vg[u];
+        }
+      }
+      q0c = fq0 - bt.p0;
+      q1c = fq1 - bt.p0;
+      int len = q1c - q0c;
+      // (the longest row of the tile bounds the gathers every lane makes)
+      int m = len;
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) {
+        const int o = __shfl_xor(m, off, kWave);
+        m = o > m ? o : m;
+      }
+      lmax = __builtin_amdgcn_readfirstlane(m);
+      wave_sync();
+      const int c0 = cis[q0c];
+#pragma unroll
+      for (int k = 0; k < kShortRow; ++k) {
+        if (k < lmax) {
+          const int ck = cis[q0c + k];
+          xg[k] = x[k < len ? ck : c0];  // (past the row's end: its first entry again)
+        }
+      }
+    };
+    TileB bc{}, bg{}, bf{};
+    if (nt > 0) {
+      load_chunk(0);
+      bg = tile_bounds(0);
+      fetch_s(bg);
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      stage_gather(bg);
+      pre_load(bg);
     }
-    if (i + 1 < nt) {
-      bg = bf;
+    if (nt > 1) {
+      bf = tile_bounds(1);
+      fetch_s(bf);
+    }
+    for (int i = 0; i < nt; ++i) {
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      if (i + 2 < nt && ((i + 2) & 63) == 0) load_chunk((i + 2) >> 6);
+      bc = bg;
+      const int nrows = bc.r1 - bc.r0;
+      // the row sum of this lane's row, entries in order
+      double v[kShortRow];
+#pragma unroll
+      for (int k = 0; k < kShortRow; ++k) v[k] = static_cast<double>(vls[q0c + k]);
+      double acc = 0.0;
+      const int len = q1c - q0c;
+#pragma unroll
+      for (int k = 0; k < kShortRow; ++k)
+        if (k < lmax && k < len) acc += v[k] * static_cast<double>(xg[k]);
+      const Pre pre = epre;
+      wave_sync();  // the stage is read: the next tile may overwrite it
+      if (i + 1 < nt) {
+        bg = bf;
+        stage_gather(bg);
+        pre_load(bg);
+      }
+      if (lane < nrows) epilogue(bc.r0 + lane, acc, pre);
+      if (i + 2 < nt) {
+        bf = tile_bounds(i + 2);
+        fetch_s(bf);
+      }
+      wave_sync();
+    }
+  } else {
+    TileB bc{}, bg{}, bf{};
+    if (nt > 0) {
+      load_chunk(0);
+      bg = tile_bounds(0);
+      fetch(bg);
       gather(bg);
+      epi_load(bg);
     }
-    if (i + 2 < nt) {
-      bf = tile_bounds(i + 2);
+    if (nt > 1) {
+      bf = tile_bounds(1);
       fetch(bf);
     }
-    wave_sync();
-    reduce(bc);
-    if (i + 1 < nt) epi_load(bg);
-    wave_sync();
+    for (int i = 0; i < nt; ++i) {
+      // the one wait of the iteration: every request of the previous one
+      // (vector memory count 0; export and LDS/scalar counts left alone)
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      if (i + 2 < nt && ((i + 2) & 63) == 0) load_chunk((i + 2) >> 6);
+      bc = bg;
+      if (staged(bc)) {
+  #pragma unroll
+        for (int u = 0; u < kU; ++u)
+          if (u * kWave < bc.L)
+            prod[u * kWave + lane] = static_cast<double>(vg[u]) * static_cast<double>(xg[u]);
+      }
+      if (i + 1 < nt) {
+        bg = bf;
+        gather(bg);
+      }
+      if (i + 2 < nt) {
+        bf = tile_bounds(i + 2);
+        fetch(bf);
+      }
+      wave_sync();
+      reduce(bc);
+      if (i + 1 < nt) epi_load(bg);
+      wave_sync();
+    }
+
   }
 
   // one sketch row and one scalar row of partial sums per workgroup (fixed
@@ -426,7 +552,7 @@ __global__ __launch_bounds__(kSpmvMaxThreads) void k_spmv(SpmvArgs a) {
   if constexpr (kSketch) {
     double* prow = a.part + (int64_t)blockIdx.x * S;
     for (int q = tid; q < S; q += blockDim.x) {
-      const double* sk0 = lds + kWStage + kShortRow + q;  // wave 0's copy
+      const double* sk0 = lds + stage + q;  // wave 0's copy
       double v = sk0[0];
       for (int k = 1; k < nw; ++k) v += sk0[(size_t)k * wstride];
       prow[q] = v;
@@ -482,8 +608,9 @@ static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
 
 template <typename VT, int MODE, int NW>
 static hipError_t launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
-  const size_t per_wave = (size_t)wave_lds_doubles(zb > 0 ? a.s : 0) * sizeof(double);
-  c.waves = spmv_waves(zb > 0 ? a.s : 0);
+  const bool short_tiles = sizeof(VT) == 4 && a.short_tiles != 0;
+  const size_t per_wave = (size_t)wave_lds_doubles(zb > 0 ? a.s : 0, short_tiles) * sizeof(double);
+  c.waves = spmv_waves(zb > 0 ? a.s : 0, short_tiles);
   c.lds = per_wave * c.waves;
   switch (zb) {
     case 0:
@@ -507,8 +634,8 @@ static hipError_t launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) 
   return launch_spmv_zb<VT, MODE, kMaxT>(zb, c, a);
 }
 
-int spmv_waves(int s) {
-  const size_t per_wave = (size_t)wave_lds_doubles(s) * sizeof(double);
+int spmv_waves(int s, bool short_tiles) {
+  const size_t per_wave = (size_t)wave_lds_doubles(s, short_tiles) * sizeof(double);
   int nw = kSpmvMaxWaves;
   while (nw > 1 && per_wave * nw > (size_t)kSpmvLdsMax) nw >>= 1;
   return nw;
