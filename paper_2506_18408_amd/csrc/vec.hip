@@ -65,22 +65,36 @@ __global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
   VT* B = static_cast<VT*>(a.B);
   VT* out = B + (int64_t)a.inext * a.ldb;
   const VT* win = B + (int64_t)a.l0 * a.ldb;
-  const int64_t stride = (int64_t)gridDim.x * kVecThreads * kUnroll;
-  const int64_t base0 = (int64_t)blockIdx.x * kVecThreads * kUnroll + tid;
-
-  // first stretch of y and the window (independent of the coefficients).
+  // Workgroup stretches of kS elements: the full ones at wg0 + k gstride,
+  // k < nfull, then at most one partial stretch.  Over the full stretches
+  // the next stretch is requested before the current one is written, with
+  // no lane-dependent branch, so a stretch waits only for its own loads.
+  constexpr int kS = kVecThreads * kUnroll;
+  const int64_t wg0 = (int64_t)blockIdx.x * kS;
+  const int64_t gstride = (int64_t)gridDim.x * kS;
+  const int64_t nfull = n >= wg0 + kS ? (n - wg0 - kS) / gstride + 1 : 0;
+  // window columns past nwin read column l0 again (their coefficient is 0)
+  int64_t woff[NW];
+#pragma unroll
+  for (int l = 0; l < NW; ++l) woff[l] = (int64_t)(l < nwin ? l : 0) * a.ldb;
   // y and the oldest window column are read for the last time in the inner
   // step: streaming loads, so they do not displace the matrix from the
   // last-level cache
-  VT y0[kUnroll], b0[NW][kUnroll];
+  auto load_full = [&](int64_t k, VT (&yv)[kUnroll], VT (&bv)[NW][kUnroll]) {
+    const int64_t r0 = wg0 + k * gstride + tid;
 #pragma unroll
-  for (int u = 0; u < kUnroll; ++u) {
-    const int64_t r = base0 + u * kVecThreads;
-    y0[u] = r < n ? __builtin_nontemporal_load(&W[r]) : VT(0);
+    for (int u = 0; u < kUnroll; ++u) {
+      const int64_t r = r0 + u * kVecThreads;
+      yv[u] = __builtin_nontemporal_load(&W[r]);
 #pragma unroll
-    for (int l = 0; l < NW; ++l)
-      b0[l][u] = (l < nwin && r < n) ? (l == 0 ? __builtin_nontemporal_load(&win[r]) : win[(int64_t)l * a.ldb + r]) : VT(0);
-  }
+      for (int l = 0; l < NW; ++l)
+        bv[l][u] = l == 0 ? __builtin_nontemporal_load(&win[r]) : win[woff[l] + r];
+    }
+  };
+
+  // first full stretch (independent of the coefficients)
+  VT yA[kUnroll], bA[NW][kUnroll], yB[kUnroll], bB[NW][kUnroll];
+  if (nfull > 0) load_full(0, yA, bA);
   // the coefficients
   double v[kNV];
 #pragma unroll
@@ -127,19 +141,19 @@ __global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
   __syncthreads();
   const double ys = cf[kMaxT];
   double n2 = 0.0;
-  auto update = [&](int64_t base, const VT (&yv)[kUnroll], const VT (&bv)[NW][kUnroll]) {
+  auto update = [&](int64_t r0, const VT (&yv)[kUnroll], const VT (&bv)[NW][kUnroll],
+                    bool full) {
     double acc[kUnroll];
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) acc[u] = ys * static_cast<double>(yv[u]);
 #pragma unroll
     for (int l = 0; l < NW; ++l)
-      if (l < nwin)
 #pragma unroll
-        for (int u = 0; u < kUnroll; ++u) acc[u] -= cf[l] * static_cast<double>(bv[l][u]);
+      for (int u = 0; u < kUnroll; ++u) acc[u] -= cf[l] * static_cast<double>(bv[l][u]);
 #pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const int64_t r = base + u * kVecThreads;
-      if (r < n) {
+      const int64_t r = r0 + u * kVecThreads;
+      if (full || r < n) {
         const VT o = static_cast<VT>(acc[u]);
         out[r] = o;
         const double od = static_cast<double>(o);
@@ -147,17 +161,35 @@ __global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
       }
     }
   };
-  update(base0, y0, b0);
-  for (int64_t base = base0 + stride; base < n; base += stride) {
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const int64_t r = base + u * kVecThreads;
-      y0[u] = r < n ? __builtin_nontemporal_load(&W[r]) : VT(0);
-#pragma unroll
-      for (int l = 0; l < NW; ++l)
-        b0[l][u] = (l < nwin && r < n) ? (l == 0 ? __builtin_nontemporal_load(&win[r]) : win[(int64_t)l * a.ldb + r]) : VT(0);
+  // full stretches, two register sets in turn
+  for (int64_t k = 0; k < nfull; k += 2) {
+    const int64_t ra = wg0 + k * gstride + tid;
+    if (k + 1 >= nfull) {
+      update(ra, yA, bA, true);
+      break;
     }
-    update(base, y0, b0);
+    load_full(k + 1, yB, bB);
+    update(ra, yA, bA, true);
+    if (k + 2 >= nfull) {
+      update(ra + gstride, yB, bB, true);
+      break;
+    }
+    load_full(k + 2, yA, bA);
+    update(ra + gstride, yB, bB, true);
+  }
+  // the partial stretch
+  {
+    const int64_t r0 = wg0 + nfull * gstride + tid;
+    if (wg0 + nfull * gstride < n) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) {
+        const int64_t r = r0 + u * kVecThreads;
+        yA[u] = r < n ? W[r] : VT(0);
+#pragma unroll
+        for (int l = 0; l < NW; ++l) bA[l][u] = r < n ? win[woff[l] + r] : VT(0);
+      }
+      update(r0, yA, bA, false);
+    }
   }
   n2 = block_sum(n2, scratch);
   if (tid == 0) a.vnext[blockIdx.x] = n2;
