@@ -23,6 +23,8 @@
 // rows in a fixed order.
 #include <hip/hip_ext.h>
 
+#include <algorithm>
+
 #include "kernels.hpp"
 
 namespace sfg {
@@ -634,11 +636,11 @@ static hipError_t launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) 
   return launch_spmv_zb<VT, MODE, kMaxT>(zb, c, a);
 }
 
+// (the largest count that fits: 14 waves rather than 8 for s = 800)
 int spmv_waves(int s, bool short_tiles) {
   const size_t per_wave = (size_t)wave_lds_doubles(s, short_tiles) * sizeof(double);
-  int nw = kSpmvMaxWaves;
-  while (nw > 1 && per_wave * nw > (size_t)kSpmvLdsMax) nw >>= 1;
-  return nw;
+  const size_t fit = (size_t)kSpmvLdsMax / per_wave;
+  return (int)std::max<size_t>(1, std::min<size_t>(kSpmvMaxWaves, fit));
 }
 
 hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,
