@@ -66,6 +66,13 @@ def parse():
                     help="2 = the benchmark line (128^3); 3 = 1M power-law (FP64 and mixed), "
                          "4 = 512^2 parameterised operator and 5 = 256^3 variable coefficients "
                          "(forward and adjoint): informational timings of the other workloads")
+    ap.add_argument("--m", type=int, default=None, help="override the workload's inner cap k_max")
+    ap.add_argument("--t", type=int, default=None, help="override the Arnoldi window")
+    ap.add_argument("--s", type=int, default=None, help="override the sketch rows")
+    ap.add_argument("--zeta", type=int, default=None, help="override the sketch nonzeros per column")
+    ap.add_argument("--precisions", default=None, help="comma list of fp64,mixed (other workloads)")
+    ap.add_argument("--cond-threshold", type=float, default=None,
+                    help="override the C2 condition threshold (other workloads)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -131,9 +138,14 @@ def other_workload(args):
     log(f"workload {p['name']}: n={A.n} nnz={A.nnz} generated in {time.time() - t0:.1f}s")
     rp, ci, va = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.val))
     bt = torch.from_numpy(b).to(dev)
+    for k in ("m", "t", "s", "zeta"):
+        if getattr(args, k) is not None:
+            p[k] = getattr(args, k)
     m, t, zeta = p["m"], p["t"], p["zeta"]
     precs = ["mixed"] if args.workload == 5 else ["fp64", "mixed"]
-    adjoint = args.workload in (4, 5)
+    if args.precisions:
+        precs = args.precisions.split(",")
+    adjoint = args.workload in (4, 5) and args.precisions is None
     out = {"metric": "time-to-1e-8 rel. residual (s) per solve", "unit": "s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
            "data": "synthetic",
@@ -142,6 +154,8 @@ def other_workload(args):
     for prec in precs:
         prm = P.SolveParams(m=m, t=t, s=p["s"], zeta=zeta, tol=p["tol"], seed=p["seed"],
                             max_outer=p["max_outer"], precision=prec)
+        if args.cond_threshold is not None:
+            prm.cond_threshold = args.cond_threshold
         x = torch.empty_like(bt)
         for _ in range(args.warmup):
             P.solve(rp, ci, va, bt, params=prm, out=x)
@@ -190,7 +204,8 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.workload != 2:
+    if args.workload != 2 or any(getattr(args, k) is not None
+                                 for k in ("m", "t", "s", "zeta", "cond_threshold")):
         other_workload(args)
         return
 

@@ -81,7 +81,9 @@ typedef struct sfgmres_csr {
 typedef struct sfgmres_options {
   int32_t precision;            /* SFGMRES_FP64 (default) or SFGMRES_MIXED                       */
   int32_t max_outer;            /* outer FGMRES steps, default 100                               */
-  double  cond_threshold;       /* C2 threshold on the condition estimate, default 1e15 (Sec. 3) */
+  double  cond_threshold;       /* C2 threshold on the condition estimate (Sec. 3); 0 = default:
+                                   1e15 in FP64 (the paper's value), 1e15 u64/u32 = 1e15 2^-29
+                                   ~ 1.86e6 in mixed precision, where the basis is FP32          */
   int32_t record_true_residual; /* 1: also compute ||b - A x_j|| after every outer step (+1 SpMV
                                    and one n x j combination per step), default 0                */
   int32_t profile;              /* N > 0: time the inner SpMV+sketch launch of every N-th

@@ -31,7 +31,8 @@ class SolveParams:
     m: inner sGMRES basis cap k_max (rule C1); t: Arnoldi truncation window;
     s: sketch rows; zeta: nonzeros per sketch column; tol: relative
     tolerance on ||b - A x|| / ||b||; seed: sketch seed; cond_threshold: C2
-    threshold; precision: "fp64" or "mixed"; lookahead: inner steps the host
+    threshold (0: 1e15 in FP64, 1e15 * 2**-29 in mixed precision, whose
+    basis is FP32); precision: "fp64" or "mixed"; lookahead: inner steps the host
     runs ahead of the device's last decision (0: default); panel: columns
     per decision launch (0: default 8; the stopping rule still acts after
     every column).
@@ -43,7 +44,7 @@ class SolveParams:
     tol: float = 1e-8
     seed: int = 0
     max_outer: int = 100
-    cond_threshold: float = 1e15
+    cond_threshold: float = 0.0
     precision: str = "fp64"
     lookahead: int = 0
     panel: int = 0

@@ -51,6 +51,17 @@ namespace sfg {
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// C2 threshold.  The paper's 1e15 is a double-precision choice (a column
+// is dropped once the sketched basis is within a few digits of singular in
+// FP64); with an FP32 basis the same margin is reached at 1e15 u64/u32 =
+// 1e15 2^-29.  Measured on the 128^3 system in mixed precision: t = 0,
+// 162 -> 53 ms; the paper's t = 0, zeta = 1, s = 1000, k_max = 500:
+// 1312 -> 68 ms; t = 2 unchanged; 256^3, t = 2: 1.53 -> 1.33 s.
+double cond_threshold_of(const sfgmres_options& o) {
+  if (o.cond_threshold > 0.0) return o.cond_threshold;
+  return o.precision == SFGMRES_MIXED ? 1e15 * 0x1p-29 : 1e15;
+}
+
 // Columns per decision launch and the host's lookahead (in inner steps).
 int panel_cols(const sfgmres_options& o) { return o.panel > 0 ? o.panel : kPanel; }
 int lookahead_steps(const sfgmres_options& o) {
@@ -143,7 +154,7 @@ sfgmres_options defaults() {
   memset(&o, 0, sizeof(o));
   o.precision = SFGMRES_FP64;
   o.max_outer = 100;
-  o.cond_threshold = 1e15;
+  o.cond_threshold = 0.0;  // the precision's default
   o.record_true_residual = 0;
   o.profile = 0;
   o.lookahead = 0;
@@ -173,7 +184,8 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
   if (o.profile < 0) return fail(h, SFGMRES_ERR_INVALID, "need profile >= 0");
   if (o.max_outer < 1 || o.max_outer > SFGMRES_MAX_OUTER)
     return fail(h, SFGMRES_ERR_INVALID, "need 1 <= max_outer <= 2000");
-  if (!(o.cond_threshold > 0.0)) return fail(h, SFGMRES_ERR_INVALID, "cond_threshold must be > 0");
+  if (!(o.cond_threshold >= 0.0) || std::isinf(o.cond_threshold))
+    return fail(h, SFGMRES_ERR_INVALID, "cond_threshold must be finite and >= 0 (0: default)");
   if (o.lookahead < 0 || o.lookahead > 64)
     return fail(h, SFGMRES_ERR_INVALID, "need 0 <= lookahead <= 64");
   if (o.panel < 0 || o.panel > kPanel) return fail(h, SFGMRES_ERR_INVALID, "need 0 <= panel <= 8");
@@ -376,7 +388,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int Gn = rows_grid(n);
   const int G2 = vec_grid(n);
   memset((void*)hsh, 0, sizeof(HostStatus));
-  SFG_HIP(launch_init_ctl(P.ctl, m, t, s, o.cond_threshold, tol, st));
+  SFG_HIP(launch_init_ctl(P.ctl, m, t, s, cond_threshold_of(o), tol, st));
   if (f32) SFG_HIP(launch_cast_f32(A->val, P.val32, nnz, st));
   SFG_HIP(launch_sketch_pack(n, s, zeta, k0, k1, P.skp, st));
 

@@ -423,7 +423,8 @@ def test_tiny_threshold_forces_k1_monotone():
 
 
 @pytest.mark.parametrize("bad", [dict(m=60), dict(t=31), dict(zeta=61), dict(tol=0.0),
-                                 dict(zeta=0), dict(m=0), dict(s=3000), dict(t=9, m=40)])
+                                 dict(zeta=0), dict(m=0), dict(s=3000), dict(t=9, m=40),
+                                 dict(cond_threshold=-1.0), dict(cond_threshold=float("inf"))])
 def test_invalid_arguments(bad):
     A, b, prm = _case("c1")
     with pytest.raises(P.SFGMRESError) as e:
@@ -461,12 +462,16 @@ def test_workspace_too_small():
 
 
 # ------------------------------------------------------------ mixed precision
-@pytest.mark.parametrize("name", ["c1", "powerlaw_20k", "convdiff3d_24", "theta2d_64"])
+@pytest.mark.parametrize("name", ["c1", "powerlaw_20k", "convdiff3d_24", "theta2d_64",
+                                  "cw_sketch_t0"])
 def test_mixed_precision_reaches_tol(name):
     A, b, prm = _case(name)
     prm = dict(prm, max_outer=200)
     x, info = _gpu(A, b, prm, precision="mixed")
     assert info["converged"]
+    # the mixed-precision default C2 threshold, 1e15 u64/u32 (FP32 basis)
+    if "cond_threshold" not in prm:
+        assert np.all(np.asarray(info["cond_at_stop"]) <= 1e15 * 2.0**-29 * (1 + 1e-12))
     xs = x.cpu().numpy()
     tr = np.linalg.norm(b - A.to_scipy() @ xs) / np.linalg.norm(b)
     assert tr <= prm["tol"] * (1 + 1e-4)

@@ -39,7 +39,8 @@ def test_nm_lists_symbols_as_global_text(lib):
 def test_default_options(lib):
     o = L.Options()
     assert lib.sfgmres_default_options(C.byref(o)) == 0
-    assert o.precision == L.FP64 and o.max_outer == 100 and o.cond_threshold == 1e15
+    # cond_threshold 0 selects the precision's default (1e15 in FP64)
+    assert o.precision == L.FP64 and o.max_outer == 100 and o.cond_threshold == 0.0
     assert lib.sfgmres_default_options(None) == L.ERR_INVALID
 
 
