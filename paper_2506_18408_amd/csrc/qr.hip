@@ -1,7 +1,8 @@
 // Coefficients, reductions and decisions of the inner sGMRES cycle
 // (Section 3, with the truncated Arnoldi basis of Section 4.1).
 //
-// k_coef (one workgroup, on the critical path of every inner step) sums the
+// k_coef (one workgroup; t = 0, and the last step of a cycle: otherwise the
+// truncated-Arnoldi update forms these coefficients itself) sums the
 // window dots and ||y||^2 of the fused SpMV's scalar rows, forms
 // sigma_i = 1/||u_i|| of the current (unnormalised) Arnoldi vector from the
 // norm partials of the previous Arnoldi update, and stores the coefficients
@@ -18,14 +19,16 @@
 // k_reduce_slots (many workgroups) sums the partial rows of the p slots in
 // slot order, and
 //
-// k_qr_block (one workgroup, 1024 threads) appends the p columns
+// k_qr_block (one workgroup, 1024 threads; both run on a stream of their
+// own, concurrently with the next inner steps) appends the p columns
 // c_i = S A b_i / sqrt(zeta) (b_i = sigma_i u_i; for t = 0 the SpMV already
 // returned A b_i) to the Householder QR of S A B, in float64:
 //   * blocked update with the existing reflectors in compact-WY form
 //     (Q = I - V T V^T, T upper triangular): A = V^T C, B = T^T A,
 //     C <- C - V B, one pass over V (twice) and T for all p columns;
 //   * the p new reflectors column by column (right-looking inside the
-//     panel), with d = Q^T S v_j carried along, the sketched least-squares
+//     panel, four waves; the other twelve exit after the blocked update),
+//     with d = Q^T S v_j carried along, the sketched least-squares
 //     residual ||d[i+1:]|| (the estimate C3 uses) and Bischof's incremental
 //     condition estimate of R (the estimate C2 uses) after every column;
 //   * the decision after every column, in this order: a zero Arnoldi vector
@@ -34,7 +37,9 @@
 //     C1 (i = m).  Column i's decision uses the quantities a one-column
 //     update gives (R_i is the leading block of R_k), so the blocking
 //     changes rounding only; steps run past the stop are discarded;
-//   * if the cycle goes on, T extended by the p new reflectors.
+//   * T extended by the previous panel's reflectors at the start of the
+//     next launch, where all waves are present (a cycle's last panel never
+//     pays for it).
 // It is the only writer of the stop flag.  k_rq_init takes d0 = S v_j and
 // resets the cycle state; k_sketch_out is the test export of one fused SpMV.
 #include "kernels.hpp"

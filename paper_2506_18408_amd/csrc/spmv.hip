@@ -5,22 +5,25 @@
 // first Gram-Schmidt dot; the initial residual b - A x0; a true residual),
 // and the generation of the packed sketch.
 //
-// Design (gfx950): a persistent grid of one workgroup per CU, of 16 waves
-// (8 when the sketch is large); every wave walks its own sequence of tiles
-// (every 16th tile of its workgroup's contiguous range) without any
-// workgroup barrier, so the waves of a CU keep independent streams of memory
-// requests in flight on neighbouring tiles.  A tile (64 rows, one per lane, when
-// every row has at most 8 nonzeros; else about 256 nonzeros) has its column
-// indices and values loaded with coalesced loads one tile ahead, its x
-// entries gathered, the products staged in the wave's own LDS region, and
-// its rows reduced from LDS by groups of 1..64 lanes; the row leader then
-// runs the epilogue: store, scatter +-y_r into the wave's own LDS sketch
+// Design (gfx950): a persistent grid of at most one workgroup per CU (248:
+// one CU per XCD stays free for the decision kernel on its own stream), of
+// as many waves as the LDS holds (16; fewer for large sketches and wide
+// windows); every wave walks its own sequence of tiles (every nw-th tile of
+// its workgroup's contiguous, XCD-grouped range) without any workgroup
+// barrier.  A tile is 64 rows (one per lane) when every row has at most 8
+// nonzeros, else about 256 nonzeros.  Per wave the tiles form a software
+// pipeline: while tile i is reduced, the column indices of tile i+2 and the
+// values, x gathers and epilogue inputs of tile i+1 are in flight, and the
+// wave waits once per tile.  General tiles stage their products in the
+// wave's own LDS region and reduce each row with a group of 1..64 lanes;
+// short-row tiles with FP32 values stage indices and values instead and
+// let every lane gather x for its own row.  The row's lane then runs the
+// epilogue: store, scatter +-y_r into the wave's own LDS sketch
 // accumulators (the zeta rows and signs of column r of S come from the
-// packed sketch) and accumulate the dot products in registers.  The
-// epilogue's inputs are requested together with the gathers.  At the end
+// packed sketch) and accumulate the dot products in registers.  At the end
 // the workgroup adds its wave copies in wave order and writes one row of
 // sketch partials and one row of scalar partials; later kernels combine the
-// rows in a fixed order.
+// rows in a fixed order, so results do not depend on timing.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
