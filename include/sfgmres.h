@@ -53,6 +53,10 @@ extern "C" {
                              float64 sketch accumulation, sketched QR/least squares,
                              z = B y accumulation, outer SpMV, Gram-Schmidt and Givens       */
 
+/* ---- outer iterations (sfgmres_options.outer) ------------------------ */
+#define SFGMRES_OUTER_FGMRES    0  /* Algorithm 1 (default)                               */
+#define SFGMRES_OUTER_RESTARTED 1  /* restarted sGMRES (the paper's comparison method)    */
+
 /* ---- inner stop reasons (sfgmres_info.stop_reason) ------------------- */
 #define SFGMRES_STOP_C1         1  /* k reached m                                  */
 #define SFGMRES_STOP_C2         2  /* cond estimate of S A B_i exceeded threshold: k = i-1 */
@@ -96,7 +100,12 @@ typedef struct sfgmres_options {
                                    0..8; 0 = default (8).  The stopping rule is applied after
                                    every column whatever the panel; up to panel - 1 inner steps
                                    past the stop are computed and discarded                      */
-  int32_t reserved[3];
+  int32_t outer;                /* SFGMRES_OUTER_FGMRES (default): Algorithm 1, sGMRES cycles as
+                                   the flexible preconditioner of FGMRES.  SFGMRES_OUTER_RESTARTED:
+                                   restarted sGMRES, the comparison method of Section 4 (each
+                                   cycle solves A z = r_j / ||r_j|| and x <- x + ||r_j|| z; C3
+                                   uses ||r_j|| as its factor).  The adjoint solve follows it too */
+  int32_t reserved[2];
 } sfgmres_options;
 
 /* Solve diagnostics.  Scalars are always written; each per-step array is a

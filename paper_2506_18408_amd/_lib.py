@@ -51,7 +51,8 @@ class Options(C.Structure):
         ("profile", C.c_int32),
         ("lookahead", C.c_int32),
         ("panel", C.c_int32),
-        ("reserved", C.c_int32 * 3),
+        ("outer", C.c_int32),
+        ("reserved", C.c_int32 * 2),
     ]
 
 

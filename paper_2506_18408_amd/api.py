@@ -35,7 +35,8 @@ class SolveParams:
     basis is FP32); precision: "fp64" or "mixed"; lookahead: inner steps the host
     runs ahead of the device's last decision (0: default); panel: columns
     per decision launch (0: default 8; the stopping rule still acts after
-    every column).
+    every column); outer: "fgmres" (Algorithm 1) or "restarted" (restarted
+    sGMRES, the paper's comparison method).
     """
     m: int = 30
     t: int = 2
@@ -48,6 +49,7 @@ class SolveParams:
     precision: str = "fp64"
     lookahead: int = 0
     panel: int = 0
+    outer: str = "fgmres"
 
 
 _HANDLES = {}
@@ -102,6 +104,7 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.profile = int(profile)  # False/True -> 0/1; N -> every N-th inner step
     o.lookahead = p.lookahead
     o.panel = p.panel
+    o.outer = {"fgmres": 0, "restarted": 1}[p.outer]
     return o
 
 

@@ -13,6 +13,7 @@ enum SpmvMode : int {
   kModeResid = 2,    // w = b - A x ; ||w||^2 ; ||b||^2
   kModeTrueRes = 3,  // ||b - A x||^2
   kModePlain = 4,    // as kModeInner with a scale, without predication (test export)
+  kModeRestart = 5,  // finisher only: beta = ||b - A x|| of a restart (kModeResid SpMV)
 };
 
 struct SpmvArgs {
@@ -161,9 +162,11 @@ hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double*
                                    const uint2* skp, int zb, double* part, hipStream_t st);
 hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
                            const double* sigma, int32_t m, double* y, hipStream_t st);
+// out = add + sum_l y_l B_l (l < k); with `scale` (device scalar) the sum is
+// formed first and out = add + scale * sum.
 hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, const double* y,
                           const int32_t* kdev, int32_t khost, const double* add,
-                          double* out, hipStream_t st);
+                          double* out, hipStream_t st, const double* scale = nullptr);
 hipError_t launch_backsolve(const double* HR, const double* g, int32_t J, int32_t ldh,
                             double* y, hipStream_t st);
 hipError_t launch_cast_f32(const double* src, float* dst, int64_t count, hipStream_t st);

@@ -159,6 +159,7 @@ sfgmres_options defaults() {
   o.profile = 0;
   o.lookahead = 0;
   o.panel = 0;
+  o.outer = SFGMRES_OUTER_FGMRES;
   return o;
 }
 
@@ -189,6 +190,8 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
   if (o.lookahead < 0 || o.lookahead > 64)
     return fail(h, SFGMRES_ERR_INVALID, "need 0 <= lookahead <= 64");
   if (o.panel < 0 || o.panel > kPanel) return fail(h, SFGMRES_ERR_INVALID, "need 0 <= panel <= 8");
+  if (o.outer != SFGMRES_OUTER_FGMRES && o.outer != SFGMRES_OUTER_RESTARTED)
+    return fail(h, SFGMRES_ERR_INVALID, "outer must be SFGMRES_OUTER_FGMRES or _RESTARTED");
   return SFGMRES_OK;
 }
 
@@ -492,7 +495,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     return SFGMRES_OK;
   };
 
-  // ---- outer FGMRES loop ---------------------------------------------------
+  // ---- outer loop: FGMRES (Algorithm 1), or restarted sGMRES --------------
+  const bool restarted = o.outer == SFGMRES_OUTER_RESTARTED;
+  double beta_cur = beta;  // restarted: ||b - A x|| of the current iterate, held in x
+  if (restarted) SFG_HIP(launch_copy_or_zero(x0, x, n, st));
   int J_done = 0;
   bool conv = false;
   double rho_last = beta;
@@ -598,6 +604,62 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     SFG_HIP(hipStreamWaitEvent(st, ev_dec, 0));
     // z_j = B_k y_k
     SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
+    if (restarted) {
+      // the cycle solved A z = r_j / beta_j: x <- x + beta_j z, then the new
+      // residual r_{j+1} = b - A x and beta_{j+1} (also the next C3 factor)
+      SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, x, x, st,
+                             &P.ctl->beta));
+      SpmvArgs a = base_args;
+      a.has_x = 1;
+      a.x = x;
+      a.w = P.W64;
+      a.b = b;
+      SFG_HIP(launch_spmv(kModeResid, false, Gp, a, 0, st));
+      SFG_HIP(launch_spmv_finish(kModeRestart, P.dpart, Gp, P.ctl, P.scal, hsd, st));
+      SFG_HIP(hipStreamSynchronize(st));
+      const int err = hsh->error;
+      const int kj = hsh->k;
+      beta_cur = hsh->beta;
+      J_done = j + 1;
+      total_inner += kj;
+      if (info) {
+        info->total_inner = total_inner;
+        if (info->residual_history) info->residual_history[j + 1] = beta_cur / nb;
+        if (info->inner_k) info->inner_k[j] = kj;
+        if (info->stop_reason) info->stop_reason[j] = hsh->stop_reason;
+        if (info->cond_at_stop) info->cond_at_stop[j] = hsh->cond;
+        if (info->inner_sketched_residual) info->inner_sketched_residual[j] = hsh->rho_hat;
+        if (info->inner_true_residual) info->inner_true_residual[j] = NAN;
+        if (info->ffom_residual) info->ffom_residual[j] = NAN;
+        if (info->true_residual_history) info->true_residual_history[j] = beta_cur / nb;
+      }
+      if (o.profile > 0) {
+        const int worked = std::min((int)hsh->steps_run, m);
+        for (int i = o.profile - 1; i < worked; i += o.profile) {
+          float ms = 0.f;
+          SFG_HIP(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+          if (info) {
+            info->spmv_ms += ms;
+            info->spmv_launches += 1;
+          }
+        }
+      }
+      if (err) {
+        finish_info(err, J_done, false, beta_cur / nb, beta_cur / nb);
+        return fail(h, err,
+                    err == SFGMRES_ERR_BREAKDOWN ? "sketch of A v_j is zero (singular inner problem)"
+                                                 : "non-finite residual of a restart");
+      }
+      if (beta_cur <= tol * nb) {
+        conv = true;
+        break;
+      }
+      // v_{j+1} = r_{j+1} / beta_{j+1}, its copy as the next cycle's b_1, S v
+      rc = sketch_v_and_init(P.W64, &P.ctl->beta, Vcol(0),
+                             (forced && j + 1 < J) ? forced[j + 1] : 0);
+      if (rc) return rc;
+      continue;
+    }
     SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
     // w = A z_j with h_{1,j}; modified Gram-Schmidt; Givens
     {
@@ -668,6 +730,12 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       conv = true;
       break;
     }
+  }
+
+  if (restarted) {  // x holds the iterate and beta_cur its true residual
+    SFG_HIP(hipStreamSynchronize(st));
+    const int status = conv ? SFGMRES_OK : SFGMRES_NOT_CONVERGED;
+    return finish_info(status, J_done, conv, beta_cur / nb, beta_cur / nb);
   }
 
   // ---- x = x0 + Z y, true residual ----------------------------------------

@@ -694,6 +694,23 @@ __global__ __launch_bounds__(kFinishThreads) void k_spmv_finish(int mode, const 
     host_store_f64(&hs->beta, beta);
     host_store_f64(&hs->nb, nb);
     host_store_i32(&hs->error, c->error);
+  } else if (mode == kModeRestart) {
+    // a restart of restarted sGMRES: the new residual norm, which is also
+    // the next cycle's C3 factor (||b|| and the tolerance are set already)
+    const double beta = sqrt(t0s);
+    c->beta = beta;
+    c->factor = beta;
+    out0[0] = beta;
+    if (!isfinite(beta) && c->error == 0) c->error = SFGMRES_ERR_NONFINITE;
+    host_store_f64(&hs->beta, beta);
+    host_store_i32(&hs->error, c->error);
+    // the finished cycle's summary (the FGMRES path publishes it with its
+    // last Gram-Schmidt pass)
+    const bool c2 = c->stop_reason == SFGMRES_STOP_C2;
+    host_store_i32(&hs->k, c->stop_k);
+    host_store_i32(&hs->stop_reason, c->stop_reason);
+    host_store_f64(&hs->cond, c2 ? c->cond_prev : c->cond_cur);
+    host_store_f64(&hs->rho_hat, c2 ? c->rho_prev : c->rho_cur);
   } else {
     out0[0] = t0s;
   }

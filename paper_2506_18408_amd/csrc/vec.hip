@@ -557,13 +557,22 @@ __global__ __launch_bounds__(kVecThreads) void k_combine(int64_t n, const VT* __
                                                          int64_t ldb,
                                                          const double* __restrict__ y,
                                                          const int32_t* kdev, int32_t khost,
-                                                         const double* __restrict__ add,
-                                                         double* __restrict__ out) {
+                                                         const double* add, double* out,
+                                                         const double* scale) {
   extern __shared__ double ys[];
   const int k = kdev ? *kdev : khost;
   for (int l = threadIdx.x; l < k; l += kVecThreads) ys[l] = y[l];
   __syncthreads();
   const int64_t stride = (int64_t)gridDim.x * kVecThreads;
+  if (scale) {  // (add and out may be the same vector)
+    const double sc = *scale;
+    for (int64_t r = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; r < n; r += stride) {
+      double z = 0.0;
+      for (int l = 0; l < k; ++l) z += ys[l] * static_cast<double>(B[(int64_t)l * ldb + r]);
+      out[r] = (add ? add[r] : 0.0) + sc * z;
+    }
+    return;
+  }
   for (int64_t r = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; r < n; r += stride) {
     double acc = add ? add[r] : 0.0;
     for (int l = 0; l < k; ++l) acc += ys[l] * static_cast<double>(B[(int64_t)l * ldb + r]);
@@ -573,16 +582,16 @@ __global__ __launch_bounds__(kVecThreads) void k_combine(int64_t n, const VT* __
 
 hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, const double* y,
                           const int32_t* kdev, int32_t khost, const double* add, double* out,
-                          hipStream_t st) {
+                          hipStream_t st, const double* scale) {
   const int kmax = kdev ? kMaxM : khost;
   const size_t lds = (size_t)(kmax > 0 ? kmax : 1) * sizeof(double);
   const int grid = vec_grid(n * kUnroll);
   if (fp32)
     hipLaunchKernelGGL(k_combine<float>, dim3(grid), dim3(kVecThreads), lds, st, n,
-                       static_cast<const float*>(B), ldb, y, kdev, khost, add, out);
+                       static_cast<const float*>(B), ldb, y, kdev, khost, add, out, scale);
   else
     hipLaunchKernelGGL(k_combine<double>, dim3(grid), dim3(kVecThreads), lds, st, n,
-                       static_cast<const double*>(B), ldb, y, kdev, khost, add, out);
+                       static_cast<const double*>(B), ldb, y, kdev, khost, add, out, scale);
   return hipGetLastError();
 }
 
