@@ -73,6 +73,8 @@ def parse():
     ap.add_argument("--precisions", default=None, help="comma list of fp64,mixed (other workloads)")
     ap.add_argument("--cond-threshold", type=float, default=None,
                     help="override the C2 condition threshold (other workloads)")
+    ap.add_argument("--outer", default=None, choices=["fgmres", "restarted"],
+                    help="outer iteration (other workloads): FGMRES or restarted sGMRES")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -156,6 +158,8 @@ def other_workload(args):
                             max_outer=p["max_outer"], precision=prec)
         if args.cond_threshold is not None:
             prm.cond_threshold = args.cond_threshold
+        if args.outer is not None:
+            prm.outer = args.outer
         x = torch.empty_like(bt)
         for _ in range(args.warmup):
             P.solve(rp, ci, va, bt, params=prm, out=x)
@@ -168,6 +172,7 @@ def other_workload(args):
         inf = infos[-1]
         avg, nbytes = fused_rate(infos, A, t, m, zeta, prec == "mixed")
         rec = {"time_to_tol_s": sec, "converged": bool(inf["converged"]),
+               "residual_history": [float(v) for v in inf["residual_history"]],
                "true_rel_residual": inf["true_rel_residual"], "outer_iters": inf["outer_iters"],
                "total_inner": inf["total_inner"], "spmv_mean_launch_us": avg * 1e6,
                "spmv_bytes_per_launch": nbytes, "spmv_achieved_gbs": nbytes / avg / 1e9}
@@ -205,7 +210,7 @@ def main():
         copy_calibration(args.copy_calibration)
         return
     if args.workload != 2 or any(getattr(args, k) is not None
-                                 for k in ("m", "t", "s", "zeta", "cond_threshold")):
+                                 for k in ("m", "t", "s", "zeta", "cond_threshold", "outer")):
         other_workload(args)
         return
 
