@@ -16,10 +16,15 @@
  *    and unmodified until the call returns.  Host arrays are marked "host".
  *  - Every call enqueues its GPU work on the caller's HIP stream `stream`
  *    (NULL = the default stream) and returns after that work is complete.
+ *    The solves also use a second stream owned by the handle (default
+ *    priority, non-blocking), for the inner cycle's slot reductions and
+ *    decision kernels; it is ordered against `stream` by events, and the
+ *    caller's stream waits for all of its work before the call returns.
  *  - The library allocates no device memory: the caller provides one
  *    workspace of at least the size returned by sfgmres_workspace_bytes,
- *    256-byte aligned.  It allocates only a small pinned host status block
- *    per handle (in sfgmres_create).
+ *    256-byte aligned.  It allocates only a small pinned host status block,
+ *    one stream and a few events per handle (in sfgmres_create and on the
+ *    first solve).
  *  - Return codes: 0 = success; > 0 = success with a warning (the result is
  *    valid); < 0 = error, in which case output arrays may be partially
  *    written and sfgmres_last_error(h) describes the problem.  No C++
@@ -150,7 +155,8 @@ int sfgmres_default_options(sfgmres_options* opt);
 int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
                             const sfgmres_options* opt, int32_t adjoint, size_t* bytes);
 
-/* Create a handle bound to the current HIP device. */
+/* Create a handle bound to the current HIP device (with its decision
+ * stream).  Returns SFGMRES_ERR_HIP if the runtime cannot provide them. */
 int sfgmres_create(sfgmres_handle* h);
 
 /* Release a handle (NULL is ignored). */
