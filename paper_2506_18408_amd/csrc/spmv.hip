@@ -153,7 +153,6 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   constexpr int kU = kWStage / kWave;
   // per wave: the products of its tile, then (sketching) its s accumulators
   extern __shared__ double lds[];
-  __shared__ double scratch[kSpmvMaxWaves];
 
   if (MODE == kModeInner && a.ctl->stop_k != 0) return;
 
@@ -404,6 +403,26 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
     }
   };
 
+  // Wave pacing.  At equal priority a SIMD issues for its oldest wave
+  // first, so the waves of a workgroup finish in order of age (for the
+  // 128^3 stencil the last group of four 12 us after the first, while the
+  // barrier below waits for all of them).  A wave starts at priority 3 and
+  // steps down after 1/2, 3/4 and 9/10 of its tiles, so waves that are
+  // ahead yield to those behind.  The tile assignment is unchanged.
+  __builtin_amdgcn_s_setprio(3);
+  int pstage = 0;
+  auto pace = [&](int i) {
+    const int st = (2 * i >= nt) + (4 * i >= 3 * nt) + (10 * i >= 9 * nt);
+    if (st != pstage) {
+      pstage = st;
+      if (st == 1)
+        __builtin_amdgcn_s_setprio(2);
+      else if (st == 2)
+        __builtin_amdgcn_s_setprio(1);
+      else
+        __builtin_amdgcn_s_setprio(0);
+    }
+  };
   if (short_tiles && has_x) {
     // Short-row tiles (at most kRowTile rows of at most kShortRow nonzeros):
     // the column indices and values arrive coalesced, in nonzero order, and
@@ -488,6 +507,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
       fetch_s(bf);
     }
     for (int i = 0; i < nt; ++i) {
+      pace(i);
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
       if (i + 2 < nt && ((i + 2) & 63) == 0) load_chunk((i + 2) >> 6);
       bc = bg;
@@ -529,6 +549,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
       fetch(bf);
     }
     for (int i = 0; i < nt; ++i) {
+      pace(i);
       // the one wait of the iteration: every request of the previous one
       // (vector memory count 0; export and LDS/scalar counts left alone)
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
@@ -556,8 +577,28 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
 
   }
 
-  // one sketch row and one scalar row of partial sums per workgroup (fixed
-  // slot = blockIdx.x); the wave copies are added in wave order
+  // One sketch row and one scalar row of partial sums per workgroup (fixed
+  // slot = blockIdx.x).  Each wave reduces its scalar partials as soon as
+  // its own tiles are done (the waves of a workgroup finish at different
+  // times), so a single barrier remains; after it the wave sums, and the
+  // wave copies of the sketch, are added in wave order: the order of a
+  // block-wide sum.
+  constexpr int kNS = kInnerLike ? NW + 1 : 2;  // scalar sums per wave
+  __shared__ double wsums[kSpmvMaxWaves * kNS];
+  {
+    double sv[kNS];
+    if constexpr (kInnerLike) {
+#pragma unroll
+      for (int l = 0; l < NW; ++l) sv[l] = l < nwin ? wave_sum(dacc[l]) : 0.0;
+      sv[kNS - 1] = wave_sum(n2);
+    } else {
+      sv[0] = wave_sum(MODE == kModeOuter ? dacc[0] : n2);
+      sv[1] = wave_sum(ex);
+    }
+    if (lane == 0)
+#pragma unroll
+      for (int i = 0; i < kNS; ++i) wsums[wv * kNS + i] = sv[i];
+  }
   __syncthreads();
   if constexpr (kSketch) {
     double* prow = a.part + (int64_t)blockIdx.x * S;
@@ -568,24 +609,16 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
       prow[q] = v;
     }
   }
-  double* drow = a.dpart + (int64_t)blockIdx.x * kDP;
-  if constexpr (kInnerLike) {
-#pragma unroll
-    for (int l = 0; l < NW; ++l) {
-      if (l < nwin) {
-        const double v = block_sum(dacc[l], scratch);
-        if (tid == 0) drow[l] = v;
-      }
-    }
-    const double v = block_sum(n2, scratch);
-    if (tid == 0) drow[kMaxT] = v;
-  } else {
-    const double s0 = block_sum(MODE == kModeOuter ? dacc[0] : n2, scratch);
-    const double s1 = block_sum(ex, scratch);
-    if (tid == 0) {
-      drow[kMaxT] = s0;
-      drow[kMaxT + 1] = s1;
-    }
+  if (tid < kNS) {
+    double r = 0.0;
+    for (int k = 0; k < nw; ++k) r += wsums[k * kNS + tid];
+    double* drow = a.dpart + (int64_t)blockIdx.x * kDP;
+    if (!kInnerLike)
+      drow[kMaxT + tid] = r;  // (reference or outer dot, then the second sum)
+    else if (tid == kNS - 1)
+      drow[kMaxT] = r;        // ||w||^2
+    else if (tid < nwin)
+      drow[tid] = r;          // window dots
   }
 }
 

@@ -92,44 +92,66 @@ __global__ __launch_bounds__(kVecThreads) void k_arnoldi(ArnoldiArgs a) {
     }
   };
 
+  // The coefficients' inputs are requested first, all at once and without
+  // lane-dependent branches (addresses clamped into range, the values past
+  // the counts selected away when summed), then the first stretch: loads
+  // return in order, so the reduction costs one memory round trip, which
+  // overlaps the stretch's transfer, instead of one per block of partials.
+  // The sums keep the fixed order: block u, then thread, then wave.
+  const int stopped = ctl->stop_k;
+  const int Gd = a.Gd, Gv = a.Gv;  // (both >= 1)
+  constexpr int kUV = kVecGrid / kVecThreads;
+  double dv[NW], pv[kUV], sgw[NW];
+  {
+    const double* row = a.dpart + (int64_t)(tid < Gd ? tid : Gd - 1) * kDP;
+#pragma unroll
+    for (int l = 0; l < NW; ++l) dv[l] = row[l < nwin ? l : 0];
+  }
+#pragma unroll
+  for (int u = 0; u < kUV; ++u) {
+    const int g = tid + u * kVecThreads;
+    pv[u] = a.vprev[g < Gv ? g : Gv - 1];
+  }
+#pragma unroll
+  for (int l = 0; l < NW; ++l) {
+    const int li = a.l0 + l;
+    sgw[l] = a.sigma[li < step ? li : 0];
+  }
   // first full stretch (independent of the coefficients)
   VT yA[kUnroll], bA[NW][kUnroll], yB[kUnroll], bB[NW][kUnroll];
   if (nfull > 0) load_full(0, yA, bA);
-  // the coefficients
-  double v[kNV];
+  // v[l] = <y, u_{l0+l}> (l < nwin), v[NW] = ||u_i||^2
+  double v[NW + 1];
 #pragma unroll
-  for (int l = 0; l < kNV; ++l) v[l] = 0.0;
+  for (int l = 0; l <= NW; ++l) v[l] = 0.0;
 #pragma unroll
-  for (int u = 0; u < kMaxGrid / kVecThreads; ++u) {
-    const int g = tid + u * kVecThreads;
-    if (g < a.Gd) {
-      const double* row = a.dpart + (int64_t)g * kDP;
+  for (int l = 0; l < NW; ++l)
+    if (l < nwin) v[l] += tid < Gd ? dv[l] : 0.0;
 #pragma unroll
-      for (int l = 0; l < kMaxT; ++l)
-        if (l < nwin) v[l] += row[l];
+  for (int u = 1; u < kMaxGrid / kVecThreads; ++u) {
+    if (u * kVecThreads < Gd) {  // (uniform; the inner-step grid stays below kVecThreads)
+      const int g = tid + u * kVecThreads;
+      const double* row = a.dpart + (int64_t)(g < Gd ? g : Gd - 1) * kDP;
+#pragma unroll
+      for (int l = 0; l < NW; ++l)
+        if (l < nwin) v[l] += g < Gd ? row[l] : 0.0;
     }
   }
 #pragma unroll
-  for (int u = 0; u < kVecGrid / kVecThreads; ++u) {
-    const int g = tid + u * kVecThreads;
-    if (step > 0 && g < a.Gv) v[kMaxT] += a.vprev[g];
-  }
-  double sgw[kMaxT];
-#pragma unroll
-  for (int l = 0; l < kMaxT; ++l)
-    sgw[l] = (tid == 0 && l < nwin && a.l0 + l < step) ? a.sigma[a.l0 + l] : 0.0;
-  const int stopped = ctl->stop_k;
-  block_sum_vec<kNV>(v, buf);
+  for (int u = 0; u < kUV; ++u)
+    v[NW] += (step > 0 && tid + u * kVecThreads < Gv) ? pv[u] : 0.0;
+  block_sum_vec<NW + 1>(v, buf);
   if (stopped != 0) return;
   if (tid == 0) {
     bool brk = false;
     double sig = 1.0;
     if (step > 0) {
-      brk = v[kMaxT] == 0.0;
-      sig = brk ? 0.0 : 1.0 / sqrt(v[kMaxT]);
+      brk = v[NW] == 0.0;
+      sig = brk ? 0.0 : 1.0 / sqrt(v[NW]);
     }
-    for (int l = 0; l < kMaxT; ++l) {
-      const double sg = (a.l0 + l == step) ? sig : sgw[l];
+    for (int l = 0; l < NW; ++l) {
+      const int li = a.l0 + l;
+      const double sg = li == step ? sig : (li < step ? sgw[l] : 0.0);
       cf[l] = l < nwin ? sig * sg * sg * v[l] : 0.0;
     }
     cf[kMaxT] = sig;
