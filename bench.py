@@ -17,7 +17,7 @@ speedup and its solution error against the FP64 solution.
 
 Output: one JSON line (rank 0).  ``roofline`` is for the fused inner
 SpMV+sketch kernel: algorithmic bytes per launch,
-12 nnz + 20 n + 8 n nwin + 8 ceil(zeta/4) n (values and column indices, row
+12 nnz + 20 n + 8 n nwin + 12 ceil(zeta/8) n (values and column indices, row
 pointers, the input vector, the output vector, the nwin Arnoldi window
 vectors its fused dot products read, and the packed sketch columns),
 divided by the kernel's mean duration measured with HIP events on the
@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, averaged over the working dispatches of one FP64 solve.  Valid only for
 # the kernel source it was measured on; None whenever that kernel changes.
-PMC_TRAFFIC_BYTES = 289561784
+PMC_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -120,8 +120,8 @@ def fused_rate(infos, A, t, m, zeta, fp32):
     ms = sum(i["spmv_ms"] for i in infos)
     win = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in infos)
     vb = 4 if fp32 else 8
-    zb = (zeta + 3) // 4
-    nbytes = (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches) + 8 * zb * A.n
+    zg = (zeta + 7) // 8  # packed sketch: groups of 12 bytes per column
+    nbytes = (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches) + 12 * zg * A.n
     avg = ms * 1e-3 / launches
     return avg, nbytes
 
@@ -265,8 +265,8 @@ def main():
     if wl != launches:
         raise RuntimeError(f"launch count mismatch {wl} vs {launches}")
     avg_s = spmv_ms * 1e-3 / launches
-    zb = (zeta + 3) // 4
-    bytes_per_launch = 12 * A.nnz + 20 * A.n + 8 * A.n * (win / launches) + 8 * zb * A.n
+    zg = (zeta + 7) // 8  # packed sketch: groups of 12 bytes per column
+    bytes_per_launch = 12 * A.nnz + 20 * A.n + 8 * A.n * (win / launches) + 12 * zg * A.n
     achieved = bytes_per_launch / avg_s / 1e9
     log(f"fused spmv+sketch: {launches} launches, mean {avg_s * 1e6:.2f} us, "
         f"{bytes_per_launch / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
@@ -314,7 +314,7 @@ def main():
         ml = sum(i["spmv_launches"] for i in ims)
         mms = sum(i["spmv_ms"] for i in ims)
         mwin = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in ims)
-        mbytes = 8 * A.nnz + 12 * A.n + 4 * A.n * (mwin / ml) + 8 * zb * A.n
+        mbytes = 8 * A.nnz + 12 * A.n + 4 * A.n * (mwin / ml) + 12 * zg * A.n
         mavg = mms * 1e-3 / ml
         result["mixed"] = {
             "time_to_tol_s": msec, "speedup_vs_fp64": sec / msec,

@@ -55,11 +55,23 @@ constexpr int kDP = kMaxT + 2;
 // Columns appended to the sketched QR by one decision launch (at most).
 constexpr int kPanel = 8;
 
-// Packed sketch: every column r of S is stored as 4*ZB 16-bit fields
-// (ZB = ceil(zeta/4), a multiple of 8 bytes per column): bits 0..14 hold
-// the row in [0, s), bit 15 the sign (1 = negative); unused fields are
-// 0xFFFF.
-constexpr uint16_t kSkEmpty = 0xFFFFu;
+// Packed sketch: the zeta entries (row in [0, s), s <= 1024, and sign) of
+// column r of S in ceil(zeta/8) groups of eight 12-bit fields, three 32-bit
+// words per group (12 bytes for zeta <= 8).  Field e of a group: row bits
+// 0..7 in byte e%4 of word e/4; row bits 8..10 and the sign (bit 3 set:
+// negative) in the 4-bit nibble e of word 2.  Fields past zeta are zero and
+// are skipped by every reader (zeta is uniform over a launch).
+constexpr int kSkGroup = 8;
+struct SkGroup {
+  uint32_t w[3];
+};
+__host__ __device__ inline int sk_groups(int zeta) { return (zeta + kSkGroup - 1) / kSkGroup; }
+__host__ __device__ inline int sk_row(const SkGroup& g, int e) {
+  return (int)(((g.w[e >> 2] >> ((e & 3) * 8)) & 0xFFu) | (((g.w[2] >> (e * 4)) & 7u) << 8));
+}
+__host__ __device__ inline bool sk_neg(const SkGroup& g, int e) {
+  return ((g.w[2] >> (e * 4)) & 8u) != 0;
+}
 
 // Device control block (lives in the workspace).  Scalars are written by
 // one-workgroup kernels only.
@@ -116,7 +128,7 @@ struct Layout {
 
 // Bytes of the packed sketch of an n-column S with zeta nonzeros per column.
 inline size_t packed_sketch_bytes(int64_t n, int32_t zeta) {
-  return (size_t)n * (size_t)((zeta + 3) / 4) * 8;
+  return (size_t)n * (size_t)sk_groups(zeta) * sizeof(SkGroup);
 }
 
 // ---------------------------------------------------------------- Philox
@@ -181,24 +193,23 @@ __device__ __forceinline__ void sketch_column(uint32_t col, int s, int zeta, uin
   }
 }
 
-// Scatter +-v into the LDS accumulators of column `col` of S, read from the
-// packed sketch (ZB 8-byte groups per column).  Every wave owns a private
-// copy of the s accumulators (a workgroup sums its copies in wave order at
-// the end), so the order of the additions into one accumulator depends only
-// on the static row-to-lane assignment and the sketch of a vector is
-// reproducible bit for bit from run to run.
+// Scatter of v (the value of entry `col` of a vector) into the s LDS
+// accumulators through column col of the packed sketch (ZB groups).  Every
+// wave owns a private copy of the s accumulators (a workgroup sums its
+// copies in wave order at the end), so the order of the additions into one
+// accumulator depends only on the static row-to-lane assignment and the
+// sketch of a vector is reproducible bit for bit from run to run.
 template <int ZB>
-__device__ __forceinline__ void sketch_scatter_packed(double* lds_sk, const uint2* __restrict__ skp,
-                                                      int64_t col, double v) {
+__device__ __forceinline__ void sketch_scatter_packed(double* lds_sk, const SkGroup* __restrict__ skp,
+                                                      int zeta, int64_t col, double v) {
 #pragma unroll
   for (int b = 0; b < ZB; ++b) {
-    const uint2 q = skp[col * ZB + b];
-    const uint32_t f[4] = {q.x & 0xFFFFu, q.x >> 16, q.y & 0xFFFFu, q.y >> 16};
+    const SkGroup q = skp[col * ZB + b];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-      if (f[e] != kSkEmpty) {
-        const double a = (f[e] & 0x8000u) ? -v : v;
-        __hip_atomic_fetch_add(&lds_sk[f[e] & 0x7FFFu], a, __ATOMIC_RELAXED,
+    for (int e = 0; e < kSkGroup; ++e) {
+      if (b * kSkGroup + e < zeta) {
+        const double a = sk_neg(q, e) ? -v : v;
+        __hip_atomic_fetch_add(&lds_sk[sk_row(q, e)], a, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_WORKGROUP);
       }
     }

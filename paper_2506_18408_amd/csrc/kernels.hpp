@@ -34,7 +34,8 @@ struct SpmvArgs {
   const double* vj;         // kModeOuter: v_j
   const double* v0;         // kModeOuter: v_1
   int32_t s;                // sketch rows (0: no sketch)
-  const uint2* skp;         // packed sketch
+  int32_t zeta;             // nonzeros per sketch column
+  const SkGroup* skp;       // packed sketch
   const void* U;            // window base (same type as val), column-major
   int64_t ldu;
   int32_t l0, nwin;         // window columns [l0, l0 + nwin)
@@ -43,7 +44,8 @@ struct SpmvArgs {
   const DevCtl* ctl;
 };
 
-// Number of 8-byte groups per packed sketch column.
+// Number of Philox4x32 blocks (four entries each) that generate one sketch
+// column.
 __host__ __device__ inline int zeta_blocks(int zeta) { return (zeta + 3) / 4; }
 
 // Row tiles of the SpMV kernels (rows_per_tile > 0: fixed row count, else
@@ -54,8 +56,8 @@ hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, i
                              hipStream_t st);
 // Waves per SpMV workgroup for an s-row sketch (0: none), bounded by LDS.
 int spmv_waves(int s, bool short_tiles);
-// ev0/ev1 non-null: the launch records them at the kernel's own start and
-// end (timing of the kernel alone).
+// zb = sk_groups(zeta) with a sketch, else 0.  ev0/ev1 non-null: the launch
+// records them at the kernel's own start and end (timing of the kernel alone).
 hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,
                        hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 
@@ -67,8 +69,8 @@ hipError_t launch_spmv_finish(int mode, const double* dpart, int32_t G, DevCtl* 
 // Sketch generation (Philox4x32-10 + Floyd) into the packed format, and its
 // export as (row, sign) arrays for tests.
 hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, uint32_t k1,
-                              uint2* skp, hipStream_t st);
-hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const uint2* skp, int32_t* rows,
+                              SkGroup* skp, hipStream_t st);
+hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const SkGroup* skp, int32_t* rows,
                                 int8_t* signs, hipStream_t st);
 
 // Multi-workgroup reduction of sketch rows: for the ring slots
@@ -159,7 +161,8 @@ hipError_t launch_mgs_finish(const double* vpart, int32_t G, double* hout, DevCt
                              int32_t ldh, HostStatus* hs, hipStream_t st);
 hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double* W,
                                    const double* hptr, double* Vout, void* Bout, int32_t s,
-                                   const uint2* skp, int zb, double* part, hipStream_t st);
+                                   const SkGroup* skp, int32_t zeta, double* part,
+                                   hipStream_t st);
 hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
                            const double* sigma, int32_t m, double* y, hipStream_t st);
 // out = add + sum_l y_l B_l (l < k); with `scale` (device scalar) the sum is

@@ -248,7 +248,7 @@ struct Ptrs {
   int32_t *tiles, *tp, *ipart;
   double *part, *dpart, *vpart, *red, *V, *T, *R, *d, *scal, *tau, *ice_x, *ice_z, *sigma, *coef, *yin,
       *H, *HR, *cs, *sn, *g, *yout, *Vb, *Zb, *W64, *X;
-  uint2* skp;
+  SkGroup* skp;
   void* Bb;
   float *W32, *val32;
 };
@@ -263,7 +263,7 @@ Ptrs make_ptrs(char* base, const Layout& L) {
   p.dpart = reinterpret_cast<double*>(base + L.dpart);
   p.vpart = reinterpret_cast<double*>(base + L.vpart);
   p.red = reinterpret_cast<double*>(base + L.red);
-  p.skp = reinterpret_cast<uint2*>(base + L.skp);
+  p.skp = reinterpret_cast<SkGroup*>(base + L.skp);
   p.V = reinterpret_cast<double*>(base + L.qr_V);
   p.T = reinterpret_cast<double*>(base + L.qr_T);
   p.R = reinterpret_cast<double*>(base + L.qr_R);
@@ -339,7 +339,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int ldh = J + 1;
   const int64_t ld = L.ld;
   const size_t vt = f32 ? 4 : 8;
-  const int zb = zeta_blocks(zeta);
+  const int zb = sk_groups(zeta);
   const uint32_t k0 = (uint32_t)(seed & 0xFFFFFFFFu);
   const uint32_t k1 = (uint32_t)(seed >> 32);
   const double inv_sqrt_zeta = 1.0 / sqrt((double)zeta);
@@ -409,6 +409,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   base_args.ctl = P.ctl;
   base_args.scale_val = 1.0;
   base_args.skp = P.skp;
+  base_args.zeta = zeta;
 
   QrBlockArgs qa{};
   qa.red = P.red;
@@ -433,7 +434,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   // 0, reduced, then d0 and the cycle reset
   auto sketch_v_and_init = [&](const double* W, const double* hptr, double* vout,
                                int32_t forced_k) -> int {
-    SFG_HIP(launch_normalize_sketch(f32, Gn, n, W, hptr, vout, Bcol(0), s, P.skp, zb, P.part,
+    SFG_HIP(launch_normalize_sketch(f32, Gn, n, W, hptr, vout, Bcol(0), s, P.skp, zeta, P.part,
                                     st));
     SFG_HIP(launch_reduce_slots(P.part, Gn, s, s, 0, 1, nring, slot_part, slot_red, P.red, P.ctl,
                                 false, st));
@@ -946,7 +947,7 @@ int sfgmres_sketch_materialize(sfgmres_handle h, int64_t n, int32_t s, int32_t z
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
-  uint2* skp = reinterpret_cast<uint2*>(static_cast<char*>(ws) + L.skp);
+  SkGroup* skp = reinterpret_cast<SkGroup*>(static_cast<char*>(ws) + L.skp);
   SFG_HIP(launch_sketch_pack(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32),
                              skp, st));
   SFG_HIP(launch_sketch_unpack(n, zeta, skp, rows, signs, st));
@@ -968,13 +969,13 @@ int sfgmres_sketch_apply(sfgmres_handle h, int64_t n, int32_t s, int32_t zeta, u
   DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
   double* part = reinterpret_cast<double*>(base + L.part);
   double* red = reinterpret_cast<double*>(base + L.red);
-  uint2* skp = reinterpret_cast<uint2*>(base + L.skp);
+  SkGroup* skp = reinterpret_cast<SkGroup*>(base + L.skp);
   const int G = rows_grid(n);
   SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
   SFG_HIP(launch_sketch_pack(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32),
                              skp, st));
-  SFG_HIP(launch_normalize_sketch(false, G, n, w, nullptr, nullptr, nullptr, s, skp,
-                                  zeta_blocks(zeta), part, st));
+  SFG_HIP(launch_normalize_sketch(false, G, n, w, nullptr, nullptr, nullptr, s, skp, zeta, part,
+                                  st));
   SFG_HIP(launch_reduce_slots(part, G, s, s, 0, 1, 1, 0, 0, red, ctl, false, st));
   SFG_HIP(launch_sketch_out(red, s, 1.0 / sqrt((double)zeta), nullptr, 0, 0, out, nullptr,
                             nullptr, st));
@@ -1010,7 +1011,7 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   double* part = reinterpret_cast<double*>(base + L.part);
   double* dpart = reinterpret_cast<double*>(base + L.dpart);
   double* red = reinterpret_cast<double*>(base + L.red);
-  uint2* skp = reinterpret_cast<uint2*>(base + L.skp);
+  SkGroup* skp = reinterpret_cast<SkGroup*>(base + L.skp);
   Tiling tiling{};
   const int prc = plan_tiling(h, A, tiles, tp, ipart, st, &tiling);
   if (prc) return prc;
@@ -1033,6 +1034,7 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   a.w = w;
   a.s = s;
   a.skp = skp;
+  a.zeta = zeta;
   a.U = U;
   a.ldu = ldu;
   a.l0 = 0;
@@ -1040,7 +1042,7 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
   a.part = part;
   a.dpart = dpart;
   a.ctl = ctl;
-  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, zeta_blocks(zeta), st));
+  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, sk_groups(zeta), st));
   SFG_HIP(launch_reduce_slots(part, Gp, s, s, 0, 1, 1, 0, 0, red, ctl, false, st));
   SFG_HIP(launch_sketch_out(red, s, 1.0 / sqrt((double)zeta), dpart, Gp, nwin, c, dots, norm2,
                             st));

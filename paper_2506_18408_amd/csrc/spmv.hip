@@ -126,7 +126,7 @@ __host__ __device__ constexpr int stage_doubles(bool short_tiles) {
 // accumulators and one slot that absorbs the empty entries of the packed
 // sketch.
 __host__ __device__ constexpr int wave_lds_doubles(int s, bool short_tiles) {
-  return stage_doubles(short_tiles) + (s > 0 ? s + 1 : 0);
+  return stage_doubles(short_tiles) + (s > 0 ? s : 0);
 }
 
 // s_waitcnt operand that waits for every outstanding vector memory access
@@ -154,13 +154,16 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // per wave: the products of its tile, then (sketching) its s accumulators
   extern __shared__ double lds[];
 
-  if (MODE == kModeInner && a.ctl->stop_k != 0) return;
+  // (a launch past the cycle's stop does nothing; the flag is tested once
+  // this wave's first tile bounds are in flight)
+  const int stop_k = MODE == kModeInner ? a.ctl->stop_k : 0;
 
   const int tid = threadIdx.x;
   const int lane = tid & (kWave - 1);
   const int wv = __builtin_amdgcn_readfirstlane(tid / kWave);  // (uniform: scalar loop control)
   const int nw = blockDim.x / kWave;
   const int S = kSketch ? a.s : 0;
+  const int zeta = a.zeta;
   // (the short-row path pays for itself with FP32 values only: staging FP64
   // values doubles its LDS traffic, and their row-wise reads conflict)
   const bool short_tiles = sizeof(VT) == 4 && a.short_tiles != 0;
@@ -190,7 +193,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   const int nwin = NW < a.nwin ? NW : a.nwin;
 
   if (kSketch)
-    for (int q = lane; q <= S; q += kWave) wave_sk[q] = 0.0;
+    for (int q = lane; q < S; q += kWave) wave_sk[q] = 0.0;
 
   double dacc[NW > 0 ? NW : 1];
 #pragma unroll
@@ -200,7 +203,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // inputs of the epilogue of row r, independent of the row sum
   struct Pre {
     VT u[NW > 0 ? NW : 1];  // (converted at use, so the loads stay in flight)
-    uint2 sk[ZB > 0 ? ZB : 1];
+    SkGroup sk[ZB > 0 ? ZB : 1];
     double b0, b1;
   };
   auto load_pre = [&](int r, Pre& p) {
@@ -225,15 +228,13 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
       if constexpr (kSketch) {
 #pragma unroll
         for (int b = 0; b < ZB; ++b) {
-          const uint32_t f[4] = {p.sk[b].x & 0xFFFFu, p.sk[b].x >> 16, p.sk[b].y & 0xFFFFu,
-                                 p.sk[b].y >> 16};
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            // (an empty entry lands in the spare slot S)
-            const int row = f[e] == kSkEmpty ? S : (int)(f[e] & 0x7FFFu);
-            const double av = (f[e] & 0x8000u) ? -wd : wd;
-            __hip_atomic_fetch_add(&wave_sk[row], av, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+          for (int e = 0; e < kSkGroup; ++e) {
+            if (b * kSkGroup + e < zeta) {  // (uniform)
+              const double av = sk_neg(p.sk[b], e) ? -wd : wd;
+              __hip_atomic_fetch_add(&wave_sk[sk_row(p.sk[b], e)], av, __ATOMIC_RELAXED,
+                                     __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
           }
         }
       }
@@ -270,13 +271,16 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // is outstanding and waited for at once, so the common path never waits.
   int ch_r0 = 0, ch_r1 = 0, ch_p0 = 0, ch_p1 = 0;
   const int nt = t0 < t1 ? (t1 - t0 + nw - 1) / nw : 0;
-  auto load_chunk = [&](int c) {
+  auto request_chunk = [&](int c) {
     int tj = t0 + (c * kWave + lane) * nw;
     tj = tj < t1 ? tj : t1 - 1;
     ch_r0 = a.tiles[tj];
     ch_r1 = a.tiles[tj + 1];
     ch_p0 = a.tp[tj];
     ch_p1 = a.tp[tj + 1];
+  };
+  auto load_chunk = [&](int c) {
+    request_chunk(c);
     __builtin_amdgcn_s_waitcnt(kWaitVmem0);
   };
   auto tile_bounds = [&](int j) {
@@ -403,6 +407,11 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
     }
   };
 
+  if (nt > 0) request_chunk(0);
+  if (stop_k != 0) {
+    __builtin_amdgcn_s_waitcnt(kWaitVmem0);  // (no load left in flight at exit)
+    return;
+  }
   // Wave pacing.  At equal priority a SIMD issues for its oldest wave
   // first, so the waves of a workgroup finish in order of age (for the
   // 128^3 stencil the last group of four 12 us after the first, while the
@@ -495,7 +504,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
     };
     TileB bc{}, bg{}, bf{};
     if (nt > 0) {
-      load_chunk(0);
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);  // (the first chunk, requested above)
       bg = tile_bounds(0);
       fetch_s(bg);
       __builtin_amdgcn_s_waitcnt(kWaitVmem0);
@@ -538,7 +547,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   } else {
     TileB bc{}, bg{}, bf{};
     if (nt > 0) {
-      load_chunk(0);
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);  // (the first chunk, requested above)
       bg = tile_bounds(0);
       fetch(bg);
       gather(bg);
@@ -660,12 +669,8 @@ static hipError_t launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
       return launch_one<VT, 0, MODE, NW>(c, a);
     case 1:
       return launch_one<VT, 1, MODE, NW>(c, a);
-    case 2:
-      return launch_one<VT, 2, MODE, NW>(c, a);
-    case 3:
-      return launch_one<VT, 3, MODE, NW>(c, a);
     default:
-      return launch_one<VT, 4, MODE, NW>(c, a);
+      return launch_one<VT, 2, MODE, NW>(c, a);
   }
 }
 
@@ -757,29 +762,38 @@ hipError_t launch_spmv_finish(int mode, const double* dpart, int32_t G, DevCtl* 
 }
 
 // ------------------------------------------------------------ packed sketch
+// (ZB Philox blocks of four entries generate a column; it is stored as
+// sk_groups(zeta) packed groups)
 template <int ZB>
 __global__ void k_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, uint32_t k1,
-                              uint2* __restrict__ skp) {
+                              SkGroup* __restrict__ skp) {
+  constexpr int kG = (4 * ZB + kSkGroup - 1) / kSkGroup;
+  const int ng = sk_groups(zeta);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
     int rows[4 * ZB];
     uint32_t neg;
     sketch_column<ZB>((uint32_t)r, s, zeta, k0, k1, rows, neg);
 #pragma unroll
-    for (int b = 0; b < ZB; ++b) {
-      uint32_t f[4];
+    for (int b = 0; b < kG; ++b) {
+      if (b >= ng) break;
+      SkGroup q{{0u, 0u, 0u}};
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int d = 4 * b + e;
-        f[e] = d < zeta ? ((uint32_t)rows[d] | (((neg >> d) & 1u) << 15)) : kSkEmpty;
+      for (int e = 0; e < kSkGroup; ++e) {
+        const int d = kSkGroup * b + e;
+        if (d < zeta && d < 4 * ZB) {
+          const uint32_t row = (uint32_t)rows[d];
+          q.w[e >> 2] |= (row & 0xFFu) << ((e & 3) * 8);
+          q.w[2] |= (((row >> 8) & 7u) | (((neg >> d) & 1u) << 3)) << (e * 4);
+        }
       }
-      skp[r * ZB + b] = make_uint2(f[0] | (f[1] << 16), f[2] | (f[3] << 16));
+      skp[r * ng + b] = q;
     }
   }
 }
 
 hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, uint32_t k1,
-                              uint2* skp, hipStream_t st) {
+                              SkGroup* skp, hipStream_t st) {
   const int grid = vec_grid(n);
   switch (zeta_blocks(zeta)) {
     case 1:
@@ -798,22 +812,20 @@ hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, u
   return hipGetLastError();
 }
 
-__global__ void k_sketch_unpack(int64_t n, int32_t zeta, const uint2* __restrict__ skp,
+__global__ void k_sketch_unpack(int64_t n, int32_t zeta, const SkGroup* __restrict__ skp,
                                 int32_t* __restrict__ rows, int8_t* __restrict__ signs) {
-  const int zb = zeta_blocks(zeta);
+  const int ng = sk_groups(zeta);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
     for (int d = 0; d < zeta; ++d) {
-      const uint2 q = skp[r * zb + d / 4];
-      const uint32_t word = (d & 2) ? q.y : q.x;
-      const uint32_t f = (d & 1) ? (word >> 16) : (word & 0xFFFFu);
-      rows[r * zeta + d] = (int32_t)(f & 0x7FFFu);
-      signs[r * zeta + d] = (f & 0x8000u) ? (int8_t)-1 : (int8_t)1;
+      const SkGroup q = skp[r * ng + d / kSkGroup];
+      rows[r * zeta + d] = (int32_t)sk_row(q, d % kSkGroup);
+      signs[r * zeta + d] = sk_neg(q, d % kSkGroup) ? (int8_t)-1 : (int8_t)1;
     }
   }
 }
 
-hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const uint2* skp, int32_t* rows,
+hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const SkGroup* skp, int32_t* rows,
                                 int8_t* signs, hipStream_t st) {
   hipLaunchKernelGGL(k_sketch_unpack, dim3(vec_grid(n)), dim3(256), 0, st, n, zeta, skp, rows,
                      signs);

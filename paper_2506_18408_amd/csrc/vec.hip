@@ -381,8 +381,9 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
                                                         const double* hptr,
                                                         double* __restrict__ Vout,
                                                         VT* __restrict__ Bout,
-                                                        const uint2* __restrict__ skp,
-                                                        int32_t s, double* __restrict__ part) {
+                                                        const SkGroup* __restrict__ skp,
+                                                        int32_t zeta, int32_t s,
+                                                        double* __restrict__ part) {
   extern __shared__ double lds_sk[];  // per-wave copies of the s accumulators
   constexpr int kWaves = kVecThreads / kWave;
   const int tid = threadIdx.x;
@@ -402,7 +403,7 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
       v = W[r];
     if (Vout) Vout[r] = v;
     if (Bout) Bout[r] = static_cast<VT>(v);
-    sketch_scatter_packed<ZB>(wave_sk, skp, r, v);
+    sketch_scatter_packed<ZB>(wave_sk, skp, zeta, r, v);
   }
   __syncthreads();
   double* prow = part + (int64_t)blockIdx.x * s;
@@ -417,37 +418,27 @@ __global__ __launch_bounds__(kVecThreads) void k_normsk(int64_t n, const double*
 template <typename VT>
 static void launch_normsk_t(int zb, int grid, size_t lds, hipStream_t st, int64_t n,
                             const double* W, const double* hptr, double* Vout, VT* Bout,
-                            const uint2* skp, int32_t s, double* part) {
-  switch (zb) {
-    case 1:
-      hipLaunchKernelGGL((k_normsk<VT, 1>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part);
-      break;
-    case 2:
-      hipLaunchKernelGGL((k_normsk<VT, 2>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part);
-      break;
-    case 3:
-      hipLaunchKernelGGL((k_normsk<VT, 3>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part);
-      break;
-    default:
-      hipLaunchKernelGGL((k_normsk<VT, 4>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
-                         Vout, Bout, skp, s, part);
-      break;
-  }
+                            const SkGroup* skp, int32_t zeta, int32_t s, double* part) {
+  if (zb == 1)
+    hipLaunchKernelGGL((k_normsk<VT, 1>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
+                       Vout, Bout, skp, zeta, s, part);
+  else
+    hipLaunchKernelGGL((k_normsk<VT, 2>), dim3(grid), dim3(kVecThreads), lds, st, n, W, hptr,
+                       Vout, Bout, skp, zeta, s, part);
 }
 
 hipError_t launch_normalize_sketch(bool fp32, int grid, int64_t n, const double* W,
                                    const double* hptr, double* Vout, void* Bout, int32_t s,
-                                   const uint2* skp, int zb, double* part, hipStream_t st) {
+                                   const SkGroup* skp, int32_t zeta, double* part,
+                                   hipStream_t st) {
   const size_t lds = (size_t)(kVecThreads / kWave) * s * sizeof(double);
+  const int zb = sk_groups(zeta);
   if (fp32)
     launch_normsk_t<float>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<float*>(Bout), skp,
-                           s, part);
+                           zeta, s, part);
   else
     launch_normsk_t<double>(zb, grid, lds, st, n, W, hptr, Vout, static_cast<double*>(Bout), skp,
-                            s, part);
+                            zeta, s, part);
   return hipGetLastError();
 }
 
