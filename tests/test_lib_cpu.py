@@ -65,7 +65,8 @@ def test_workspace_bytes(lib):
 
 def test_small_workspace_queries(lib):
     out = C.c_size_t()
-    assert lib.sfgmres_sketch_workspace_bytes(10**6, 400, 8, C.byref(out)) == 0 and out.value > 16 * 10**6
+    # (at least the packed sketch: 12 bytes per column at zeta = 8)
+    assert lib.sfgmres_sketch_workspace_bytes(10**6, 400, 8, C.byref(out)) == 0 and out.value >= 12 * 10**6
     assert lib.sfgmres_sketch_workspace_bytes(10**6, 5000, 8, C.byref(out)) == L.ERR_INVALID
     assert lib.sfgmres_transpose_workspace_bytes(100, 500, C.byref(out)) == 0
     assert lib.sfgmres_spmv_workspace_bytes(100, 500, 60, 8, C.byref(out)) == 0
