@@ -21,7 +21,7 @@ SpMV+sketch kernel: algorithmic bytes per launch,
 pointers, the input vector, the output vector, the nwin Arnoldi window
 vectors its fused dot products read, and the packed sketch columns),
 divided by the kernel's mean duration measured with HIP events on the
-library's stream over the timed solves (every 8th inner step's launch, the
+library's stream over the timed solves (every 7th inner step's launch, the
 events being recorded by the launch itself at the kernel's start and end).  ``cpu_baseline`` times the CPU
 oracle on the first outer step of the same solve (k_1 inner steps, one
 thread) and scales its per-inner-step time to the GPU run's total inner
@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, averaged over the working dispatches of one FP64 solve.  Valid only for
 # the kernel source it was measured on; None whenever that kernel changes.
-PMC_TRAFFIC_BYTES = None
+PMC_TRAFFIC_BYTES = 272209751
 
 
 def log(*a):
@@ -92,7 +92,11 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
 
 
-PROFILE_STRIDE = 8      # time the fused kernel on every 8th inner step (events cost ~10 us)
+# Time the fused kernel on every 7th inner step (an event-carrying launch
+# costs ~10 us of dispatch).  7 is co-prime with the 8 steps of a decision
+# panel, so the timed launches cover every position in a panel: the launches
+# at a panel's start run beside the decision kernel and take ~5% longer.
+PROFILE_STRIDE = 7
 
 
 def window_sum(inner_k, stop_reason, t, m, panel=8, stride=PROFILE_STRIDE):
