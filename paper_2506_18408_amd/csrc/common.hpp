@@ -44,6 +44,7 @@ constexpr int kMaxGrid = 1024;
 // workgroup in the vector partial buffer).
 constexpr int kVecThreads = 256;
 constexpr int kVecGrid = 1024;
+constexpr int kArnoldiGrid = 512;  // (<= kVecGrid)
 // Partial sums written by every multi-workgroup kernel, one row per
 // workgroup (slot = blockIdx.x):
 //   sketch rows: s accumulators (sum of +-w_r, unscaled), row stride s;

@@ -183,5 +183,6 @@ hipError_t launch_transpose(const int32_t* row_ptr, const int32_t* col_idx, cons
 
 size_t transpose_scan_tmp_ints(int64_t n);
 int vec_grid(int64_t n);
+int arnoldi_grid(int64_t n);
 
 }  // namespace sfg

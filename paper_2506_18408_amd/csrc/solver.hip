@@ -390,6 +390,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int Gp = tiling.grid;
   const int Gn = rows_grid(n);
   const int G2 = vec_grid(n);
+  const int Ga = arnoldi_grid(n);  // the Arnoldi update (and its norm partials)
   memset((void*)hsh, 0, sizeof(HostStatus));
   SFG_HIP(launch_init_ctl(P.ctl, m, t, s, cond_threshold_of(o), tol, st));
   if (f32) SFG_HIP(launch_cast_f32(A->val, P.val32, nnz, st));
@@ -560,17 +561,17 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
         aa.dpart = P.dpart;
         aa.Gd = Gp;
         aa.vprev = vprev;
-        aa.Gv = G2;
+        aa.Gv = Ga;
         aa.vnext = vnext;
         aa.sigma = P.sigma;
         aa.ctl = P.ctl;
-        SFG_HIP(launch_arnoldi_update(f32, G2, aa, st));
+        SFG_HIP(launch_arnoldi_update(f32, Ga, aa, st));
       } else {
         CoefArgs ca{};
         ca.dpart = P.dpart;
         ca.G = Gp;
         ca.vpart = vprev;
-        ca.Gv = G2;
+        ca.Gv = Ga;
         ca.t = t;
         ca.nwin = nwin;
         ca.l0 = l0;

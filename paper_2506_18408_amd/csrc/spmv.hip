@@ -416,12 +416,12 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // first, so the waves of a workgroup finish in order of age (for the
   // 128^3 stencil the last group of four 12 us after the first, while the
   // barrier below waits for all of them).  A wave starts at priority 3 and
-  // steps down after 1/2, 3/4 and 9/10 of its tiles, so waves that are
+  // steps down after 1/4, 1/2 and 3/4 of its tiles, so waves that are
   // ahead yield to those behind.  The tile assignment is unchanged.
   __builtin_amdgcn_s_setprio(3);
   int pstage = 0;
   auto pace = [&](int i) {
-    const int st = (2 * i >= nt) + (4 * i >= 3 * nt) + (10 * i >= 9 * nt);
+    const int st = (4 * i >= nt) + (2 * i >= nt) + (4 * i >= 3 * nt);
     if (st != pstage) {
       pstage = st;
       if (st == 1)
