@@ -75,6 +75,8 @@ def parse():
                     help="override the C2 condition threshold (other workloads)")
     ap.add_argument("--outer", default=None, choices=["fgmres", "restarted"],
                     help="outer iteration (other workloads): FGMRES or restarted sGMRES")
+    ap.add_argument("--adjoint", action="store_true",
+                    help="workloads 4 and 5: time the adjoint solve also when --precisions is given")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -151,7 +153,7 @@ def other_workload(args):
     precs = ["mixed"] if args.workload == 5 else ["fp64", "mixed"]
     if args.precisions:
         precs = args.precisions.split(",")
-    adjoint = args.workload in (4, 5) and args.precisions is None
+    adjoint = args.workload in (4, 5) and (args.precisions is None or args.adjoint)
     out = {"metric": "time-to-1e-8 rel. residual (s) per solve", "unit": "s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "higher_is_better": False,
            "data": "synthetic",
