@@ -93,6 +93,25 @@ def test_spmv_sketch_integer_bit_exact(case, nwin):
     assert nrm.item() == float(wo @ wo)
 
 
+@pytest.mark.parametrize("zeta", [1, 5, 9, 13, 16])
+def test_spmv_sketch_zeta_groups_integer_bit_exact(zeta):
+    """The packed sketch holds ceil(zeta/8) groups of eight entries; zeta of
+    1, 5 (one partial group), 9, 13 (a partial second group) and 16 (two
+    full groups), through the fused SpMV's scatter and through the plain
+    sketch kernel: integers, so every sum is exact and must match bit for
+    bit."""
+    A = _int_matrix(W.convdiff3d(21), 3)
+    n, s, seed = A.n, 300, 2**40 + 7
+    u = np.random.default_rng(zeta).integers(-8, 9, size=n).astype(np.float64)
+    So = oracle.sketch_matrix(n, s, zeta, seed)
+    w, c, _, _ = P.spmv_sketch(*to_dev(A), tvec(u), s, zeta, seed)
+    wo = A.to_scipy() @ u
+    assert np.array_equal(w.cpu().numpy(), wo)
+    assert np.array_equal(c.cpu().numpy(), oracle.apply_sketch(So, wo))
+    c2 = P.sketch_apply(tvec(u), s, zeta, seed).cpu().numpy()
+    assert np.array_equal(c2, oracle.apply_sketch(So, u))
+
+
 @pytest.mark.parametrize("case", ["convdiff3d_37", "powerlaw_200k", "long_and_empty_rows"])
 def test_spmv_sketch_real(case):
     A = SPMV_CASES[case]()
