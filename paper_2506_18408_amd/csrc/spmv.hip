@@ -123,8 +123,7 @@ __host__ __device__ constexpr int stage_doubles(bool short_tiles) {
   return short_tiles ? kShortStage : kGenStage;
 }
 // Doubles of LDS per wave: the stage, then, when sketching, the s sketch
-// accumulators and one slot that absorbs the empty entries of the packed
-// sketch.
+// accumulators.
 __host__ __device__ constexpr int wave_lds_doubles(int s, bool short_tiles) {
   return stage_doubles(short_tiles) + (s > 0 ? s : 0);
 }
