@@ -574,6 +574,21 @@ hipError_t launch_backsolve(const double* HR, const double* g, int32_t J, int32_
 
 // ------------------------------------------------- tall-skinny combination
 // out = add + sum_{l<k} y_l B[:, l], k read from the device (kdev) or given.
+// Each thread owns one 16-byte group of rows (four FP32 or two FP64 rows,
+// one load per column; the columns are 256-byte aligned with a leading
+// dimension that is a multiple of 64 elements) and sums every row over the
+// columns in order; rows past the last full group are done one by one.
+template <typename VT>
+struct Vec16;
+template <>
+struct Vec16<float> {
+  typedef float type __attribute__((ext_vector_type(4)));
+};
+template <>
+struct Vec16<double> {
+  typedef double type __attribute__((ext_vector_type(2)));
+};
+
 template <typename VT>
 __global__ __launch_bounds__(kVecThreads) void k_combine(int64_t n, const VT* __restrict__ B,
                                                          int64_t ldb,
@@ -581,24 +596,35 @@ __global__ __launch_bounds__(kVecThreads) void k_combine(int64_t n, const VT* __
                                                          const int32_t* kdev, int32_t khost,
                                                          const double* add, double* out,
                                                          const double* scale) {
+  using V = typename Vec16<VT>::type;
+  constexpr int kG = 16 / (int)sizeof(VT);
   extern __shared__ double ys[];
   const int k = kdev ? *kdev : khost;
   for (int l = threadIdx.x; l < k; l += kVecThreads) ys[l] = y[l];
   __syncthreads();
+  const double sc = scale ? *scale : 1.0;
   const int64_t stride = (int64_t)gridDim.x * kVecThreads;
-  if (scale) {  // (add and out may be the same vector)
-    const double sc = *scale;
-    for (int64_t r = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; r < n; r += stride) {
-      double z = 0.0;
-      for (int l = 0; l < k; ++l) z += ys[l] * static_cast<double>(B[(int64_t)l * ldb + r]);
-      out[r] = (add ? add[r] : 0.0) + sc * z;
+  const int64_t ng = n / kG;
+  // (with a scale the sum is formed first, then out = add + scale * sum;
+  // add and out may be the same vector)
+  for (int64_t gi = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; gi < ng; gi += stride) {
+    const int64_t r0 = gi * kG;
+    double acc[kG];
+#pragma unroll
+    for (int c = 0; c < kG; ++c) acc[c] = scale ? 0.0 : (add ? add[r0 + c] : 0.0);
+    for (int l = 0; l < k; ++l) {
+      const V b = *reinterpret_cast<const V*>(B + (int64_t)l * ldb + r0);
+#pragma unroll
+      for (int c = 0; c < kG; ++c) acc[c] += ys[l] * static_cast<double>(b[c]);
     }
-    return;
+#pragma unroll
+    for (int c = 0; c < kG; ++c)
+      out[r0 + c] = scale ? (add ? add[r0 + c] : 0.0) + sc * acc[c] : acc[c];
   }
-  for (int64_t r = (int64_t)blockIdx.x * kVecThreads + threadIdx.x; r < n; r += stride) {
-    double acc = add ? add[r] : 0.0;
+  for (int64_t r = ng * kG + (int64_t)blockIdx.x * kVecThreads + threadIdx.x; r < n; r += stride) {
+    double acc = scale ? 0.0 : (add ? add[r] : 0.0);
     for (int l = 0; l < k; ++l) acc += ys[l] * static_cast<double>(B[(int64_t)l * ldb + r]);
-    out[r] = acc;
+    out[r] = scale ? (add ? add[r] : 0.0) + sc * acc : acc;
   }
 }
 
@@ -607,7 +633,7 @@ hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, cons
                           hipStream_t st, const double* scale) {
   const int kmax = kdev ? kMaxM : khost;
   const size_t lds = (size_t)(kmax > 0 ? kmax : 1) * sizeof(double);
-  const int grid = vec_grid(n * kUnroll);
+  const int grid = vec_grid(n * kUnroll / (fp32 ? 4 : 2));
   if (fp32)
     hipLaunchKernelGGL(k_combine<float>, dim3(grid), dim3(kVecThreads), lds, st, n,
                        static_cast<const float*>(B), ldb, y, kdev, khost, add, out, scale);
