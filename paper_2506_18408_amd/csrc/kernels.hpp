@@ -41,8 +41,18 @@ struct SpmvArgs {
   int32_t l0, nwin;         // window columns [l0, l0 + nwin)
   double* part;             // sketch rows: gridDim.x rows of s doubles
   double* dpart;            // scalar rows: gridDim.x rows of kDP doubles
-  const DevCtl* ctl;
+  DevCtl* ctl;
+  // kModeInner, t = 0 after a cycle's first step (sig_part non-NULL): the
+  // scale sigma_i = 1/||u_i|| is formed from the previous step's scalar rows
+  // (sig_G <= kWave * kSigLoads of them) instead of read from scale_ptr;
+  // workgroup 0 stores it to sig_out and flags u_i = 0 as a breakdown at
+  // sig_step.
+  const double* sig_part;
+  int32_t sig_G, sig_step;
+  double* sig_out;
 };
+constexpr int kSigLoads = 4;
+static_assert(kSpmvGrid <= kWave * kSigLoads, "sig_part rows per lane");
 
 // Number of Philox4x32 blocks (four entries each) that generate one sketch
 // column.

@@ -89,7 +89,7 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.tp = take((size_t)(L.ntiles_max + 1) * 4);
   L.ipart = take((size_t)(kVecGrid + 1) * 4);
   L.part = take((size_t)2 * panel * kMaxGrid * s * 8);  // two panels of sketch rows
-  L.dpart = take((size_t)kMaxGrid * kDP * 8);
+  L.dpart = take((size_t)2 * kMaxGrid * kDP * 8);  // two: inner steps alternate
   L.vpart = take((size_t)2 * kVecGrid * 8);  // two: read by one Arnoldi update, written by it
   L.red = take((size_t)2 * panel * s * 8);
   L.skp = take(packed_sketch_bytes(n, zeta));
@@ -531,8 +531,19 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
       a.x = Bcol(i);
       // t = 0: y = sigma_i A u_i = A b_i is the next (unnormalised) power-basis
-      // vector; t > 0: y = A u_i, scaled inside the Arnoldi update
-      a.scale_ptr = (t == 0) ? P.sigma + i : nullptr;
+      // vector, sigma_i formed by the SpMV itself from the previous step's
+      // norm partials (sigma_0 is set with the cycle); t > 0: y = A u_i,
+      // scaled inside the Arnoldi update.  Scalar rows alternate between two
+      // buffers, so a step reads its predecessor's while writing its own.
+      double* const dcur = P.dpart + (int64_t)(i & 1) * kMaxGrid * kDP;
+      a.dpart = dcur;
+      a.scale_ptr = (t == 0 && i == 0) ? P.sigma : nullptr;
+      if (t == 0 && i > 0) {
+        a.sig_part = P.dpart + (int64_t)((i - 1) & 1) * kMaxGrid * kDP;
+        a.sig_G = Gp;
+        a.sig_step = i;
+        a.sig_out = P.sigma + i;
+      }
       a.w = (t == 0) ? Bcol(i + 1) : (f32 ? static_cast<void*>(P.W32) : static_cast<void*>(P.W64));
       a.s = s;
       a.U = P.Bb;
@@ -543,9 +554,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       const bool timed = o.profile > 0 && i % o.profile == o.profile - 1;
       SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st, timed ? h->ev[2 * i] : nullptr,
                           timed ? h->ev[2 * i + 1] : nullptr));
-      // sigma and the window coefficients: inside the Arnoldi update for
-      // t > 0 (norm partials alternate between two buffers), else (t = 0, or
-      // the cycle's last step) a one-workgroup kernel
+      // t > 0: sigma and the window coefficients inside the Arnoldi update
+      // (norm partials alternate between two buffers), or a one-workgroup
+      // kernel at the cycle's last step; t = 0: nothing (the next SpMV
+      // forms sigma)
       double* vprev = P.vpart + (int64_t)(i & 1) * kVecGrid;
       double* vnext = P.vpart + (int64_t)((i + 1) & 1) * kVecGrid;
       if (t > 0 && i + 1 < m) {
@@ -558,7 +570,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
         aa.nwin = nwin;
         aa.inext = i + 1;
         aa.step = i;
-        aa.dpart = P.dpart;
+        aa.dpart = dcur;
         aa.Gd = Gp;
         aa.vprev = vprev;
         aa.Gv = Ga;
@@ -566,9 +578,9 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
         aa.sigma = P.sigma;
         aa.ctl = P.ctl;
         SFG_HIP(launch_arnoldi_update(f32, Ga, aa, st));
-      } else {
+      } else if (t > 0) {
         CoefArgs ca{};
-        ca.dpart = P.dpart;
+        ca.dpart = dcur;
         ca.G = Gp;
         ca.vpart = vprev;
         ca.Gv = Ga;

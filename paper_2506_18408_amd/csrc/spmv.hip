@@ -186,9 +186,11 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   VT* __restrict__ w = static_cast<VT*>(a.w);
   const VT* __restrict__ U = static_cast<const VT*>(a.U);
   const bool has_x = (MODE != kModeResid) || a.has_x;
-  const double scale = (MODE == kModePlain)   ? a.scale_val
-                       : (MODE == kModeInner) ? (a.scale_ptr ? *a.scale_ptr : 1.0)
-                                              : 1.0;
+  // (t = 0 has no window: only the NW = 0 instances carry the sigma path)
+  const bool sig_here = MODE == kModeInner && NW == 0 && a.sig_part != nullptr;
+  double scale = (MODE == kModePlain)                 ? a.scale_val
+                 : (MODE == kModeInner && !sig_here) ? (a.scale_ptr ? *a.scale_ptr : 1.0)
+                                                     : 1.0;
   const int nwin = NW < a.nwin ? NW : a.nwin;
 
   if (kSketch)
@@ -406,10 +408,34 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
     }
   };
 
+  // t = 0 after a cycle's first step: sigma_i = 1/||u_i|| from the previous
+  // step's norm partials, requested before this wave's first tile bounds and
+  // summed by every wave in one fixed order (lane, then the wave's DPP
+  // tree), so that all waves hold the same value.  It replaces a
+  // one-workgroup kernel between the two SpMVs.
+  double sgp[kSigLoads];
+  if (sig_here) {
+#pragma unroll
+    for (int u = 0; u < kSigLoads; ++u) {
+      const int g = lane + u * kWave;
+      sgp[u] = a.sig_part[(int64_t)(g < a.sig_G ? g : a.sig_G - 1) * kDP + kMaxT];
+    }
+  }
   if (nt > 0) request_chunk(0);
   if (stop_k != 0) {
     __builtin_amdgcn_s_waitcnt(kWaitVmem0);  // (no load left in flight at exit)
     return;
+  }
+  if (sig_here) {
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < kSigLoads; ++u) v += lane + u * kWave < a.sig_G ? sgp[u] : 0.0;
+    const double n2 = wave_sum(v);
+    scale = n2 == 0.0 ? 0.0 : 1.0 / sqrt(n2);
+    if (blockIdx.x == 0 && tid == 0) {
+      *a.sig_out = scale;
+      if (n2 == 0.0 && a.ctl->brk_step < 0) a.ctl->brk_step = a.sig_step;  // u_step = 0
+    }
   }
   // Wave pacing.  At equal priority a SIMD issues for its oldest wave
   // first, so the waves of a workgroup finish in order of age (for the
