@@ -356,6 +356,32 @@ def test_exact_truncated_arnoldi_breakdown(panel):
         assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-12
 
 
+@pytest.mark.parametrize("panel", [1, 8])
+def test_zero_power_basis_vector(panel):
+    """t = 0 with the shift matrix A e_j = e_{j+1} and b = e_{n-2}: the second
+    power-basis vector A e_{n-1} is exactly zero, so its sketched column is
+    zero, C2 (an infinite condition estimate) keeps k = 1 on both sides, and
+    the least-squares coefficient is 0 (b is orthogonal to A e_{n-2}).  On the
+    device the SpMV of that step forms sigma = 0 from zero norm partials, so
+    nothing after it may turn into NaN."""
+    n = 50
+    A = W.CSR(n, np.concatenate(([0], np.arange(n, dtype=np.int32))).astype(np.int32),
+              np.arange(n - 1, dtype=np.int32), np.ones(n - 1))
+    assert np.array_equal(A.to_scipy().toarray(), np.eye(n, k=-1))
+    b = np.zeros(n)
+    b[n - 2] = 1.0
+    prm = dict(m=5, t=0, s=20, zeta=8, tol=1e-300, seed=2, max_outer=1)
+    ref = _oracle(A, b, prm)
+    assert ref.inner_k == [1] and ref.stop_reason == ["C2"]
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        x, info = _gpu(A, b, prm, panel=panel)
+    assert list(info["inner_k"]) == [1] and info["stop_reason"][0] == "C2"
+    h = np.asarray(info["residual_history"])
+    assert np.all(np.isfinite(h)) and abs(h[-1] - 1.0) <= 1e-14
+    assert np.all(np.isfinite(x.cpu().numpy())) and np.linalg.norm(x.cpu().numpy()) <= 1e-14
+
+
 @pytest.mark.parametrize("stride", [1, 4])
 def test_profile_counts_working_launches(stride):
     """profile = N times the fused kernel of inner steps N-1, 2N-1, ... that
