@@ -37,6 +37,11 @@ constexpr int kWStage = 512;
 constexpr int kShortRow = 8;
 constexpr int kRowTile = kWStage / kShortRow;
 constexpr int kTileNnz = kWStage / 2;
+// A matrix of more bytes than this per SpMV (well beyond the chip's 256 MB
+// last-level cache) whose rows are too long for short-row tiles is read by
+// the FP64 inner SpMV with streaming loads, so that it does not evict the x
+// entries its gathers reuse.
+constexpr size_t kStreamMatrixBytes = (size_t)300 << 20;
 constexpr int kSpmvLdsMax = 150 * 1024;  // dynamic LDS of one SpMV workgroup (bytes)
 // Bound on the number of partial rows any multi-workgroup kernel writes.
 constexpr int kMaxGrid = 1024;

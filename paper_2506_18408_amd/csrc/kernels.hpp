@@ -26,6 +26,7 @@ struct SpmvArgs {
   int32_t ntiles;
   int32_t short_tiles;      // 1: tiles of kRowTile rows, every row at most kShortRow nonzeros
   int32_t has_x;            // kModeResid: 0 means x = 0
+  int32_t stream_matrix;    // kModeInner, FP64 values: read the matrix with streaming loads
   const void* x;            // input vector, same type as val
   const double* scale_ptr;  // kModeInner: device scalar sigma (NULL: 1)
   double scale_val;         // kModePlain: w = scale * A u

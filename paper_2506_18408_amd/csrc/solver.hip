@@ -405,6 +405,8 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   base_args.tp = P.tp;
   base_args.ntiles = ntiles;
   base_args.short_tiles = tiling.max_row <= kShortRow;
+  base_args.stream_matrix =
+      !f32 && tiling.max_row > kShortRow && (size_t)nnz * 12 > kStreamMatrixBytes;
   base_args.part = P.part;
   base_args.dpart = P.dpart;
   base_args.ctl = P.ctl;

@@ -145,7 +145,17 @@ __device__ __forceinline__ void wave_sync() {
 template <int NW>
 constexpr int spmv_max_threads() { return NW > 4 ? 12 * kWave : kSpmvMaxThreads; }
 
-template <typename VT, int ZB, int MODE, int NW>
+// A matrix load: cached, or streaming (NT) for a matrix that cannot stay in
+// the last-level cache.
+template <bool NT, typename T>
+__device__ __forceinline__ T mat_load(const T* p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+
+template <typename VT, int ZB, int MODE, int NW, bool NT>
 __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   constexpr bool kSketch = ZB > 0;
   constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain);
@@ -299,17 +309,20 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // partial block with its index clamped into the tile).  Ordinary loads: the
   // matrix is read again by every inner step, and the chip's last-level
   // cache keeps much of it between steps; streaming (non-temporal) loads
-  // made each FP64 step ~10% slower.
+  // made each FP64 step ~10% slower.  A matrix far larger than that cache
+  // with irregular rows (NT, chosen by the host) takes streaming loads: it
+  // cannot stay resident, and cached loads of it would evict the x entries
+  // its random gathers reuse (1M power-law rows, FP64: -5% per solve).
   auto fetch = [&](const TileB& bt) {  // column indices
     if (!staged(bt)) return;
     const int32_t* cb = col_idx + bt.p0 + lane;
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if ((u + 1) * kWave <= bt.L) {
-        ci[u] = *(cb + u * kWave);
+        ci[u] = mat_load<NT>(cb + u * kWave);
       } else if (u * kWave < bt.L) {
         const int q = u * kWave + lane;
-        ci[u] = col_idx[bt.p0 + (q < bt.L ? q : bt.L - 1)];
+        ci[u] = mat_load<NT>(&col_idx[bt.p0 + (q < bt.L ? q : bt.L - 1)]);
       }
     }
   };
@@ -319,11 +332,11 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
       if ((u + 1) * kWave <= bt.L) {
-        vg[u] = *(vb + u * kWave);
+        vg[u] = mat_load<NT>(vb + u * kWave);
         xg[u] = x[ci[u]];
       } else if (u * kWave < bt.L) {
         const int q = u * kWave + lane;
-        vg[u] = val[bt.p0 + (q < bt.L ? q : bt.L - 1)];
+        vg[u] = mat_load<NT>(&val[bt.p0 + (q < bt.L ? q : bt.L - 1)]);
         xg[u] = x[ci[u]];
       }
     }
@@ -664,23 +677,31 @@ struct LaunchCfg {
   hipEvent_t ev0, ev1;
 };
 
-template <typename VT, int ZB, int MODE, int NW>
-static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
+template <typename VT, int ZB, int MODE, int NW, bool NT>
+static hipError_t launch_nt(const LaunchCfg& c, const SpmvArgs& a) {
   static bool attr_set = false;  // dynamic LDS above the default limit
   if (!attr_set) {
     const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<VT, ZB, MODE, NW>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<VT, ZB, MODE, NW, NT>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const dim3 block(c.waves * kWave);
   if (c.ev0)
-    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), block, c.lds, c.st, c.ev0,
-                          c.ev1, 0, a);
+    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW, NT>), dim3(c.grid), block, c.lds, c.st,
+                          c.ev0, c.ev1, 0, a);
   else
-    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW>), dim3(c.grid), block, c.lds, c.st, a);
+    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW, NT>), dim3(c.grid), block, c.lds, c.st, a);
   return hipGetLastError();
+}
+
+// (only the FP64 inner SpMV has a streaming-load instance)
+template <typename VT, int ZB, int MODE, int NW>
+static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
+  if constexpr (sizeof(VT) == 8 && MODE == kModeInner)
+    if (a.stream_matrix) return launch_nt<VT, ZB, MODE, NW, true>(c, a);
+  return launch_nt<VT, ZB, MODE, NW, false>(c, a);
 }
 
 template <typename VT, int MODE, int NW>
