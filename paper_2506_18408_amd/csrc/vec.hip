@@ -511,6 +511,7 @@ __global__ __launch_bounds__(kFinThreads) void k_finalize(const DevCtl* ctl, con
       const double yl = read_lane(rl, l % kWave) / dl;
 #pragma unroll
       for (int u = 0; u < kFinRows; ++u) {
+        if (u > ul) break;  // (uniform: the rows of blocks past ul are done)
         const int p = lane + u * kWave;
         if (p == l) yv[u] = yl;
         if (p < l) r[u] -= cl[p] * yl;
