@@ -23,7 +23,12 @@
 // packed sketch) and accumulate the dot products in registers.  At the end
 // the workgroup adds its wave copies in wave order and writes one row of
 // sketch partials and one row of scalar partials; later kernels combine the
-// rows in a fixed order, so results do not depend on timing.
+// rows in a fixed order, so results do not depend on timing.  Waves lower
+// their issue priority as they progress, so that the oldest wave of a SIMD
+// does not finish far ahead of the youngest while the final barrier waits.
+// At t = 0 the kernel forms its own scale sigma_i = 1/||u_i|| from the
+// previous step's norm partials; an FP64 matrix far beyond the last-level
+// cache with irregular rows is read through a streaming-load instance.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
