@@ -382,10 +382,13 @@ def test_zero_power_basis_vector(panel):
     assert np.all(np.isfinite(x.cpu().numpy())) and np.linalg.norm(x.cpu().numpy()) <= 1e-14
 
 
-@pytest.mark.parametrize("stride", [1, 4])
+@pytest.mark.parametrize("stride", [1, 4, 7])
 def test_profile_counts_working_launches(stride):
     """profile = N times the fused kernel of inner steps N-1, 2N-1, ... that
-    ran: every step up to the end of the panel holding the stopping column."""
+    ran: every step up to the end of the panel holding the stopping column.
+    The benchmark's count of timed launches (its window_sum, stride 7) must
+    be the same."""
+    from bench import window_sum
     A, b, prm = _case("c1")
     x, info = _gpu(A, b, prm, profile=stride)
     m, panel = prm["m"], 8
@@ -396,6 +399,8 @@ def test_profile_counts_working_launches(stride):
         want += len(range(stride - 1, steps, stride))
     assert info["spmv_launches"] == want
     assert info["spmv_ms"] > 0.0
+    assert window_sum(info["inner_k"], info["stop_reason"], prm["t"], m, panel=panel,
+                      stride=stride)[1] == want
 
 
 def test_invalid_panel_and_lookahead():
