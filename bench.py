@@ -298,7 +298,7 @@ def main():
                    "true_rel_residual": last["true_rel_residual"]},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": PMC_TRAFFIC_BYTES,
-                     "kernel": "k_spmv<double,2,kModeInner> (fused SpMV+sketch+window dots)",
+                     "kernel": "k_spmv<double, 1, kModeInner, 2, false> (fused SpMV+sketch+window dots; ZB = ceil(zeta/8) = 1, window 2)",
                      "bytes_per_launch": bytes_per_launch, "mean_launch_us": avg_s * 1e6,
                      "launches": launches},
     }
