@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 # of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 + WRITE_SIZE x
 # 1.0, averaged over the working dispatches of one FP64 solve.  Valid only for
 # the kernel source it was measured on; None whenever that kernel changes.
-PMC_TRAFFIC_BYTES = 268956552
+PMC_TRAFFIC_BYTES = 269046574
 
 
 def log(*a):
