@@ -267,10 +267,14 @@ def test_invariants_on_gpu_output(run):
         assert tr <= prm["tol"] * (1 + 1e-4)
 
 
-def test_determinism():
-    A, b, prm = _case("convdiff3d_24")
-    x1, i1 = _gpu(A, b, prm)
-    x2, i2 = _gpu(A, b, prm)
+@pytest.mark.parametrize("name,precision", [("convdiff3d_24", "fp64"), ("cw_sketch_t0", "fp64"),
+                                            ("convdiff3d_24", "mixed"), ("c1_power_basis_c2", "mixed")])
+def test_determinism(name, precision):
+    """(t = 0 cases: sigma is formed inside each SpMV from the previous step's
+    partials, summed by every wave in one fixed order)"""
+    A, b, prm = _case(name)
+    x1, i1 = _gpu(A, b, prm, precision=precision)
+    x2, i2 = _gpu(A, b, prm, precision=precision)
     # every reduction runs in a fixed order (per-wave sketch accumulators,
     # slot-ordered partial sums), so a repeated solve is bitwise identical
     assert list(i1["inner_k"]) == list(i2["inner_k"])
