@@ -72,6 +72,14 @@ class OracleResult:
     V: np.ndarray = None            # n x (J+1) orthonormal basis (keep_basis=True)
 
 
+def arnoldi_window(i, t):
+    """Basis indices (0-based, oldest first) that w = A b_i is orthogonalised
+    against at inner step i (1-based): the t most recent vectors
+    b_{i-t+1}, ..., b_i, i.e. Python indices i-t .. i-1, fewer while i < t
+    (Section 4.1's truncation to the previous t vectors; t = 0: none)."""
+    return range(max(0, i - t), i)
+
+
 def _cond_exact(R):
     sv = np.linalg.svd(R, compute_uv=False)
     return math.inf if sv[-1] == 0.0 else float(sv[0] / sv[-1])
@@ -81,7 +89,10 @@ def sgmres_cycle(A, v, sketch, *, m, t, tol_abs, factor, cond_threshold=1e15,
                  c2_rule="ice", forced_k=None, trace=None):
     """One inner sGMRES solve of A z = v (||v|| = 1), zero initial guess.
 
-    Returns (z, info) with info = dict(k, reason, cond, rho_hat).
+    Returns (z, info) with info = dict(k, reason, cond, rho_hat, y, basis);
+    basis lists the normalised truncated-Arnoldi vectors b_1, b_2, ... formed
+    before the cycle stopped (k of them after a stop by C1, C3 or a forced
+    dimension, k + 1 after C2, which drops the last column).
     """
     d0 = sketch(v)
     s = d0.shape[0]
@@ -121,7 +132,7 @@ def sgmres_cycle(A, v, sketch, *, m, t, tol_abs, factor, cond_threshold=1e15,
                 k, reason = m, "C1"
                 break
         # truncated Arnoldi: MGS against the last t basis vectors, oldest first
-        for l in range(max(0, i - t), i):
+        for l in arnoldi_window(i, t):
             h = float(w @ basis[l])
             w = w - h * basis[l]
         eta = float(np.linalg.norm(w))
@@ -135,7 +146,7 @@ def sgmres_cycle(A, v, sketch, *, m, t, tol_abs, factor, cond_threshold=1e15,
     z = np.zeros_like(basis[0])
     for l in range(k):
         z = z + y[l] * basis[l]
-    info = dict(k=k, reason=reason, cond=conds[k - 1], rho_hat=rhos[k - 1], y=y)
+    info = dict(k=k, reason=reason, cond=conds[k - 1], rho_hat=rhos[k - 1], y=y, basis=basis)
     return z, info
 
 
