@@ -88,20 +88,54 @@ def convdiff3d(N: int, kappa: float = 1.0, c=(50.0, 50.0, 50.0)) -> CSR:
     return _convdiff_const(N, 3, kappa, c)
 
 
+def _assemble_slots(n: int, slots: list) -> CSR:
+    """CSR from per-row slots listed in ascending column order: each slot is
+    (cols, vals, mask) over all n rows; masked-out entries are dropped.  The
+    result equals _assemble of the same entries (rows in order, columns
+    ascending) without a sort: entry (r, k) goes to position row_ptr[r] +
+    (number of kept slots before k in row r)."""
+    counts = np.zeros(n, dtype=np.int64)
+    for _, _, m in slots:
+        counts += m
+    row_ptr = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(counts, out=row_ptr[1:])
+    nnz = int(row_ptr[-1])
+    col_idx = np.empty(nnz, dtype=np.int32)
+    val = np.empty(nnz, dtype=np.float64)
+    pos = row_ptr[:-1].copy()
+    for c, v, m in slots:
+        p = pos[m]
+        col_idx[p] = c[m]
+        val[p] = v[m]
+        pos += m
+    return CSR(n, row_ptr.astype(np.int32), col_idx, val)
+
+
+def _stencil_slot_order(dim: int):
+    """(axis, direction) of the neighbours in ascending column order, with
+    None for the diagonal: -N^(dim-1) ... -1, 0, +1 ... +N^(dim-1)."""
+    lower = [(a, -1) for a in reversed(range(dim))]
+    upper = [(a, +1) for a in range(dim)]
+    return lower + [None] + upper
+
+
 def _convdiff_const(N, dim, kappa, c) -> CSR:
     h = 1.0 / (N + 1)
     n = N ** dim
     idx, coords, offsets = _stencil_parts(N, dim)
     stride = [N ** a for a in range(dim)]
-    rows, cols, vals = [idx], [idx], [np.full(n, 2 * dim * kappa + h * sum(abs(ci) for ci in c))]
-    for a, d in offsets:
+    slots = []
+    for od in _stencil_slot_order(dim):
+        if od is None:
+            slots.append((idx, np.full(n, 2 * dim * kappa + h * sum(abs(ci) for ci in c)),
+                          np.ones(n, dtype=bool)))
+            continue
+        a, d = od
         ok = coords[a] + d >= 0 if d < 0 else coords[a] + d < N
         ca = c[a]
         upw = h * max(ca, 0.0) if d < 0 else -h * min(ca, 0.0)
-        rows.append(idx[ok])
-        cols.append(idx[ok] + d * stride[a])
-        vals.append(np.full(int(ok.sum()), -kappa - upw))
-    return _assemble(n, rows, cols, vals)
+        slots.append((idx + d * stride[a], np.full(n, -kappa - upw), ok))
+    return _assemble_slots(n, slots)
 
 
 def convdiff3d_varcoef(N: int, rng: np.random.Generator, kmin=0.1, kmax=10.0,
@@ -117,23 +151,20 @@ def convdiff3d_varcoef(N: int, rng: np.random.Generator, kmin=0.1, kmax=10.0,
     idx, coords, offsets = _stencil_parts(N, 3)
     stride = [1, N, N * N]
     diag = np.full(n, h * sum(abs(ci) for ci in c))
-    rows, cols, vals = [], [], []
+    off = {}
+    # (the diagonal accumulates the faces in the order of `offsets`)
     for a, d in offsets:
         ok = coords[a] + d >= 0 if d < 0 else coords[a] + d < N
-        i = idx[ok]
-        j = i + d * stride[a]
-        kf = 2.0 * kap[i] * kap[j] / (kap[i] + kap[j])
-        diag[i] += kf
-        diag[idx[~ok]] += kap[idx[~ok]]
+        j = np.where(ok, idx + d * stride[a], idx)
+        kf = 2.0 * kap * kap[j] / (kap + kap[j])
+        diag[ok] += kf[ok]
+        diag[~ok] += kap[~ok]
         ca = c[a]
         upw = h * max(ca, 0.0) if d < 0 else -h * min(ca, 0.0)
-        rows.append(i)
-        cols.append(j)
-        vals.append(-kf - upw)
-    rows.append(idx)
-    cols.append(idx)
-    vals.append(diag)
-    return _assemble(n, rows, cols, vals)
+        off[(a, d)] = (idx + d * stride[a], -kf - upw, ok)
+    slots = [(idx, diag, np.ones(n, dtype=bool)) if od is None else off[od]
+             for od in _stencil_slot_order(3)]
+    return _assemble_slots(n, slots)
 
 
 def _powerlaw_alpha(Lmin: int, Lmax: int, mean: float) -> float:
