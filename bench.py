@@ -1,31 +1,42 @@
 """Benchmark: time to a 1e-8 relative residual of the sketched-FGMRES solver
-on one MI355X, with the fused SpMV+sketch kernel's HBM roofline fraction.
+on one MI355X, forward plus adjoint, FP64 against mixed precision, with the
+fused SpMV+sketch kernel's HBM roofline fraction.
 
-Workload (the default): 3D convection-diffusion, 7-point first-order upwind
-stencil on a 128^3 grid (n = 2,097,152, nnz = 14,581,760, CSR FP64,
-diffusion 1, convection (50, 50, 50)), b uniform in [-1, 1) from a fixed
-seed, x0 = 0; inner sGMRES m = 100, Arnoldi window t = 2, sparse sign sketch
-s = 400, zeta = 8; FGMRES to tol 1e-8 in FP64.
+Workload (the default, the largest single-GPU configuration): 3D
+convection-diffusion on a 256^3 grid (n = 16,777,216, nnz = 117,047,296, CSR
+FP64, 7-point first-order upwind stencil, nodal diffusion log-uniform in
+[0.1, 10] with harmonic face means, convection (50, 50, 50)), b uniform in
+[-1, 1) from a fixed seed, x0 = 0; inner sGMRES m = 200, Arnoldi window t = 2,
+sparse sign sketch s = 800, zeta = 8; FGMRES to tol 1e-8.  The adjoint solves
+A^T lambda = g for g = dL/dx of L = ||x - x_target||^2 (x_target uniform in
+[0, 1)) and forms dL/dA on A's pattern.
 
-One step = one complete solve (every step of the method: initial residual,
-inner cycles of fused SpMV+sketch+window dots, sketched QR and decisions,
-truncated Arnoldi, z = B y, outer SpMV, Gram-Schmidt, Givens, final iterate
-and its true residual).  Inputs are resident in HBM before the timed region.
-The same solve in mixed precision (FP32 inner SpMV/sketch input/basis, FP64
-sketch accumulation, QR, outer loop) is timed after it and reported with its
-speedup and its solution error against the FP64 solution.
+One step = one FP64 forward solve plus one FP64 adjoint solve (the CSR
+transpose, the transposed solve and dL/dA), every step of the method on the
+GPU (initial residual, inner cycles of fused SpMV+sketch+window dots, sketched
+QR and decisions, truncated Arnoldi, z = B y, outer SpMV, Gram-Schmidt,
+Givens, final iterate and its true residual).  Inputs are resident in HBM
+before the timed region.  The same forward+adjoint in mixed precision (FP32
+inner SpMV, sketch input and basis; FP64 sketch accumulation, QR and outer
+loop) is timed after it and reported with its speedup and its errors against
+the FP64 solution and adjoint.
 
-Output: one JSON line (rank 0).  ``roofline`` is for the fused inner
-SpMV+sketch kernel: algorithmic bytes per launch,
-12 nnz + 20 n + 8 n nwin + 12 ceil(zeta/8) n (values and column indices, row
-pointers, the input vector, the output vector, the nwin Arnoldi window
-vectors its fused dot products read, and the packed sketch columns),
-divided by the kernel's mean duration measured with HIP events on the
-library's stream over the timed solves (every 7th inner step's launch, the
-events being recorded by the launch itself at the kernel's start and end).  ``cpu_baseline`` times the CPU
-oracle on the first outer step of the same solve (k_1 inner steps, one
-thread) and scales its per-inner-step time to the GPU run's total inner
-steps.
+Output: one JSON line.  ``roofline`` is for the FP64 fused inner
+SpMV+sketch kernel of the forward solve: algorithmic bytes per launch,
+12 nnz + 20 n + 8 n nwin (values and column indices, row pointers, the input
+vector, the output vector, and the nwin Arnoldi window vectors its fused dot
+products read; the sketch S counts 0 bytes, since it is defined by a counter
+-based generator: the packed copy the kernel reads, 12 n bytes, is reported
+separately as implementation traffic), divided by the kernel's mean duration
+measured with HIP events on the library's stream over the timed solves
+(every 7th inner step's launch, the events recorded by the launch itself at
+the kernel's start and end).  ``cpu_baseline`` times the CPU oracle on a
+bounded prefix of the same forward solve (the sketch generation and the
+first outer step with a forced short inner cycle) and extrapolates it per
+inner step to the GPU run's forward and adjoint inner steps.  ``secondary``
+holds the 128^3 constant-coefficient system (whose matrix largely fits the
+chip's 256 MB last-level cache, so its rate is not an HBM figure) and the 1M
+power-law system, each against the 60% target.
 """
 from __future__ import annotations
 
@@ -42,12 +53,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
-# HBM bytes per dispatch of the fused kernel from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB), each scaled by the factor measured on a plain device copy
-# of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 + WRITE_SIZE x
-# 1.0, averaged over the working dispatches of one FP64 solve.  Valid only for
-# the kernel source it was measured on; None whenever that kernel changes.
-PMC_TRAFFIC_BYTES = 269046574
+TARGET_FRAC = 0.60      # the fused kernel's target fraction of HBM peak
+# HBM bytes per dispatch of the headline fused kernel (FP64, 256^3 system)
+# from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB), each scaled by the factor
+# measured on a plain device copy of known size (bench.py --copy-calibration):
+# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, averaged over the working dispatches of
+# one forward solve.  Valid only for the kernel source it was measured on;
+# None whenever that kernel changes.
+PMC_TRAFFIC_BYTES = None
 
 
 def log(*a):
@@ -59,13 +72,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--grid", type=int, default=128, help="grid points per axis (128 = the benchmark workload)")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
-    ap.add_argument("--workload", type=int, default=2, choices=[2, 3, 4, 5],
-                    help="2 = the benchmark line (128^3); 3 = 1M power-law (FP64 and mixed), "
-                         "4 = 512^2 parameterised operator and 5 = 256^3 variable coefficients "
-                         "(forward and adjoint): informational timings of the other workloads")
+    ap.add_argument("--no-secondary", action="store_true",
+                    help="skip the 128^3 and power-law rows of the benchmark line")
+    ap.add_argument("--workload", type=int, default=5, choices=[2, 3, 4, 5],
+                    help="5 = the benchmark line (256^3, forward + adjoint, FP64 vs mixed); "
+                         "2 = 128^3, 3 = 1M power-law, 4 = 512^2 parameterised operator: "
+                         "informational timings of the other workloads")
+    ap.add_argument("--info", action="store_true",
+                    help="informational timings of --workload (any of them) instead of the "
+                         "benchmark line")
     ap.add_argument("--m", type=int, default=None, help="override the workload's inner cap k_max")
     ap.add_argument("--t", type=int, default=None, help="override the Arnoldi window")
     ap.add_argument("--s", type=int, default=None, help="override the sketch rows")
@@ -77,6 +94,8 @@ def parse():
                     help="outer iteration (other workloads): FGMRES or restarted sGMRES")
     ap.add_argument("--adjoint", action="store_true",
                     help="workloads 4 and 5: time the adjoint solve also when --precisions is given")
+    ap.add_argument("--phases", action="store_true",
+                    help="other workloads: report the solver's per-phase GPU times")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB 5 times (counter calibration) and exit")
     return ap.parse_args()
@@ -120,16 +139,25 @@ def window_sum(inner_k, stop_reason, t, m, panel=8, stride=PROFILE_STRIDE):
 
 
 def fused_rate(infos, A, t, m, zeta, fp32):
-    """Mean duration of the timed working fused launches and their algorithmic
-    bytes (matrix, row pointers, x, y, window, packed sketch)."""
+    """Mean duration of the timed working fused launches, their algorithmic
+    bytes (matrix values and indices, row pointers, input, output and the
+    window vectors of the fused dots; S counts 0 bytes) and the bytes of the
+    packed sketch the kernel also reads (implementation traffic)."""
     launches = sum(i["spmv_launches"] for i in infos)
     ms = sum(i["spmv_ms"] for i in infos)
-    win = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in infos)
+    win, wl = 0, 0
+    for i in infos:
+        a_, b_ = window_sum(i["inner_k"], i["stop_reason"], t, m)
+        win += a_
+        wl += b_
+    if wl != launches:
+        raise RuntimeError(f"timed launch count mismatch {wl} vs {launches}")
     vb = 4 if fp32 else 8
     zg = (zeta + 7) // 8  # packed sketch: groups of 12 bytes per column
-    nbytes = (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches) + 12 * zg * A.n
+    alg = (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches)
+    sk = 12 * zg * A.n
     avg = ms * 1e-3 / launches
-    return avg, nbytes
+    return avg, alg, sk, launches
 
 
 def other_workload(args):
@@ -176,15 +204,21 @@ def other_workload(args):
         torch.cuda.synchronize()
         sec = (time.perf_counter() - ts) / args.steps
         inf = infos[-1]
-        avg, nbytes = fused_rate(infos, A, t, m, zeta, prec == "mixed")
+        avg, alg, sk, _ = fused_rate(infos, A, t, m, zeta, prec == "mixed")
         rec = {"time_to_tol_s": sec, "converged": bool(inf["converged"]),
                "residual_history": [float(v) for v in inf["residual_history"]],
                "true_rel_residual": inf["true_rel_residual"], "outer_iters": inf["outer_iters"],
                "total_inner": inf["total_inner"], "spmv_mean_launch_us": avg * 1e6,
-               "spmv_bytes_per_launch": nbytes, "spmv_achieved_gbs": nbytes / avg / 1e9}
+               "spmv_alg_bytes_per_launch": alg, "packed_sketch_bytes": sk,
+               "spmv_alg_gbs": alg / avg / 1e9, "frac": alg / avg / 1e9 / HBM_PEAK_GBS}
+        if args.phases:
+            _, ph = P.solve(rp, ci, va, bt, params=prm, out=x, phase_timers=True)
+            rec["phase_ms"] = ph["phase_ms"]
+            log(f"{prec} phases (ms): " + ", ".join(f"{k} {v:.2f}" for k, v in ph["phase_ms"].items()))
         log(f"{prec}: {sec * 1e3:.2f} ms/solve outer={inf['outer_iters']} "
             f"inner={inf['total_inner']} true_rel_res={inf['true_rel_residual']:.3e} "
-            f"fused {avg * 1e6:.1f} us ({nbytes / avg / 1e9:.0f} GB/s)")
+            f"fused {avg * 1e6:.1f} us ({alg / avg / 1e9:.0f} GB/s, "
+            f"{alg / avg / 1e9 / HBM_PEAK_GBS:.2f} of peak)")
         if adjoint:
             g = 2.0 * (x - bt)  # any right-hand side of the adjoint solve
             for _ in range(args.warmup):
@@ -206,20 +240,75 @@ def other_workload(args):
     print(json.dumps(out), flush=True)
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
-              "multi-GPU path in this build.", file=sys.stderr)
-        sys.exit(2)
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    if args.workload != 2 or any(getattr(args, k) is not None
-                                 for k in ("m", "t", "s", "zeta", "cond_threshold", "outer")):
-        other_workload(args)
-        return
+def timed_solves(P, rp, ci, va, bt, prm, steps, warmup, adjoint=None, label=""):
+    """Warm-up and timed solves (forward, then the adjoint when `adjoint` =
+    (g, x_for_gradient) or "auto" with g = 2 (x - x_target)); returns the
+    mean seconds per step, the forward infos, the last x, the adjoint infos
+    and the last lambda."""
+    import torch
+    x = torch.empty_like(bt)
 
+    def one(timed):
+        _, inf = P.solve(rp, ci, va, bt, params=prm, out=x,
+                         profile=PROFILE_STRIDE if timed else 0)
+        ia, lam = None, None
+        if adjoint is not None:
+            g = adjoint(x)
+            lam, _, ia = P.solve_adjoint(rp, ci, va, g, x, params=prm)
+        return inf, ia, lam
+
+    for w in range(warmup):
+        t0 = time.perf_counter()
+        inf, ia, _ = one(False)
+        torch.cuda.synchronize()
+        log(f"{label} warmup {w}: {time.perf_counter() - t0:.3f} s outer={inf['outer_iters']} "
+            f"inner={inf['total_inner']}" + (f" adjoint outer={ia['outer_iters']}" if ia else ""))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos, ainfos, lam = [], [], None
+    for k in range(steps):
+        inf, ia, lam = one(True)
+        infos.append(inf)
+        if ia is not None:
+            ainfos.append(ia)
+        if k == 0 or (k + 1) % 5 == 0:
+            torch.cuda.synchronize()
+            log(f"{label} step {k + 1}/{steps}: {time.perf_counter() - t0:.2f} s so far")
+    torch.cuda.synchronize()
+    sec = (time.perf_counter() - t0) / steps
+    return sec, infos, x, ainfos, lam
+
+
+def secondary_row(P, W, torch, cfg, steps):
+    """FP64 and mixed solves of the 128^3 (cfg 2) or power-law (cfg 3)
+    system: time to tol and the fused kernel's rate against the target."""
+    dev = torch.device("cuda:0")
+    A, b, p = W.make_workload(cfg)
+    rp, ci, va = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.val))
+    bt = torch.from_numpy(b).to(dev)
+    row = {"workload": p["name"], "n": A.n, "nnz": A.nnz, "m": p["m"], "t": p["t"], "s": p["s"],
+           "zeta": p["zeta"]}
+    for prec in ("fp64", "mixed"):
+        prm = P.SolveParams(m=p["m"], t=p["t"], s=p["s"], zeta=p["zeta"], tol=p["tol"],
+                            seed=p["seed"], max_outer=p["max_outer"], precision=prec)
+        sec, infos, _, _, _ = timed_solves(P, rp, ci, va, bt, prm, steps, 1, label=p["name"] + " " + prec)
+        avg, alg, sk, nl = fused_rate(infos, A, p["t"], p["m"], p["zeta"], prec == "mixed")
+        inf = infos[-1]
+        row[prec] = {"time_to_tol_s": sec, "converged": bool(inf["converged"]),
+                     "true_rel_residual": inf["true_rel_residual"],
+                     "outer_iters": inf["outer_iters"], "total_inner": inf["total_inner"],
+                     "fused_mean_launch_us": avg * 1e6, "fused_alg_bytes": alg,
+                     "fused_alg_gbs": alg / avg / 1e9, "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
+                     "target_frac": TARGET_FRAC, "packed_sketch_bytes": sk}
+        log(f"{p['name']} {prec}: {sec * 1e3:.2f} ms, fused {avg * 1e6:.1f} us "
+            f"({alg / avg / 1e9:.0f} GB/s, {alg / avg / 1e9 / HBM_PEAK_GBS:.2f} of peak)")
+    if cfg == 2:
+        row["note"] = ("the matrix (175 MB) largely fits the 256 MB last-level cache: "
+                       "the rate is not an HBM figure")
+    return row
+
+
+def headline(args):
     import torch
     import paper_2506_18408_amd as P
     import workloads as W
@@ -227,55 +316,36 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     dev = torch.device("cuda:0")
+    log("generating the 256^3 variable-coefficient system ...")
     t0 = time.time()
-    N = args.grid
-    A = W.convdiff3d(N, 1.0, (50.0, 50.0, 50.0))
-    b = W.rhs(A.n, np.random.default_rng([2, 1]), "u11")
-    seed = W.sketch_seed(2)
-    m, t, s, zeta, tol = 100, 2, 400, 8, 1e-8
-    log(f"workload convdiff3d N={N}: n={A.n} nnz={A.nnz} generated in {time.time() - t0:.1f}s")
+    A, b, p = W.make_workload(5)
+    x_target = np.random.default_rng([5, 3]).uniform(0.0, 1.0, size=A.n)
+    log(f"workload {p['name']}: n={A.n} nnz={A.nnz} generated in {time.time() - t0:.1f}s")
     rp, ci, va = (torch.from_numpy(a).to(dev) for a in (A.row_ptr, A.col_idx, A.val))
     bt = torch.from_numpy(b).to(dev)
-    prm = P.SolveParams(m=m, t=t, s=s, zeta=zeta, tol=tol, seed=seed, max_outer=100)
-    x = torch.empty_like(bt)
+    xt = torch.from_numpy(x_target).to(dev)
+    m, t, s, zeta, tol = p["m"], p["t"], p["s"], p["zeta"], p["tol"]
+    prm = P.SolveParams(m=m, t=t, s=s, zeta=zeta, tol=tol, seed=p["seed"],
+                        max_outer=p["max_outer"])
+    grad_of = lambda x: 2.0 * (x - xt)  # noqa: E731  (dL/dx of ||x - x_target||^2)
     torch.cuda.synchronize()
 
-    for w in range(args.warmup):
-        _, info = P.solve(rp, ci, va, bt, params=prm, out=x)
-        log(f"warmup {w}: {info['solve_ms']:.1f} ms outer={info['outer_iters']} inner={info['total_inner']}")
+    sec, infos, x, ainfos, lam = timed_solves(P, rp, ci, va, bt, prm, args.steps, args.warmup,
+                                              adjoint=grad_of, label="fp64")
+    last, alast = infos[-1], ainfos[-1]
+    fwd_s = sum(i["solve_ms"] for i in infos) * 1e-3 / len(infos)
+    adj_s = sec - fwd_s
+    log(f"fp64: {sec:.3f} s per forward+adjoint (forward {fwd_s:.3f} s), outer={last['outer_iters']} "
+        f"inner={last['total_inner']} true_rel_res={last['true_rel_residual']:.3e}; adjoint "
+        f"outer={alast['outer_iters']} true_rel_res={alast['true_rel_residual']:.3e}")
+    for inf, what in ((last, "forward"), (alast, "adjoint")):
+        if not inf["converged"] or not inf["true_rel_residual"] <= tol * (1 + 1e-6):
+            raise RuntimeError(f"FP64 {what} solve did not reach tol: {inf['true_rel_residual']}")
 
-    torch.cuda.synchronize()
-    t_start = time.perf_counter()
-    infos = []
-    for k in range(args.steps):
-        _, info = P.solve(rp, ci, va, bt, params=prm, out=x, profile=PROFILE_STRIDE)
-        infos.append(info)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t_start
-    sec = elapsed / args.steps
-    last = infos[-1]
-    log(f"fp64: {sec * 1e3:.2f} ms/solve, outer={last['outer_iters']} inner={last['total_inner']} "
-        f"true_rel_res={last['true_rel_residual']:.3e}")
-    if not last["converged"] or not last["true_rel_residual"] <= tol * (1 + 1e-6):
-        raise RuntimeError(f"FP64 solve did not reach tol: {last['true_rel_residual']}")
-
-    # fused SpMV+sketch kernel: mean duration of its working launches
-    spmv_ms = sum(i["spmv_ms"] for i in infos)
-    launches = sum(i["spmv_launches"] for i in infos)
-    win = 0
-    wl = 0
-    for i in infos:
-        a_, b_ = window_sum(i["inner_k"], i["stop_reason"], t, m)
-        win += a_
-        wl += b_
-    if wl != launches:
-        raise RuntimeError(f"launch count mismatch {wl} vs {launches}")
-    avg_s = spmv_ms * 1e-3 / launches
-    zg = (zeta + 7) // 8  # packed sketch: groups of 12 bytes per column
-    bytes_per_launch = 12 * A.nnz + 20 * A.n + 8 * A.n * (win / launches) + 12 * zg * A.n
-    achieved = bytes_per_launch / avg_s / 1e9
-    log(f"fused spmv+sketch: {launches} launches, mean {avg_s * 1e6:.2f} us, "
-        f"{bytes_per_launch / 1e6:.1f} MB algorithmic -> {achieved:.0f} GB/s")
+    avg_s, alg, sk, launches = fused_rate(infos, A, t, m, zeta, False)
+    achieved = alg / avg_s / 1e9
+    log(f"fused spmv+sketch (FP64): {launches} timed launches, mean {avg_s * 1e6:.2f} us, "
+        f"{alg / 1e6:.1f} MB algorithmic (+{sk / 1e6:.1f} MB packed sketch) -> {achieved:.0f} GB/s")
 
     result = {
         "metric": "time-to-1e-8 rel. residual (s) + SpMV/sketch HBM GB/s vs peak, FP64 vs mixed",
@@ -290,70 +360,114 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"convdiff3d_{N}^3 7-point upwind, n={A.n}, nnz={A.nnz}, "
-                               f"conv (50,50,50), b~U[-1,1); sGMRES m={m} t={t} s={s} zeta={zeta}; "
-                               f"FGMRES tol {tol:g}, FP64",
-                   "n": A.n, "nnz": A.nnz, "outer_iters": last["outer_iters"],
-                   "total_inner": last["total_inner"],
-                   "true_rel_residual": last["true_rel_residual"]},
+        "config": {"workload": (f"varcoef_convdiff3d_256^3 7-point upwind, n={A.n}, nnz={A.nnz}, "
+                                f"kappa log-uniform [0.1,10], conv (50,50,50), b~U[-1,1); "
+                                f"sGMRES m={m} t={t} s={s} zeta={zeta}; FGMRES tol {tol:g}; "
+                                f"one step = FP64 forward + adjoint (A^T solve, dL/dA)"),
+                   "n": A.n, "nnz": A.nnz,
+                   "forward": {"time_s": fwd_s, "outer_iters": last["outer_iters"],
+                               "total_inner": last["total_inner"],
+                               "true_rel_residual": last["true_rel_residual"]},
+                   "adjoint": {"time_s": adj_s, "outer_iters": alast["outer_iters"],
+                               "total_inner": alast["total_inner"],
+                               "true_rel_residual": alast["true_rel_residual"]}},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": PMC_TRAFFIC_BYTES,
-                     "kernel": "k_spmv<double, 1, kModeInner, 2, false> (fused SpMV+sketch+window dots; ZB = ceil(zeta/8) = 1, window 2)",
-                     "bytes_per_launch": bytes_per_launch, "mean_launch_us": avg_s * 1e6,
-                     "launches": launches},
+                     "target_frac": TARGET_FRAC,
+                     "kernel": "k_spmv<double, 1, kModeInner, 2, false> (fused SpMV+sketch+window "
+                               "dots, FP64, forward solve; ZB = ceil(zeta/8) = 1, window 2)",
+                     "bytes_per_launch": alg, "packed_sketch_bytes_per_launch": sk,
+                     "mean_launch_us": avg_s * 1e6, "launches": launches},
     }
 
     if not args.no_mixed:
         pm = P.SolveParams(**{**prm.__dict__, "precision": "mixed"})
-        xm = torch.empty_like(bt)
-        _, im = P.solve(rp, ci, va, bt, params=pm, out=xm)   # warm-up (also builds the FP32 copy)
-        torch.cuda.synchronize()
-        tm0 = time.perf_counter()
         reps = max(1, min(args.steps, 3))
-        ims = []
-        for _ in range(reps):
-            _, im = P.solve(rp, ci, va, bt, params=pm, out=xm, profile=PROFILE_STRIDE)
-            ims.append(im)
-        torch.cuda.synchronize()
-        msec = (time.perf_counter() - tm0) / reps
+        msec, minfos, xm, mainfos, lamm = timed_solves(P, rp, ci, va, bt, pm, reps, 1,
+                                                       adjoint=grad_of, label="mixed")
+        im, iam = minfos[-1], mainfos[-1]
         err = (torch.linalg.norm(xm - x) / torch.linalg.norm(x)).item()
-        ml = sum(i["spmv_launches"] for i in ims)
-        mms = sum(i["spmv_ms"] for i in ims)
-        mwin = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in ims)
-        mbytes = 8 * A.nnz + 12 * A.n + 4 * A.n * (mwin / ml) + 12 * zg * A.n
-        mavg = mms * 1e-3 / ml
+        # (the mixed adjoint's right-hand side is formed from the mixed x)
+        lerr = (torch.linalg.norm(lamm - lam) / torch.linalg.norm(lam)).item()
+        mavg, malg, msk, ml = fused_rate(minfos, A, t, m, zeta, True)
+        mfwd = sum(i["solve_ms"] for i in minfos) * 1e-3 / len(minfos)
         result["mixed"] = {
-            "time_to_tol_s": msec, "speedup_vs_fp64": sec / msec,
-            "converged": bool(im["converged"]), "true_rel_residual": im["true_rel_residual"],
+            "time_to_tol_s": msec, "forward_time_s": mfwd, "adjoint_time_s": msec - mfwd,
+            "speedup_vs_fp64": sec / msec,
+            "forward_speedup_vs_fp64": fwd_s / mfwd,
+            "converged": bool(im["converged"] and iam["converged"]),
+            "true_rel_residual": im["true_rel_residual"],
+            "adjoint_true_rel_residual": iam["true_rel_residual"],
             "outer_iters": im["outer_iters"], "total_inner": im["total_inner"],
-            "rel_error_vs_fp64_solution": err,
-            "spmv_mean_launch_us": mavg * 1e6, "spmv_bytes_per_launch": mbytes,
-            "spmv_achieved_gbs": mbytes / mavg / 1e9,
+            "adjoint_outer_iters": iam["outer_iters"],
+            "rel_error_vs_fp64_solution": err, "rel_error_vs_fp64_adjoint": lerr,
+            "fused_mean_launch_us": mavg * 1e6, "fused_alg_bytes": malg,
+            "fused_alg_gbs": malg / mavg / 1e9, "frac": malg / mavg / 1e9 / HBM_PEAK_GBS,
+            "kernel": "k_spmv<float, 1, kModeInner, 2, false>",
         }
-        log(f"mixed: {msec * 1e3:.2f} ms/solve (x{sec / msec:.2f}), outer={im['outer_iters']} "
-            f"inner={im['total_inner']} true_rel_res={im['true_rel_residual']:.3e} err={err:.2e}")
+        log(f"mixed: {msec:.3f} s per forward+adjoint (x{sec / msec:.2f}), outer={im['outer_iters']} "
+            f"inner={im['total_inner']} true_rel_res={im['true_rel_residual']:.3e} err={err:.2e} "
+            f"adjoint err={lerr:.2e}; fused {mavg * 1e6:.1f} us ({malg / mavg / 1e9:.0f} GB/s)")
+
+    if not args.no_secondary:
+        reps = max(1, min(args.steps, 3))
+        result["secondary"] = [secondary_row(P, W, torch, 2, reps),
+                               secondary_row(P, W, torch, 3, reps)]
 
     if not args.no_cpu:
-        import oracle
-        from threadpoolctl import threadpool_limits
-        As = A.to_scipy()
-        k1 = int(last["inner_k"][0])
-        with threadpool_limits(1):
-            tc = time.perf_counter()
-            r = oracle.sfgmres(As, b, m=m, t=t, s=s, zeta=zeta, tol=tol, seed=seed, max_outer=1,
-                               forced_k=[k1], record_true_residual=False)
-            tcpu = time.perf_counter() - tc
-        per_inner = tcpu / k1
-        result["cpu_baseline"] = {
-            "value": per_inner * last["total_inner"], "unit": "s", "cores": 1, "kind": "oracle",
-            "sample": (f"first outer FGMRES step of the same solve (k_1={k1} inner sGMRES steps + "
-                       f"one outer step) timed at {tcpu:.1f}s on 1 thread; value = that time per "
-                       f"inner step x the GPU run's {last['total_inner']} inner steps (extrapolated)"),
-        }
-        log(f"cpu oracle: {tcpu:.1f}s for k_1={k1} -> extrapolated {per_inner * last['total_inner']:.1f}s")
-        del r
+        result["cpu_baseline"] = cpu_baseline(A, b, p, last["total_inner"] + alast["total_inner"])
 
     print(json.dumps(result), flush=True)
+
+
+def cpu_baseline(A, b, p, total_inner):
+    """The oracle on a bounded prefix of the forward solve, one BLAS thread:
+    the sketch generation, then one outer step with a forced inner cycle of
+    K steps; the per-inner-step time is extrapolated to the GPU run's inner
+    steps (forward and adjoint), plus one sketch generation per solve."""
+    import oracle
+    from threadpoolctl import threadpool_info, threadpool_limits
+    K = 4
+    As = A.to_scipy()
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        S = oracle.sketch_matrix(A.n, p["s"], p["zeta"], p["seed"])
+        t_sketch = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        oracle.sfgmres(As, b, m=p["m"], t=p["t"], s=p["s"], zeta=p["zeta"], tol=p["tol"],
+                       seed=p["seed"], max_outer=1, forced_k=[K], record_true_residual=False,
+                       sketch=lambda w: oracle.apply_sketch(S, w))
+        t_step = time.perf_counter() - t0
+    per_inner = t_step / K
+    value = 2 * t_sketch + per_inner * total_inner
+    blas = [d.get("num_threads") for d in threadpool_info()]
+    log(f"cpu oracle: sketch {t_sketch:.1f}s, first outer step with k={K} {t_step:.1f}s -> "
+        f"extrapolated {value:.0f}s")
+    return {"value": value, "unit": "s", "cores": 1, "kind": "oracle",
+            "sample": (f"256^3 system, same seed: the oracle's sketch generation ({t_sketch:.1f}s) "
+                       f"and its first outer FGMRES step with a forced inner cycle of k={K} "
+                       f"({t_step:.1f}s), one thread (scipy SpMV and numpy sketch are single-"
+                       f"threaded; BLAS limited to 1); value = 2 sketch generations + the time per "
+                       f"inner step x the GPU run's {total_inner} forward+adjoint inner steps "
+                       f"(extrapolated)"),
+            "host_cpu_count": os.cpu_count(), "blas_threads_default": blas}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the solver has no "
+              "multi-GPU path in this build.", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    if args.info or args.workload != 5 or any(getattr(args, k) is not None for k in
+                                              ("m", "t", "s", "zeta", "cond_threshold", "outer",
+                                               "precisions")):
+        other_workload(args)
+        return
+    headline(args)
 
 
 if __name__ == "__main__":

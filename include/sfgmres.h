@@ -49,7 +49,8 @@ extern "C" {
 #define SFGMRES_ERR_HIP         -2   /* a HIP runtime call failed                          */
 #define SFGMRES_ERR_WORKSPACE   -3   /* workspace missing, too small or misaligned         */
 #define SFGMRES_ERR_NONFINITE   -4   /* NaN/Inf met in a norm or in the outer recurrence   */
-#define SFGMRES_ERR_BREAKDOWN   -5   /* S A v_j = 0: the inner problem is singular          */
+#define SFGMRES_ERR_BREAKDOWN   -5   /* S A v_j = 0 (the inner problem is singular), or
+                                        h_{j+1,j} = 0 with a singular H_j (z_j = 0)           */
 #define SFGMRES_ERR_TIMEOUT     -6   /* the device made no progress for 60 s                */
 
 /* ---- precision modes ------------------------------------------------- */
@@ -110,6 +111,13 @@ typedef struct sfgmres_options {
                                    restarted sGMRES, the comparison method of Section 4 (each
                                    cycle solves A z = r_j / ||r_j|| and x <- x + ||r_j|| z; C3
                                    uses ||r_j|| as its factor).  The adjoint solve follows it too */
+  int32_t identity_sketch;      /* 1: S = I instead of the random sketch (a test option: needs
+                                   s == n and zeta == 1).  The sketched least-squares problem of
+                                   eq. (1.2) then minimises the true inner residual, so the
+                                   inner cycle is GMRES(k) on a truncated-Arnoldi basis of the
+                                   same Krylov space.  Default 0                                 */
+  int32_t phase_timers;         /* 1: time the phases of the solve with HIP events on the
+                                   caller's stream into sfgmres_info.phase_ms; default 0        */
   int32_t reserved[2];
 } sfgmres_options;
 
@@ -131,12 +139,34 @@ typedef struct sfgmres_info {
   double* inner_true_residual;      /* [max_outer]: ||v_j - A z_j||                  */
   double* ffom_residual;            /* [max_outer]: FFOM residual norm, eq. (2.1), absolute */
   const int32_t* forced_k;          /* input [max_outer] or NULL: replay these inner
-                                       dimensions (k_j steps, no C1-C3 tests)         */
+                                       dimensions (k_j steps, no C1-C3 tests); every
+                                       entry in [0, m], 0 = not forced (SFGMRES_ERR_INVALID
+                                       otherwise)                                      */
   double  spmv_ms;                  /* profile: summed duration of the timed inner
                                        SpMV+sketch launches that did work              */
   int64_t spmv_launches;            /* profile: number of those launches              */
   double  solve_ms;                 /* host wall time of the call                      */
-  double  reserved[6];
+  double* bound;                    /* [max_outer]: the right side of eq. (2.2) for step j,
+                                       ||r~_{j-1}|| ||v_j - A z_j|| (absolute; ||r~_0|| =
+                                       beta), which bounds the minimised residual |g_{j+1}| */
+  double* delta_bound;              /* [max_outer]: delta_j of the recursive bound eq. (2.3),
+                                       delta_j = ||v_j - A z_j|| / sqrt(1 - delta_{j-1}^2),
+                                       delta_0 = 0, so that |g_{j+1}| <= delta_j |g_j| while
+                                       every delta so far is < 1; NaN once 1 - delta^2 <= 0 */
+  double* ffom_x;                   /* DEVICE [n] output or NULL: the FFOM iterate of the
+                                       last outer step J (Algorithm 1, "FFOM" line),
+                                       x~_J = x0 + Z_J H_J^{-1} beta e_1; NaN entries when H_J
+                                       is singular.  FGMRES outer only (the restarted outer
+                                       leaves it untouched)                                 */
+  double  phase_ms[8];              /* phase_timers: summed GPU time per phase, ms:
+                                       [0] set-up (tiles, sketch, FP32 values, r0, S v_1),
+                                       [1] inner steps of the cycles (until each cycle's last
+                                           decision is in), [2] y = R^{-1} d and z_j = B y,
+                                       [3] outer SpMV, Gram-Schmidt, Givens, v_{j+1} and S v,
+                                       [4] diagnostic true residuals (record_true_residual),
+                                       [5] final iterate, its true residual, FFOM iterate,
+                                       [6] adjoint: CSR(A^T), [7] adjoint: dL/dA            */
+  double  reserved[4];
 } sfgmres_info;
 
 typedef struct sfgmres_ctx* sfgmres_handle;

@@ -44,7 +44,7 @@ def restarted_sgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_restarts=10
 
     nb = float(np.linalg.norm(b))
     x = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64).copy()
-    res = OracleResult(x, STATUS_OK, 0, [], [], [], [], [], [], [], [], [],
+    res = OracleResult(x, STATUS_OK, 0, [], [], [], [], [], [], [], [], [], [],
                        np.zeros((1, 0)), nb, [])
     if nb == 0.0:
         res.x = np.zeros(n)

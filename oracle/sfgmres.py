@@ -10,6 +10,10 @@ Restated from Guettel & Pearson, arXiv 2506.18408:
 * FFOM residual, eq. (2.1): ||r~_j|| = h_{j+1,j} |e_j^T H_j^{-1} beta e1|.
 * Residual bound, eq. (2.2): ||r_j|| <= ||r~_{j-1}|| ||r^_j||, with
   ||r~_0|| read as beta (the j = 1 case of Section 2.1).
+* Recursive bound, eq. (2.3) (Section 2.3): ||r_j|| <= delta_j ||r_{j-1}||
+  with delta_j = ||r^_j|| / sqrt(1 - delta_{j-1}^2), delta_0 = 0, valid
+  while every delta so far is below one (recorded as NaN once
+  1 - delta^2 <= 0, where the recursion has no real value).
 * Inner solve -- sGMRES, eq. (1.2) and Section 3: B_k spans
   K_k(A, v_j) with b_1 = v_j, built by truncated Arnoldi (Section 4.1: each
   new vector is orthogonalised against the previous t basis vectors only, by
@@ -65,6 +69,7 @@ class OracleResult:
     inner_true_residual: list       # ||v_j - A z_j||
     ffom_residual: list             # ||r~_j|| (absolute)
     bound: list                     # ||r~_{j-1}|| ||r^_j|| (absolute)
+    delta: list                     # delta_j of eq. (2.3)
     H: np.ndarray
     nb: float
     trace: list
@@ -167,7 +172,7 @@ def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
 
     nb = float(np.linalg.norm(b))
     x0 = np.zeros(n) if x0 is None else np.asarray(x0, dtype=np.float64)
-    empty = OracleResult(np.zeros(n), STATUS_OK, 0, [], [], [], [], [], [], [], [], [],
+    empty = OracleResult(np.zeros(n), STATUS_OK, 0, [], [], [], [], [], [], [], [], [], [],
                          np.zeros((1, 0)), nb, [])
     if nb == 0.0:
         return empty
@@ -186,6 +191,7 @@ def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
     e1 = np.zeros(max_outer + 1)
     e1[0] = beta
     factor = beta                     # ||r~_0|| read as beta
+    delta = 0.0                       # delta_0 of eq. (2.3)
     status = STATUS_NOT_CONVERGED
     y = None
     J = 0
@@ -213,6 +219,9 @@ def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
             ffom = math.inf
         res.bound.append(factor * rhat)
         factor = ffom if math.isfinite(ffom) else math.inf
+        q = 1.0 - delta * delta
+        delta = rhat / math.sqrt(q) if q > 0.0 else math.nan
+        res.delta.append(delta)
         res.inner_k.append(info["k"])
         res.stop_reason.append(info["reason"])
         res.cond_at_stop.append(info["cond"])

@@ -25,6 +25,9 @@ MIXED = 1
 
 STOP_REASONS = {1: "C1", 2: "C2", 3: "C3", 4: "breakdown", 5: "forced"}
 
+PHASES = ("setup", "inner", "cycle_end", "outer", "true_residuals", "final", "transpose",
+          "gradient")
+
 MAX_ZETA = 16
 MAX_S = 1024
 MAX_M = 512
@@ -52,6 +55,8 @@ class Options(C.Structure):
         ("lookahead", C.c_int32),
         ("panel", C.c_int32),
         ("outer", C.c_int32),
+        ("identity_sketch", C.c_int32),
+        ("phase_timers", C.c_int32),
         ("reserved", C.c_int32 * 2),
     ]
 
@@ -76,7 +81,11 @@ class Info(C.Structure):
         ("spmv_ms", C.c_double),
         ("spmv_launches", C.c_int64),
         ("solve_ms", C.c_double),
-        ("reserved", C.c_double * 6),
+        ("bound", C.POINTER(C.c_double)),
+        ("delta_bound", C.POINTER(C.c_double)),
+        ("ffom_x", C.c_void_p),
+        ("phase_ms", C.c_double * 8),
+        ("reserved", C.c_double * 4),
     ]
 
 

@@ -36,7 +36,9 @@ class SolveParams:
     runs ahead of the device's last decision (0: default); panel: columns
     per decision launch (0: default 8; the stopping rule still acts after
     every column); outer: "fgmres" (Algorithm 1) or "restarted" (restarted
-    sGMRES, the paper's comparison method).
+    sGMRES, the paper's comparison method); identity_sketch: S = I (a test
+    option: needs s == n and zeta == 1; the inner cycle is then GMRES(k));
+    phase_timers: per-phase GPU times into info["phase_ms"].
     """
     m: int = 30
     t: int = 2
@@ -50,6 +52,8 @@ class SolveParams:
     lookahead: int = 0
     panel: int = 0
     outer: str = "fgmres"
+    identity_sketch: bool = False
+    phase_timers: bool = False
 
 
 _HANDLES = {}
@@ -89,9 +93,35 @@ def _csr(row_ptr, col_idx, val) -> L.Csr:
                           ("val", val, torch.float64)):
         if tns.dtype != dt or not tns.is_cuda or not tns.is_contiguous():
             raise ValueError(f"{name} must be a contiguous {dt} tensor on the GPU")
+        if tns.device != row_ptr.device:
+            raise ValueError(f"{name} is not on row_ptr's device")
     if col_idx.numel() != val.numel():
         raise ValueError("col_idx and val differ in length")
     return L.Csr(n, col_idx.numel(), row_ptr.data_ptr(), col_idx.data_ptr(), val.data_ptr())
+
+
+def check_vector(name: str, t, n: int, device: torch.device) -> None:
+    """A vector argument of the C ABI: a contiguous float64 tensor of length n
+    on `device` (the device of A).  The library cannot tell a host pointer
+    from a device pointer, so anything else is rejected before a launch."""
+    if not isinstance(t, torch.Tensor):
+        raise ValueError(f"{name} must be a torch tensor")
+    if t.dtype != torch.float64:
+        raise ValueError(f"{name} must be float64 (got {t.dtype})")
+    if t.device != device:
+        raise ValueError(f"{name} must be on {device} (got {t.device})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != n:
+        raise ValueError(f"{name} must have {n} entries (got {t.numel()})")
+
+
+def check_forced_k(forced_k, m: int) -> None:
+    if forced_k is None:
+        return
+    fk = np.asarray(forced_k)
+    if fk.size and (fk.min() < 0 or fk.max() > m):
+        raise ValueError(f"forced_k entries must lie in [0, m = {m}]")
 
 
 def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Options:
@@ -105,6 +135,8 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.lookahead = p.lookahead
     o.panel = p.panel
     o.outer = {"fgmres": 0, "restarted": 1}[p.outer]
+    o.identity_sketch = 1 if p.identity_sketch else 0
+    o.phase_timers = 1 if p.phase_timers else 0
     return o
 
 
@@ -118,6 +150,8 @@ class _InfoBuffers:
         self.inner_sketched_residual = np.full(J, np.nan)
         self.inner_true_residual = np.full(J, np.nan)
         self.ffom_residual = np.full(J, np.nan)
+        self.bound = np.full(J, np.nan)
+        self.delta_bound = np.full(J, np.nan)
         self.forced = None
         if forced_k is not None:
             fk = np.zeros(J, dtype=np.int32)
@@ -134,6 +168,8 @@ class _InfoBuffers:
         self.info.inner_sketched_residual = self.inner_sketched_residual.ctypes.data_as(dp)
         self.info.inner_true_residual = self.inner_true_residual.ctypes.data_as(dp)
         self.info.ffom_residual = self.ffom_residual.ctypes.data_as(dp)
+        self.info.bound = self.bound.ctypes.data_as(dp)
+        self.info.delta_bound = self.delta_bound.ctypes.data_as(dp)
         self.info.forced_k = self.forced.ctypes.data_as(ip) if self.forced is not None else None
 
     def to_dict(self, rc: int) -> dict:
@@ -153,9 +189,12 @@ class _InfoBuffers:
             inner_sketched_residual=self.inner_sketched_residual[:J].copy(),
             inner_true_residual=self.inner_true_residual[:J].copy(),
             ffom_residual=self.ffom_residual[:J].copy(),
+            bound=self.bound[:J].copy(),
+            delta_bound=self.delta_bound[:J].copy(),
             spmv_ms=self.info.spmv_ms,
             spmv_launches=self.info.spmv_launches,
             solve_ms=self.info.solve_ms,
+            phase_ms=dict(zip(L.PHASES, list(self.info.phase_ms))),
         )
 
 
@@ -186,28 +225,38 @@ def workspace_bytes(n, nnz, p: SolveParams, adjoint=False) -> int:
 
 
 def solve(row_ptr, col_idx, val, b, x0=None, params: SolveParams | None = None, *, out=None,
-          forced_k=None, record_true_residual=False, profile=False, **kw):
-    """Solve A x = b; returns (x, info dict).  ``kw`` overrides fields of params."""
+          forced_k=None, record_true_residual=False, profile=False, want_ffom=False, **kw):
+    """Solve A x = b; returns (x, info dict).  ``kw`` overrides fields of params.
+
+    want_ffom: also return the FFOM iterate of the last outer step
+    (Algorithm 1) as info["ffom_x"] (a device tensor)."""
     p = dataclasses.replace(params or SolveParams(), **kw)
     A = _csr(row_ptr, col_idx, val)
-    dev = b.device
-    if b.dtype != torch.float64 or not b.is_contiguous() or b.numel() != A.n:
-        raise ValueError("b must be a contiguous float64 tensor of length n")
-    if x0 is not None and (x0.dtype != torch.float64 or x0.numel() != A.n):
-        raise ValueError("x0 must be a float64 tensor of length n")
+    dev = row_ptr.device
+    check_vector("b", b, A.n, dev)
+    if x0 is not None:
+        check_vector("x0", x0, A.n, dev)
+    if out is not None:
+        check_vector("out", out, A.n, dev)
+    check_forced_k(forced_k, p.m)
     x = out if out is not None else torch.empty_like(b)
     nbytes = workspace_bytes(A.n, A.nnz, p)
     ws = _workspace(nbytes, dev, "solve")
     h = _handle(dev)
     opt = _options(p, record_true_residual, profile)
     ib = _InfoBuffers(p.max_outer, forced_k)
+    xf = torch.empty_like(b) if want_ffom else None
+    ib.info.ffom_x = _ptr(xf)
     rc = L.load().sfgmres_solve(h, C.byref(A), b.data_ptr(), _ptr(x0), x.data_ptr(), p.m, p.t, p.s,
                                 p.zeta, p.tol, p.seed & (2**64 - 1), C.byref(opt), C.byref(ib.info),
                                 ws.data_ptr(), ws.numel(), _stream())
     _check(rc, h)
     if rc == L.NOT_CONVERGED:
         warnings.warn("sfgmres: max_outer reached before tol", RuntimeWarning)
-    return x, ib.to_dict(rc)
+    info = ib.to_dict(rc)
+    if want_ffom:
+        info["ffom_x"] = xf
+    return x, info
 
 
 def solve_adjoint(row_ptr, col_idx, val, g, x=None, params: SolveParams | None = None, *,
@@ -216,7 +265,11 @@ def solve_adjoint(row_ptr, col_idx, val, g, x=None, params: SolveParams | None =
     grad_val[p] = -lam[row(p)] x[col(p)] when x is given."""
     p = dataclasses.replace(params or SolveParams(), **kw)
     A = _csr(row_ptr, col_idx, val)
-    dev = g.device
+    dev = row_ptr.device
+    check_vector("g", g, A.n, dev)
+    if x is not None:
+        check_vector("x", x, A.n, dev)
+    check_forced_k(forced_k, p.m)
     lam = torch.empty_like(g)
     gv = torch.empty_like(val) if (want_grad_val and x is not None) else None
     nbytes = workspace_bytes(A.n, A.nnz, p, adjoint=True)
@@ -224,7 +277,7 @@ def solve_adjoint(row_ptr, col_idx, val, g, x=None, params: SolveParams | None =
     h = _handle(dev)
     opt = _options(p)
     ib = _InfoBuffers(p.max_outer, forced_k)
-    rc = L.load().sfgmres_solve_adjoint(h, C.byref(A), g.contiguous().data_ptr(), lam.data_ptr(),
+    rc = L.load().sfgmres_solve_adjoint(h, C.byref(A), g.data_ptr(), lam.data_ptr(),
                                         _ptr(x) if gv is not None else None, _ptr(gv), p.m, p.t,
                                         p.s, p.zeta, p.tol, p.seed & (2**64 - 1), C.byref(opt),
                                         C.byref(ib.info), ws.data_ptr(), ws.numel(), _stream())

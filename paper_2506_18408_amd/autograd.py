@@ -14,7 +14,7 @@ from .api import SolveParams, solve, solve_adjoint
 class SFGMRESSolve(torch.autograd.Function):
     @staticmethod
     def forward(ctx, row_ptr, col_idx, values, b, params: SolveParams):
-        x, info = solve(row_ptr, col_idx, values.detach(), b.detach(), params=params)
+        x, info = solve(row_ptr, col_idx, values.detach(), b.detach().contiguous(), params=params)
         ctx.save_for_backward(row_ptr, col_idx, values, x)
         ctx.params = params
         ctx.info = info

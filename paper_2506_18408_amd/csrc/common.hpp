@@ -106,6 +106,10 @@ struct DevCtl {
   double ffom;
   double hnext;          // h_{j+1,j}
   double cs_last;
+  double bound;          // eq. (2.2) at the last outer step: ||r~_{j-1}|| ||v_j - A z_j||
+  double delta;          // eq. (2.3): delta_j (0 before the first outer step)
+  double ffom_g;         // last outer step: g_j before its own rotation (FFOM right side)
+  double ffom_piv;       // ... and the pivot of column j before that rotation (H_j's R)
 };
 
 // Host-visible status block (pinned, device-mapped).
@@ -118,7 +122,7 @@ struct HostStatus {
   int32_t k;
   int32_t error;
   int32_t steps_run;         // inner steps fully executed by the cycle that stopped
-  double rho, ffom, hnext, cond, rho_hat, rhat_true, beta, nb;
+  double rho, ffom, hnext, cond, rho_hat, rhat_true, beta, nb, bound, delta;
 };
 
 // Offsets (bytes) of every workspace region.

@@ -81,6 +81,9 @@ hipError_t launch_spmv_finish(int mode, const double* dpart, int32_t G, DevCtl* 
 // export as (row, sign) arrays for tests.
 hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, uint32_t k1,
                               SkGroup* skp, hipStream_t st);
+// The identity as a packed sketch (zeta = 1, column r -> row r, sign +1);
+// a test option that needs s == n.
+hipError_t launch_sketch_identity(int64_t n, SkGroup* skp, hipStream_t st);
 hipError_t launch_sketch_unpack(int64_t n, int32_t zeta, const SkGroup* skp, int32_t* rows,
                                 int8_t* signs, hipStream_t st);
 
@@ -181,8 +184,9 @@ hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
 hipError_t launch_combine(bool fp32, int64_t n, const void* B, int64_t ldb, const double* y,
                           const int32_t* kdev, int32_t khost, const double* add,
                           double* out, hipStream_t st, const double* scale = nullptr);
+// (ffom_ctl non-null: the FFOM coefficients H_J^{-1} beta e1 instead)
 hipError_t launch_backsolve(const double* HR, const double* g, int32_t J, int32_t ldh,
-                            double* y, hipStream_t st);
+                            double* y, hipStream_t st, const DevCtl* ffom_ctl = nullptr);
 hipError_t launch_cast_f32(const double* src, float* dst, int64_t count, hipStream_t st);
 hipError_t launch_copy_or_zero(const double* src, double* dst, int64_t n, hipStream_t st);
 hipError_t launch_gradient(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,

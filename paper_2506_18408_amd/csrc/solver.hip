@@ -45,6 +45,7 @@ struct sfgmres_ctx {
   std::vector<hipEvent_t> ev;  // timing events (profile option)
   hipStream_t dec = nullptr;    // the decision stream (slot reductions, sketched QR)
   std::vector<hipEvent_t> sync; // panel hand-over events (no timing)
+  std::vector<hipEvent_t> pev;  // phase marks (phase_timers option)
 };
 
 namespace sfg {
@@ -192,6 +193,12 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
   if (o.panel < 0 || o.panel > kPanel) return fail(h, SFGMRES_ERR_INVALID, "need 0 <= panel <= 8");
   if (o.outer != SFGMRES_OUTER_FGMRES && o.outer != SFGMRES_OUTER_RESTARTED)
     return fail(h, SFGMRES_ERR_INVALID, "outer must be SFGMRES_OUTER_FGMRES or _RESTARTED");
+  if (o.identity_sketch != 0 && o.identity_sketch != 1)
+    return fail(h, SFGMRES_ERR_INVALID, "identity_sketch must be 0 or 1");
+  if (o.identity_sketch && (s != n || zeta != 1))
+    return fail(h, SFGMRES_ERR_INVALID, "identity_sketch needs s == n and zeta == 1");
+  if (o.phase_timers != 0 && o.phase_timers != 1)
+    return fail(h, SFGMRES_ERR_INVALID, "phase_timers must be 0 or 1");
   return SFGMRES_OK;
 }
 
@@ -318,6 +325,17 @@ bool spin_until(sfgmres_ctx* h, Pred pred) {
   return true;
 }
 
+// Timing events of the phase_timers option (created once per handle).
+constexpr int kPhaseMarks = 8;
+int ensure_marks(sfgmres_handle h) {
+  while ((int)h->pev.size() < kPhaseMarks) {
+    hipEvent_t e;
+    SFG_HIP(hipEventCreate(&e));
+    h->pev.push_back(e);
+  }
+  return SFGMRES_OK;
+}
+
 int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const double* x0,
                double* x, int32_t m, int32_t t, int32_t s, int32_t zeta, double tol,
                uint64_t seed, const sfgmres_options& o, sfgmres_info* info, void* ws,
@@ -353,6 +371,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   auto Vcol = [&](int64_t l) { return P.Vb + l * ld; };
   auto Zcol = [&](int64_t l) { return P.Zb + l * ld; };
   const int32_t* forced = info ? info->forced_k : nullptr;
+  if (forced)
+    for (int j = 0; j < o.max_outer; ++j)
+      if (forced[j] < 0 || forced[j] > m)
+        return fail(h, SFGMRES_ERR_INVALID, "forced_k entries must lie in [0, m]");
 
   if (info) {
     info->outer_iters = 0;
@@ -362,7 +384,28 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     info->true_rel_residual = NAN;
     info->spmv_ms = 0.0;
     info->spmv_launches = 0;
+    for (double& v : info->phase_ms) v = 0.0;
   }
+  // Phase timers: marks recorded on the caller's stream at phase
+  // boundaries; after each synchronisation the elapsed time between two
+  // marks is added to the phase that lies between them.
+  const bool timers = o.phase_timers != 0;
+  enum { kMarkStart, kMarkSetup, kMarkCycle, kMarkDecided, kMarkZ, kMarkOuter, kMarkA, kMarkB };
+  if (timers) {
+    rc = ensure_marks(h);
+    if (rc) return rc;
+  }
+  double phase[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  auto mark = [&](int slot) -> hipError_t {
+    return timers ? hipEventRecord(h->pev[slot], st) : hipSuccess;
+  };
+  auto add_phase = [&](int ph, int a, int b) -> hipError_t {
+    if (!timers) return hipSuccess;
+    float ms = 0.f;
+    const hipError_t e = hipEventElapsedTime(&ms, h->pev[a], h->pev[b]);
+    phase[ph] += ms;
+    return e;
+  };
   // hand-over events: per panel, "its steps are enqueued" and "its rows are
   // reduced", then one for the last decision
   const int npanels = (m + pc - 1) / pc;
@@ -383,6 +426,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   }
 
   // ---- setup: control block, nnz-balanced tiles, float32 values, sketch --
+  SFG_HIP(mark(kMarkStart));
   Tiling tiling{};
   rc = plan_tiling(h, A, P.tiles, P.tp, P.ipart, st, &tiling);
   if (rc) return rc;
@@ -394,7 +438,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   memset((void*)hsh, 0, sizeof(HostStatus));
   SFG_HIP(launch_init_ctl(P.ctl, m, t, s, cond_threshold_of(o), tol, st));
   if (f32) SFG_HIP(launch_cast_f32(A->val, P.val32, nnz, st));
-  SFG_HIP(launch_sketch_pack(n, s, zeta, k0, k1, P.skp, st));
+  if (o.identity_sketch)
+    SFG_HIP(launch_sketch_identity(n, P.skp, st));
+  else
+    SFG_HIP(launch_sketch_pack(n, s, zeta, k0, k1, P.skp, st));
 
   SpmvArgs base_args{};
   base_args.n = n;
@@ -457,7 +504,9 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   }
   rc = sketch_v_and_init(P.W64, &P.ctl->beta, Vcol(0), forced ? forced[0] : 0);
   if (rc) return rc;
+  SFG_HIP(mark(kMarkSetup));
   SFG_HIP(hipStreamSynchronize(st));
+  SFG_HIP(add_phase(0, kMarkStart, kMarkSetup));
   if (hsh->error) return fail(h, hsh->error, "non-finite initial residual or right-hand side");
   const double beta = hsh->beta;
   const double nb = hsh->nb;
@@ -472,6 +521,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       info->true_rel_residual = trel;
       info->status = status;
       info->solve_ms = now_ms() - t_start;
+      for (int q = 0; q < 8; ++q) info->phase_ms[q] = phase[q];
     }
     return status;
   };
@@ -494,6 +544,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     a.b = b;
     SFG_HIP(launch_spmv(kModeTrueRes, false, Gp, a, 0, st));
     SFG_HIP(launch_spmv_finish(kModeTrueRes, P.dpart, Gp, P.ctl, P.scal, hsd, st));
+    SFG_HIP(mark(kMarkB));
     SFG_HIP(hipMemcpyAsync(r2, P.scal, sizeof(double), hipMemcpyDeviceToHost, st));
     SFG_HIP(hipStreamSynchronize(st));
     return SFGMRES_OK;
@@ -514,6 +565,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     hsh->inner_step_done = 0;
     hsh->stop_step = 0;
     hsh->steps_run = 0;
+    SFG_HIP(mark(kMarkCycle));
     int panel0 = 0;  // first column of the open panel
     for (int i = 0; i < m; ++i) {
       if (i >= lookahead) {
@@ -618,6 +670,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     }
     // the cycle's last decision (and every earlier one) before its results
     SFG_HIP(hipStreamWaitEvent(st, ev_dec, 0));
+    SFG_HIP(mark(kMarkDecided));
     // z_j = B_k y_k
     SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
     if (restarted) {
@@ -632,7 +685,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       a.b = b;
       SFG_HIP(launch_spmv(kModeResid, false, Gp, a, 0, st));
       SFG_HIP(launch_spmv_finish(kModeRestart, P.dpart, Gp, P.ctl, P.scal, hsd, st));
+      SFG_HIP(mark(kMarkZ));
       SFG_HIP(hipStreamSynchronize(st));
+      SFG_HIP(add_phase(1, kMarkCycle, kMarkDecided));
+      SFG_HIP(add_phase(2, kMarkDecided, kMarkZ));
       const int err = hsh->error;
       const int kj = hsh->k;
       beta_cur = hsh->beta;
@@ -677,6 +733,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       continue;
     }
     SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
+    SFG_HIP(mark(kMarkZ));
     // w = A z_j with h_{1,j}; modified Gram-Schmidt; Givens
     {
       SpmvArgs a = base_args;
@@ -700,7 +757,11 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     rc = sketch_v_and_init(P.W64, P.H + (int64_t)j * ldh + j + 1, Vcol(j + 1),
                            (forced && j + 1 < J) ? forced[j + 1] : 0);
     if (rc) return rc;
+    SFG_HIP(mark(kMarkOuter));
     SFG_HIP(hipStreamSynchronize(st));
+    SFG_HIP(add_phase(1, kMarkCycle, kMarkDecided));
+    SFG_HIP(add_phase(2, kMarkDecided, kMarkZ));
+    SFG_HIP(add_phase(3, kMarkZ, kMarkOuter));
     const int err = hsh->error;
     const int kj = hsh->k;
     const double rho = hsh->rho;
@@ -726,20 +787,25 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       if (info->inner_sketched_residual) info->inner_sketched_residual[j] = hsh->rho_hat;
       if (info->inner_true_residual) info->inner_true_residual[j] = hsh->rhat_true;
       if (info->ffom_residual) info->ffom_residual[j] = hsh->ffom;
+      if (info->bound) info->bound[j] = hsh->bound;
+      if (info->delta_bound) info->delta_bound[j] = hsh->delta;
     }
     if (err) {
       finish_info(err, J_done, false, rho / nb, NAN);
       return fail(h, err,
-                  err == SFGMRES_ERR_BREAKDOWN ? "sketch of A v_j is zero (singular inner problem)"
-                                               : "non-finite value in the outer recurrence");
+                  err == SFGMRES_ERR_BREAKDOWN
+                      ? "singular inner problem (S A v_j = 0) or singular H_j with h_{j+1,j} = 0"
+                      : "non-finite value in the outer recurrence");
     }
     rho_last = rho;
     if (o.record_true_residual) {
+      SFG_HIP(mark(kMarkA));
       SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st));
       SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, P.X, st));
       double r2 = 0.0;
       rc = true_residual(P.X, &r2);
       if (rc) return rc;
+      SFG_HIP(add_phase(4, kMarkA, kMarkB));
       if (info && info->true_residual_history) info->true_residual_history[j] = sqrt(r2) / nb;
     }
     if (hsh->hnext == 0.0 || rho <= tol * nb) {
@@ -754,12 +820,19 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     return finish_info(status, J_done, conv, beta_cur / nb, beta_cur / nb);
   }
 
-  // ---- x = x0 + Z y, true residual ----------------------------------------
+  // ---- x = x0 + Z y, true residual, FFOM iterate ---------------------------
+  SFG_HIP(mark(kMarkA));
   SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st));
   SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, x, st));
+  if (info && info->ffom_x) {
+    // x~_J = x0 + Z_J H_J^{-1} beta e1 (Algorithm 1, FFOM)
+    SFG_HIP(launch_backsolve(P.HR, P.g, J_done, ldh, P.yout, st, P.ctl));
+    SFG_HIP(launch_combine(false, n, P.Zb, ld, P.yout, nullptr, J_done, x0, info->ffom_x, st));
+  }
   double r2 = 0.0;
   rc = true_residual(x, &r2);
   if (rc) return rc;
+  SFG_HIP(add_phase(5, kMarkA, kMarkB));
   const int status = conv ? SFGMRES_OK : SFGMRES_NOT_CONVERGED;
   return finish_info(status, J_done, conv, rho_last / nb, sqrt(r2) / nb);
 }
@@ -852,6 +925,7 @@ int sfgmres_create(sfgmres_handle* out) {
 void sfgmres_destroy(sfgmres_handle h) {
   if (!h) return;
   for (hipEvent_t e : h->ev) (void)hipEventDestroy(e);
+  for (hipEvent_t e : h->pev) (void)hipEventDestroy(e);
   for (hipEvent_t e : h->sync) (void)hipEventDestroy(e);
   if (h->dec) (void)hipStreamDestroy(h->dec);
   if (h->hs_host) (void)hipHostFree(h->hs_host);
@@ -901,8 +975,22 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   int32_t* perm = reinterpret_cast<int32_t*>(base + L.at_perm);
   int32_t* cursor = reinterpret_cast<int32_t*>(base + L.at_cursor);
   int32_t* scan_tmp = reinterpret_cast<int32_t*>(base + L.scan_tmp);
+  // (phase_timers: the transpose and the gradient are timed with the last
+  // two phase marks, each read before the solve reuses them)
+  const bool timers = o.phase_timers != 0;
+  if (timers) {
+    rc = ensure_marks(h);
+    if (rc) return rc;
+    SFG_HIP(hipEventRecord(h->pev[kPhaseMarks - 2], st));
+  }
   SFG_HIP(launch_transpose(A->row_ptr, A->col_idx, A->val, A->n, A->nnz, rp_t, col_t, val_t, perm,
                            cursor, scan_tmp, st));
+  float t_transpose = 0.f;
+  if (timers) {
+    SFG_HIP(hipEventRecord(h->pev[kPhaseMarks - 1], st));
+    SFG_HIP(hipEventSynchronize(h->pev[kPhaseMarks - 1]));
+    SFG_HIP(hipEventElapsedTime(&t_transpose, h->pev[kPhaseMarks - 2], h->pev[kPhaseMarks - 1]));
+  }
   sfgmres_csr AT{A->n, A->nnz, rp_t, col_t, val_t};
   try {
     rc = solve_impl(h, &AT, g, nullptr, lambda, m, t, s, zeta, tol, seed, o, info, ws, L.at_rowptr,
@@ -910,10 +998,18 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   } catch (...) {
     return fail(h, SFGMRES_ERR_INVALID, "internal exception");
   }
+  if (info && timers) info->phase_ms[6] = t_transpose;
   if (rc < 0) return rc;
   if (x && grad_val) {
+    if (timers) SFG_HIP(hipEventRecord(h->pev[kPhaseMarks - 2], st));
     SFG_HIP(launch_gradient(A->row_ptr, A->col_idx, A->n, lambda, x, grad_val, st));
+    if (timers) SFG_HIP(hipEventRecord(h->pev[kPhaseMarks - 1], st));
     SFG_HIP(hipStreamSynchronize(st));
+    if (info && timers) {
+      float ms = 0.f;
+      SFG_HIP(hipEventElapsedTime(&ms, h->pev[kPhaseMarks - 2], h->pev[kPhaseMarks - 1]));
+      info->phase_ms[7] = ms;
+    }
   }
   return rc;
 }

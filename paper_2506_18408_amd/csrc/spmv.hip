@@ -863,6 +863,20 @@ hipError_t launch_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, u
   return hipGetLastError();
 }
 
+__global__ void k_sketch_identity(int64_t n, SkGroup* __restrict__ skp) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const uint32_t row = (uint32_t)r;  // (n <= SFGMRES_MAX_S: 11 bits)
+    SkGroup q{{row & 0xFFu, 0u, (row >> 8) & 7u}};
+    skp[r] = q;
+  }
+}
+
+hipError_t launch_sketch_identity(int64_t n, SkGroup* skp, hipStream_t st) {
+  hipLaunchKernelGGL(k_sketch_identity, dim3(vec_grid(n)), dim3(256), 0, st, n, skp);
+  return hipGetLastError();
+}
+
 __global__ void k_sketch_unpack(int64_t n, int32_t zeta, const SkGroup* __restrict__ skp,
                                 int32_t* __restrict__ rows, int8_t* __restrict__ signs) {
   const int ng = sk_groups(zeta);

@@ -356,12 +356,28 @@ __global__ __launch_bounds__(kVecThreads) void k_mgs_finish(const double* vpart,
   const double gj = g[j];
   g[j + 1] = -s * gj;
   g[j] = c * gj;
+  // (the first j rotations triangularise H_j, the square part, up to its
+  // last pivot av: FFOM's H_j^{-1} beta e1 is that triangle with pivot av
+  // and right side gj)
+  ctl->ffom_g = gj;
+  ctl->ffom_piv = av;
   const double rho = fabs(g[j + 1]);
   const double ffom = (c != 0.0) ? rho / fabs(c) : INFINITY;
+  // eq. (2.2) with the previous FFOM residual (beta at j = 1) and the
+  // recursion eq. (2.3), both on the inner residual ||v_j - A z_j||
+  const double rhat = sqrt(ctl->rhat2);
+  const double bound = ctl->factor * rhat;
+  const double q = 1.0 - ctl->delta * ctl->delta;
+  const double delta = q > 0.0 ? rhat / sqrt(q) : NAN;
+  ctl->bound = bound;
+  ctl->delta = delta;
   ctl->rho = rho;
   ctl->ffom = ffom;
   ctl->factor = ffom;
   if ((!isfinite(rho) || !isfinite(hn)) && ctl->error == 0) ctl->error = SFGMRES_ERR_NONFINITE;
+  // h_{j+1,j} = 0 with a zero pivot: H_j is singular (z_j = 0), and the
+  // minimiser is not defined by the triangle
+  if (hn == 0.0 && rr == 0.0 && ctl->error == 0) ctl->error = SFGMRES_ERR_BREAKDOWN;
   const bool c2 = ctl->stop_reason == SFGMRES_STOP_C2;
   host_store_i32(&hs->outer_j, j + 1);
   host_store_i32(&hs->k, ctl->stop_k);
@@ -372,7 +388,9 @@ __global__ __launch_bounds__(kVecThreads) void k_mgs_finish(const double* vpart,
   host_store_f64(&hs->hnext, hn);
   host_store_f64(&hs->cond, c2 ? ctl->cond_prev : ctl->cond_cur);
   host_store_f64(&hs->rho_hat, c2 ? ctl->rho_prev : ctl->rho_cur);
-  host_store_f64(&hs->rhat_true, sqrt(ctl->rhat2));
+  host_store_f64(&hs->rhat_true, rhat);
+  host_store_f64(&hs->bound, bound);
+  host_store_f64(&hs->delta, delta);
 }
 
 hipError_t launch_mgs_finish(const double* vpart, int32_t G, double* hout, DevCtl* ctl, int last,
@@ -548,17 +566,29 @@ hipError_t launch_finalize(const DevCtl* ctl, const double* R, const double* d,
 }
 
 // Back substitution with the Givens-rotated Hessenberg factor (column-major,
-// leading dimension ldh): y = HR[0:J,0:J]^{-1} g[0:J].
+// leading dimension ldh): y = HR[0:J,0:J]^{-1} g[0:J] (FGMRES).  With `ctl`
+// the last row takes the FFOM pivot and right side recorded by the last
+// Givens update instead, which gives y = H_J^{-1} beta e1 (FFOM, Algorithm
+// 1); a zero pivot (H_J singular) gives NaN.
 __global__ __launch_bounds__(kWave) void k_backsolve(const double* HR, const double* g,
-                                                     int32_t J, int32_t ldh, double* y) {
+                                                     int32_t J, int32_t ldh, double* y,
+                                                     const DevCtl* ctl) {
   extern __shared__ double sh[];
   double* rhs = sh;
   double* ys = sh + J;
   const int tid = threadIdx.x;
   for (int p = tid; p < J; p += kWave) rhs[p] = g[p];
   __syncthreads();
+  const bool ffom = ctl != nullptr;
+  if (ffom && tid == 0) rhs[J - 1] = ctl->ffom_g;
+  __syncthreads();
+  const double piv_last = ffom ? ctl->ffom_piv : HR[(int64_t)(J - 1) * ldh + J - 1];
+  if (ffom && piv_last == 0.0) {
+    for (int p = tid; p < J; p += kWave) y[p] = NAN;
+    return;
+  }
   for (int l = J - 1; l >= 0; --l) {
-    const double yl = rhs[l] / HR[(int64_t)l * ldh + l];
+    const double yl = rhs[l] / (l == J - 1 ? piv_last : HR[(int64_t)l * ldh + l]);
     if (tid == 0) ys[l] = yl;
     for (int p = tid; p < l; p += kWave) rhs[p] -= HR[(int64_t)l * ldh + p] * yl;
     __syncthreads();
@@ -567,9 +597,9 @@ __global__ __launch_bounds__(kWave) void k_backsolve(const double* HR, const dou
 }
 
 hipError_t launch_backsolve(const double* HR, const double* g, int32_t J, int32_t ldh,
-                            double* y, hipStream_t st) {
+                            double* y, hipStream_t st, const DevCtl* ffom_ctl) {
   hipLaunchKernelGGL(k_backsolve, dim3(1), dim3(kWave), (size_t)2 * J * sizeof(double), st, HR,
-                     g, J, ldh, y);
+                     g, J, ldh, y, ffom_ctl);
   return hipGetLastError();
 }
 

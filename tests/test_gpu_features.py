@@ -1,0 +1,237 @@
+"""GPU tests of the boundary's options and outputs beyond the plain solve:
+the identity sketch (S = I reduces eq. (1.2) to GMRES, so the HIP path is
+checked against a library GMRES and against the oracle with S = I), the FFOM
+iterate of Algorithm 1, the bounds of eq. (2.2) and eq. (2.3) logged per
+outer step, the phase timers, and the argument checks (forced inner
+dimensions, vector arguments, a singular Hessenberg matrix)."""
+import ctypes as C
+import math
+import warnings
+
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+import torch
+
+import oracle
+import paper_2506_18408_amd as P
+import paper_2506_18408_amd._lib as L
+import workloads as W
+from tests.gpu_common import requires_gpu, to_dev, tvec, hist_close
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+def _ident(w):
+    return np.array(w, copy=True)
+
+
+def _small():
+    A = W.convdiff2d(24, 1.0, (10.0, 10.0))
+    b = np.random.default_rng([1, 1]).uniform(0.0, 1.0, A.n)
+    return A, b
+
+
+@pytest.mark.parametrize("t", [0, 1, 2, 8])
+def test_identity_sketch_first_step_is_gmres(t):
+    """S = I, one outer step with k inner steps: x_1 = beta z_1 where z_1 is
+    GMRES(k) on A z = v_1, i.e. x_1 is GMRES(k) on A x = b (one cycle, zero
+    initial guess), whatever the truncation window (same Krylov space)."""
+    A, b = _small()
+    n = A.n
+    k = 6 if t == 0 else 12   # (a power basis beyond ~6 steps is too ill-conditioned for 1e-9)
+    rp, ci, va = to_dev(A)
+    x, info = P.solve(rp, ci, va, tvec(b), m=k, t=t, s=n, zeta=1, tol=1e-14, seed=0,
+                      max_outer=1, identity_sketch=True, forced_k=[k], cond_threshold=1e300)
+    xg, _ = spla.gmres(A.to_scipy(), b, x0=np.zeros(n), restart=k, maxiter=1, rtol=1e-300,
+                       atol=0)
+    xs = x.cpu().numpy()
+    assert np.linalg.norm(xs - xg) <= 1e-9 * np.linalg.norm(xg)
+
+
+@pytest.mark.parametrize("t", [2, 8])
+def test_identity_sketch_solve_matches_oracle(t):
+    """The whole FGMRES solve with S = I against the oracle with S = I."""
+    A, b = _small()
+    n = A.n
+    prm = dict(m=20, t=t, s=n, zeta=1, tol=1e-8, seed=0, max_outer=40)
+    rp, ci, va = to_dev(A)
+    x, info = P.solve(rp, ci, va, tvec(b), identity_sketch=True, **prm)
+    ref = oracle.sfgmres(A.to_scipy(), b, sketch=_ident, forced_k=list(info["inner_k"]), **prm)
+    free = oracle.sfgmres(A.to_scipy(), b, sketch=_ident, **prm)
+    assert list(info["inner_k"]) == free.inner_k
+    hist_close(info["residual_history"], ref.residual_history)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_identity_sketch_fig1_analogue():
+    """Section 2.1's Figure 1 setting with S = I on the GPU: A = randn(1000)
+    + 30 I, inner cycles of 100 steps: FGMRES reaches 1e-8 in few outer
+    steps where restarted GMRES(100) stagnates above 1e-2 (the truncated
+    window t = 8 spans the same Krylov space, so the inner cycle is still
+    GMRES(100) up to rounding)."""
+    rng = np.random.default_rng(7)
+    n = 1000
+    Ad = rng.standard_normal((n, n)) + 30 * np.eye(n)
+    b = rng.standard_normal(n)
+    A = W.CSR(n, (np.arange(n + 1) * n).astype(np.int32),
+              np.tile(np.arange(n, dtype=np.int32), n), Ad.ravel().copy())
+    rp, ci, va = to_dev(A)
+    prm = dict(m=100, t=8, s=n, zeta=1, tol=1e-8, seed=0, max_outer=40)
+    x, info = P.solve(rp, ci, va, tvec(b), identity_sketch=True, **prm)
+    assert info["converged"] and info["outer_iters"] <= 30
+    ref = oracle.sfgmres(Ad, b, sketch=_ident, forced_k=list(info["inner_k"]),
+                         record_true_residual=False, **prm)
+    J = info["outer_iters"]
+    h = np.asarray(info["residual_history"])
+    r = np.asarray(ref.residual_history[:J + 1])
+    # strict while every inner least-squares problem so far is well
+    # conditioned (u kappa below the parity bar), then the invariants
+    kap = np.asarray(info["cond_at_stop"])
+    strict = int(np.argmax(kap > 1e7)) if (kap > 1e7).any() else J
+    hist_close(h[:strict + 1], r[:strict + 1])
+    assert np.all(h[1:] <= h[:-1])
+    xg, _ = spla.gmres(Ad, b, restart=100, maxiter=J, rtol=1e-12)
+    assert np.linalg.norm(b - Ad @ xg) / np.linalg.norm(b) > 1e-2
+
+
+def test_identity_sketch_needs_s_equal_n_and_zeta_one():
+    A, b = _small()
+    rp, ci, va = to_dev(A)
+    with pytest.raises(P.SFGMRESError, match="identity_sketch"):
+        P.solve(rp, ci, va, tvec(b), m=20, t=2, s=60, zeta=1, identity_sketch=True)
+    with pytest.raises(P.SFGMRESError, match="identity_sketch"):
+        P.solve(rp, ci, va, tvec(b), m=20, t=2, s=A.n, zeta=2, identity_sketch=True)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_ffom_iterate_bounds_and_delta(precision):
+    """The FFOM iterate of the last step (Algorithm 1, x0 + Z_J H_J^{-1} beta
+    e1) against the oracle's, formed there by a dense solve of H_J; its
+    explicit residual against the FFOM residual eq. (2.1); the logged bounds
+    of eq. (2.2) and eq. (2.3) against the oracle's."""
+    A, b = _small()
+    prm = dict(m=20, t=2, s=60, zeta=8, tol=1e-8, seed=1001, max_outer=40)
+    rp, ci, va = to_dev(A)
+    x, info = P.solve(rp, ci, va, tvec(b), want_ffom=True, precision=precision, **prm)
+    J = info["outer_iters"]
+    xf = info["ffom_x"].cpu().numpy()
+    As = A.to_scipy()
+    nb = np.linalg.norm(b)
+    # eq. (2.1) on the device's own iterate
+    expl = np.linalg.norm(b - As @ xf)
+    assert abs(expl - info["ffom_residual"][J - 1]) <= 1e-6 * expl + 1e-12 * nb
+    # invariants: ||r_j|| <= ||r~_j||, eq. (2.2), eq. (2.3) while delta < 1
+    h = np.asarray(info["residual_history"]) * nb
+    assert np.all(h[1:] <= np.asarray(info["ffom_residual"]) * (1 + 1e-12))
+    assert np.all(h[1:] <= np.asarray(info["bound"]) * (1 + 1e-8) + 1e-14 * nb)
+    d = np.asarray(info["delta_bound"])
+    valid = np.cumprod(np.nan_to_num(d, nan=2.0) < 1.0).astype(bool)
+    for j in np.nonzero(valid)[0]:
+        assert h[j + 1] <= d[j] * h[j] * (1 + 1e-10)
+    if precision != "fp64":
+        return
+    ref = oracle.sfgmres(As, b, forced_k=list(info["inner_k"]), keep_basis=True, **prm)
+    assert ref.outer_iters == J
+    e1 = np.zeros(J)
+    e1[0] = ref.residual_history[0] * nb
+    xf_ref = ref.Z @ np.linalg.solve(ref.H[:J, :J], e1)
+    assert np.linalg.norm(xf - xf_ref) <= 1e-9 * np.linalg.norm(xf_ref)
+    hist_close(np.asarray(info["bound"]) / nb, np.asarray(ref.bound) / nb)
+    dr = np.asarray(ref.delta)
+    assert np.array_equal(np.isnan(d), np.isnan(dr))
+    ok = ~np.isnan(dr)
+    assert np.all(np.abs(d[ok] - dr[ok]) <= 1e-9 * dr[ok])
+
+
+def test_phase_timers():
+    A, b = _small()
+    prm = dict(m=20, t=2, s=60, zeta=8, tol=1e-8, seed=1001, max_outer=40)
+    rp, ci, va = to_dev(A)
+    x, info = P.solve(rp, ci, va, tvec(b), phase_timers=True, record_true_residual=True, **prm)
+    ph = info["phase_ms"]
+    for k in ("setup", "inner", "cycle_end", "outer", "true_residuals", "final"):
+        assert ph[k] > 0.0, (k, ph)
+    assert ph["transpose"] == 0.0 and ph["gradient"] == 0.0
+    assert sum(ph.values()) <= info["solve_ms"] * 1.05
+    x2, info2 = P.solve(rp, ci, va, tvec(b), **prm)
+    assert all(v == 0.0 for v in info2["phase_ms"].values())
+    g = tvec(np.random.default_rng(2).standard_normal(A.n))
+    lam, gv, ia = P.solve_adjoint(rp, ci, va, g, x, phase_timers=True, **prm)
+    assert ia["phase_ms"]["transpose"] > 0.0 and ia["phase_ms"]["gradient"] > 0.0
+    assert ia["phase_ms"]["inner"] > 0.0
+
+
+def _raw_solve(A, b, x, prm, forced):
+    """sfgmres_solve through ctypes with a raw forced_k array (no Python-side
+    check), returning the return code and the error text."""
+    lib = L.load()
+    rp, ci, va = to_dev(A)
+    Acsr = L.Csr(A.n, A.nnz, rp.data_ptr(), ci.data_ptr(), va.data_ptr())
+    p = P.SolveParams(**prm)
+    opt = P.api._options(p)
+    ib = P.api._InfoBuffers(p.max_outer)
+    fk = np.zeros(p.max_outer, dtype=np.int32)
+    fk[:len(forced)] = forced
+    ib.info.forced_k = fk.ctypes.data_as(C.POINTER(C.c_int32))
+    nbytes = P.api.workspace_bytes(A.n, A.nnz, p)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=rp.device)
+    h = P.api._handle(rp.device)
+    bt = tvec(b)
+    rc = lib.sfgmres_solve(h, C.byref(Acsr), bt.data_ptr(), None, x.data_ptr(), p.m, p.t, p.s,
+                           p.zeta, p.tol, p.seed, C.byref(opt), C.byref(ib.info), ws.data_ptr(),
+                           ws.numel(), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    return rc, lib.sfgmres_last_error(h).decode()
+
+
+def test_forced_k_out_of_range_is_rejected_by_the_library():
+    A, b = _small()
+    x = torch.zeros(A.n, dtype=torch.float64, device="cuda:0")
+    prm = dict(m=20, t=2, s=60, zeta=8, tol=1e-8, seed=1001, max_outer=5)
+    rc, msg = _raw_solve(A, b, x, prm, [3, 21])
+    assert rc == L.ERR_INVALID and "forced_k" in msg
+    rc, msg = _raw_solve(A, b, x, prm, [-2])
+    assert rc == L.ERR_INVALID
+    rc, _ = _raw_solve(A, b, x, prm, [3, 20, 0, 4])
+    assert rc in (L.OK, L.NOT_CONVERGED)
+    assert torch.isfinite(x).all()
+
+
+def test_vector_arguments_rejected_before_launch():
+    A, b = _small()
+    rp, ci, va = to_dev(A)
+    with pytest.raises(ValueError):
+        P.solve(rp, ci, va, torch.from_numpy(b), m=20, t=2, s=60)           # host b
+    with pytest.raises(ValueError):
+        P.solve(rp, ci, va, tvec(b), x0=tvec(np.zeros(2 * A.n))[::2], m=20, t=2, s=60)
+    g = torch.zeros(A.n, dtype=torch.float32, device="cuda:0")
+    with pytest.raises(ValueError):
+        P.solve_adjoint(rp, ci, va, g, None, m=20, t=2, s=60)                # float32 g
+    with pytest.raises(ValueError):
+        P.solve_adjoint(rp, ci, va, tvec(b), torch.from_numpy(b), m=20, t=2, s=60)  # host x
+
+
+def test_singular_hessenberg_is_a_breakdown():
+    """b in the null space of S (two columns of a zeta = 1 sketch sharing a
+    row, with opposite signed entries): S v_1 = 0, so the inner solution
+    is z_1 = 0, A z_1 = 0 and H_1 = [0; 0] is singular: the FGMRES
+    minimiser is undefined (Algorithm 1 needs h_{1,1} != 0 or h_{2,1} != 0).
+    The library reports a breakdown; the oracle's triangular solve fails on
+    the same singular factor."""
+    A, _ = _small()
+    n, s = A.n, 60
+    rows, signs = P.sketch_materialize(n, s, 1, 5)
+    rows = rows.cpu().numpy()[:, 0]
+    signs = signs.cpu().numpy()[:, 0]
+    i = 0
+    j = int(np.nonzero(rows == rows[i])[0][1])
+    b = np.zeros(n)
+    b[i] = float(signs[i])
+    b[j] = -float(signs[j])
+    rp, ci, va = to_dev(A)
+    with pytest.raises(P.SFGMRESError) as ei:
+        P.solve(rp, ci, va, tvec(b), m=20, t=2, s=s, zeta=1, tol=1e-8, seed=5, max_outer=5)
+    assert ei.value.code == L.ERR_BREAKDOWN
+    with pytest.raises(Exception):
+        oracle.sfgmres(A.to_scipy(), b, m=20, t=2, s=s, zeta=1, tol=1e-8, seed=5, max_outer=5)

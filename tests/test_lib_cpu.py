@@ -83,3 +83,56 @@ def test_missing_library_fails_loudly(monkeypatch, tmp_path):
     monkeypatch.setattr(L, "LIB_PATH", str(tmp_path / "nope.so"))
     with pytest.raises(RuntimeError, match="missing"):
         L.load()
+
+
+def test_ctypes_structures_match_the_header(tmp_path):
+    """sizeof and offsetof of the option and info structs, from a C program
+    compiled against include/sfgmres.h, equal the ctypes mirrors."""
+    import shutil
+    import subprocess
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {"sfgmres_options": L.Options, "sfgmres_info": L.Info, "sfgmres_csr": L.Csr}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    for cname, cls in fields.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'  printf("{cname} {fname} %zu\\n", offsetof({cname}, {fname}));')
+    lines.append("  return 0;\n}")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c99", str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(ln.split()[:2]): int(ln.split()[2]) for ln in out if ln.strip()}
+    for cname, cls in fields.items():
+        assert got[(cname, "size")] == C.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert got[(cname, fname)] == getattr(cls, fname).offset, (cname, fname)
+
+
+def test_vector_arguments_are_checked_before_any_launch():
+    """The C ABI cannot tell host from device pointers, so the binding
+    rejects host, float32, strided and wrongly sized vectors itself."""
+    torch = pytest.importorskip("torch")
+    import paper_2506_18408_amd.api as api
+    cuda0 = torch.device("cuda", 0)
+    with pytest.raises(ValueError, match="on cuda:0"):
+        api.check_vector("b", torch.zeros(8, dtype=torch.float64), 8, cuda0)
+    with pytest.raises(ValueError, match="float64"):
+        api.check_vector("g", torch.zeros(8, dtype=torch.float32), 8, cuda0)
+    cpu = torch.device("cpu")
+    with pytest.raises(ValueError, match="contiguous"):
+        api.check_vector("x0", torch.zeros(16, dtype=torch.float64)[::2], 8, cpu)
+    with pytest.raises(ValueError, match="8 entries"):
+        api.check_vector("out", torch.zeros(9, dtype=torch.float64), 8, cpu)
+    api.check_vector("b", torch.zeros(8, dtype=torch.float64), 8, cpu)  # (well formed)
+    with pytest.raises(ValueError, match="GPU"):
+        api.solve(torch.zeros(9, dtype=torch.int32), torch.zeros(8, dtype=torch.int32),
+                  torch.zeros(8, dtype=torch.float64), torch.zeros(8, dtype=torch.float64))
+    with pytest.raises(ValueError, match="forced_k"):
+        api.check_forced_k([3, 31], 30)
+    with pytest.raises(ValueError, match="forced_k"):
+        api.check_forced_k([-1], 30)
+    api.check_forced_k([0, 30, 5], 30)

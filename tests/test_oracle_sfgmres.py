@@ -255,3 +255,31 @@ def test_adjoint_against_dense_gradient():
         Ap[rows[p], Am.col_idx[p]] -= 2 * h
         Lm = np.sum((np.linalg.solve(Ap, b) - xt) ** 2)
         assert abs((Lp - Lm) / (2 * h) - grad[p]) <= 1e-5 * max(1.0, abs(grad[p]))
+
+
+def test_recursive_bound_eq_2_3(c1_run):
+    """Section 2.3: while every delta_i (i <= j) is below one, the FGMRES
+    residual contracts at least by delta_j per step, with delta_j built
+    from the inner residuals alone."""
+    A, b, r = c1_run
+    h = np.array(r.residual_history)
+    d = np.array(r.delta)
+    rh = np.array(r.inner_true_residual)
+    assert d[0] == pytest.approx(rh[0], rel=1e-15)      # delta_1 = ||r^_1|| (delta_0 = 0)
+    valid = np.cumprod(np.nan_to_num(d, nan=2.0) < 1.0).astype(bool)
+    assert valid.sum() >= 3
+    for j in np.nonzero(valid)[0]:
+        assert h[j + 1] <= d[j] * h[j] * (1 + 1e-10)
+
+
+def test_recursive_bound_turns_nan_once_delta_reaches_one():
+    """m = 1 (FGMRES = GMRES): the inner residual is ||v - c A v|| with the
+    best scalar c, close to one, so delta exceeds one after a few steps and
+    the recursion has no real value from then on."""
+    A, b = _small_systems()[0]
+    r = oracle.sfgmres(A, b, m=1, t=0, s=40, zeta=8, tol=1e-9, seed=3, max_outer=20)
+    d = np.array(r.delta)
+    assert np.isnan(d).any()
+    first = int(np.argmax(np.isnan(d)))
+    assert first >= 1 and d[first - 1] >= 1.0
+    assert np.isnan(d[first:]).all()
