@@ -155,10 +155,26 @@ def sgmres_cycle(A, v, sketch, *, m, t, tol_abs, factor, cond_threshold=1e15,
     return z, info
 
 
+class RightPreconditioned:
+    """The operator A M^{-1} of right preconditioning (M has .solve)."""
+
+    def __init__(self, A, M):
+        self.A = A
+        self.M = M
+
+    def __matmul__(self, v):
+        return self.A @ self.M.solve(v)
+
+
 def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
             cond_threshold=1e15, c2_rule="ice", forced_k=None, sketch=None,
-            record_true_residual=True, trace=False, keep_basis=False) -> OracleResult:
-    """FGMRES (Algorithm 1) preconditioned by one sGMRES cycle per step."""
+            record_true_residual=True, trace=False, keep_basis=False,
+            precond=None) -> OracleResult:
+    """FGMRES (Algorithm 1) preconditioned by one sGMRES cycle per step.
+
+    precond (an object with .solve(r) = M^{-1} r, e.g. oracle.ilu.ILU0):
+    right preconditioning; the inner cycle solves A M^{-1} u = v_j and the
+    outer step takes z_j = M^{-1} u, so Algorithm 1 keeps A and b - A x."""
     A = sp.csr_matrix(A) if not sp.issparse(A) and not hasattr(A, "__matmul__") else A
     b = np.asarray(b, dtype=np.float64)
     n = b.shape[0]
@@ -198,9 +214,12 @@ def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
     for j in range(max_outer):
         tr = [] if trace else None
         fk = None if forced_k is None else int(forced_k[j])
-        z, info = sgmres_cycle(A, V[j], sketch, m=m, t=t, tol_abs=tol * nb, factor=factor,
+        A_in = A if precond is None else RightPreconditioned(A, precond)
+        z, info = sgmres_cycle(A_in, V[j], sketch, m=m, t=t, tol_abs=tol * nb, factor=factor,
                                cond_threshold=cond_threshold, c2_rule=c2_rule, forced_k=fk,
                                trace=tr)
+        if precond is not None:
+            z = precond.solve(z)                      # z_j = M^{-1} B_k y_k
         Z.append(z)
         w = A @ z
         rhat = float(np.linalg.norm(V[j] - w))
