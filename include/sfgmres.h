@@ -63,6 +63,13 @@ extern "C" {
 #define SFGMRES_OUTER_FGMRES    0  /* Algorithm 1 (default)                               */
 #define SFGMRES_OUTER_RESTARTED 1  /* restarted sGMRES (the paper's comparison method)    */
 
+/* ---- preconditioning (sfgmres_options.precond) ----------------------- */
+#define SFGMRES_PRECOND_NONE    0  /* (default)                                            */
+#define SFGMRES_PRECOND_ILU0    1  /* zero-fill ILU, right preconditioning (Section 4.4, the
+                                      "-p" rows of Table 1), in a multicolour elimination
+                                      order; needs sorted columns and every diagonal entry
+                                      in the pattern; FGMRES outer only                     */
+
 /* ---- inner stop reasons (sfgmres_info.stop_reason) ------------------- */
 #define SFGMRES_STOP_C1         1  /* k reached m                                  */
 #define SFGMRES_STOP_C2         2  /* cond estimate of S A B_i exceeded threshold: k = i-1 */
@@ -118,7 +125,16 @@ typedef struct sfgmres_options {
                                    same Krylov space.  Default 0                                 */
   int32_t phase_timers;         /* 1: time the phases of the solve with HIP events on the
                                    caller's stream into sfgmres_info.phase_ms; default 0        */
-  int32_t reserved[2];
+  int32_t precond;              /* SFGMRES_PRECOND_NONE (default) or SFGMRES_PRECOND_ILU0:
+                                   M = L U, the zero-fill incomplete factorisation of A in the
+                                   order of a Jones-Plassmann colouring of A + A^T (one parallel
+                                   level per colour); the inner cycle works on A M^{-1} and
+                                   z_j = M^{-1} B_k y_k, so residuals stay b - A x.  Built on
+                                   the device at the start of every solve (of A^T for the
+                                   adjoint).  SFGMRES_ERR_INVALID for unsorted columns or a
+                                   missing diagonal entry, SFGMRES_ERR_BREAKDOWN for a zero
+                                   pivot                                                          */
+  int32_t reserved[1];
 } sfgmres_options;
 
 /* Solve diagnostics.  Scalars are always written; each per-step array is a
@@ -242,6 +258,17 @@ int sfgmres_transpose_workspace_bytes(int64_t n, int64_t nnz, size_t* bytes);
 int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t,
                       int32_t* col_idx_t, double* val_t, int32_t* perm, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* The zero-fill ILU factorisation that SFGMRES_PRECOND_ILU0 builds (Section
+ * 4.4's right preconditioner), as a test export: lu [nnz] receives the
+ * factor values on A's pattern (entries whose column has a lower colour
+ * than their row hold L, unit diagonal implied; the others hold U) and
+ * color [n] the Jones-Plassmann colour of every row, which fixes the
+ * elimination order (colour, then index).  Device arrays; needs
+ * sfgmres_ilu_workspace_bytes of workspace.  Errors as for the option. */
+int sfgmres_ilu_workspace_bytes(int64_t n, int64_t nnz, size_t* bytes);
+int sfgmres_ilu0(sfgmres_handle h, const sfgmres_csr* A, double* lu, int32_t* color, void* ws,
+                 size_t ws_bytes, void* stream);
 
 /* Workspace bytes of sfgmres_sketch_materialize and sfgmres_sketch_apply
  * for an s x n sketch with zeta nonzeros per column. */

@@ -4,6 +4,7 @@ preconditioner, as hand-written HIP kernels behind the C ABI in
 include/sfgmres.h, with a PyTorch binding and an adjoint for autograd."""
 from .api import (  # noqa: F401
     SFGMRESError,
+    ilu0,
     SolveParams,
     release_workspaces,
     sketch_apply,

@@ -38,7 +38,9 @@ class SolveParams:
     every column); outer: "fgmres" (Algorithm 1) or "restarted" (restarted
     sGMRES, the paper's comparison method); identity_sketch: S = I (a test
     option: needs s == n and zeta == 1; the inner cycle is then GMRES(k));
-    phase_timers: per-phase GPU times into info["phase_ms"].
+    phase_timers: per-phase GPU times into info["phase_ms"]; precond: "none"
+    or "ilu0" (zero-fill ILU right preconditioning in a multicolour order,
+    FGMRES outer only).
     """
     m: int = 30
     t: int = 2
@@ -54,6 +56,7 @@ class SolveParams:
     outer: str = "fgmres"
     identity_sketch: bool = False
     phase_timers: bool = False
+    precond: str = "none"
 
 
 _HANDLES = {}
@@ -137,6 +140,7 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.outer = {"fgmres": 0, "restarted": 1}[p.outer]
     o.identity_sketch = 1 if p.identity_sketch else 0
     o.phase_timers = 1 if p.phase_timers else 0
+    o.precond = {"none": L.PRECOND_NONE, "ilu0": L.PRECOND_ILU0}[p.precond]
     return o
 
 
@@ -309,6 +313,23 @@ def transpose(row_ptr, col_idx, val=None):
                                       _stream()), h)
     nnz = A.nnz
     return rp_t, col_t[:nnz], (val_t[:nnz] if val_t is not None else None), perm[:nnz]
+
+
+def ilu0(row_ptr, col_idx, val):
+    """(lu [nnz], color [n]) of the ILU(0) factorisation the ilu0
+    preconditioner builds: factor values on A's pattern and the colour of
+    every row (elimination order: colour, then index)."""
+    A = _csr(row_ptr, col_idx, val)
+    dev = row_ptr.device
+    lu = torch.empty(max(A.nnz, 1), dtype=torch.float64, device=dev)
+    color = torch.empty(A.n, dtype=torch.int32, device=dev)
+    need = C.c_size_t()
+    _check(L.load().sfgmres_ilu_workspace_bytes(A.n, A.nnz, C.byref(need)), None)
+    ws = _workspace(need.value, dev, "ilu")
+    h = _handle(dev)
+    _check(L.load().sfgmres_ilu0(h, C.byref(A), lu.data_ptr(), color.data_ptr(), ws.data_ptr(),
+                                 ws.numel(), _stream()), h)
+    return lu[:A.nnz], color
 
 
 def sketch_materialize(n: int, s: int, zeta: int, seed: int, device="cuda"):

@@ -3,6 +3,8 @@
 // `st` and returns the hipError_t of the launch.
 #pragma once
 
+#include <string>
+
 #include "common.hpp"
 
 namespace sfg {
@@ -197,6 +199,47 @@ hipError_t launch_transpose(const int32_t* row_ptr, const int32_t* col_idx, cons
                             hipStream_t st);
 
 size_t transpose_scan_tmp_ints(int64_t n);
+
+// Zero-fill ILU right preconditioner in a multicolour order (ilu.hip).
+constexpr int kIluMaxColors = 4095;  // (12-bit colour field of the colouring state)
+struct IluFactors {
+  const int32_t* rp;       // A's pattern (sorted columns)
+  const int32_t* ci;
+  const double* lu;        // factor values on A's pattern: L below (by colour), U above
+  const int8_t* kind;      // per nonzero: -1 L, 0 diagonal, +1 U
+  const int32_t* diag;     // position of the diagonal in each row
+  const int32_t* order;    // rows grouped by colour
+  const int32_t* level;    // host array: order[level[c] .. level[c+1]) has colour c
+  int32_t ncolors;
+};
+hipError_t launch_ilu_init(int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
+                           double* lu, int32_t* diag, int32_t* state, int32_t* err,
+                           hipStream_t st);
+hipError_t launch_ilu_jp_round(int64_t n, const int32_t* rp, const int32_t* ci,
+                               const int32_t* rpt, const int32_t* cit, int32_t* state,
+                               int32_t round, int32_t* colored, int32_t* err, hipStream_t st);
+hipError_t launch_ilu_count(int64_t n, const int32_t* state, int32_t* cnt, hipStream_t st);
+hipError_t launch_ilu_colors(int64_t n, const int32_t* state, int32_t* color, hipStream_t st);
+hipError_t launch_ilu_scatter(int64_t n, const int32_t* rp, const int32_t* ci,
+                              const int32_t* state, const int32_t* start, int32_t* cursor,
+                              int32_t* order, int8_t* kind, hipStream_t st);
+hipError_t launch_ilu_factor(const int32_t* order, int32_t begin, int32_t end, const int32_t* rp,
+                             const int32_t* ci, const int8_t* kind, const int32_t* diag,
+                             const int32_t* state, double* lu, int32_t* err, hipStream_t st);
+// out = M^{-1} in (VT = float when fp32), through the FP64 work vector t;
+// with ctl, every launch does nothing once the inner cycle has stopped.
+hipError_t launch_ilu_apply(bool fp32, const IluFactors& f, const void* in, double* t, void* out,
+                            hipStream_t st, const DevCtl* ctl = nullptr);
+
+// The fused SpMV export (sfgmres_spmv_sketch) on a workspace of ws_bytes
+// bytes, and the bytes it needs (solver.hip).
+int spmv_sketch_impl(sfgmres_ctx* h, const sfgmres_csr* A, const double* u, double scale,
+                     double* w, int32_t s, int32_t zeta, uint64_t seed, const double* U,
+                     int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2, void* ws,
+                     size_t ws_bytes, void* stream);
+size_t spmv_sketch_workspace(int64_t n, int64_t nnz, int32_t s, int32_t zeta);
+// Records msg as the handle's last error and returns code (solver.hip).
+int report_error(sfgmres_ctx* h, int code, const std::string& msg);
 int vec_grid(int64_t n);
 int arnoldi_grid(int64_t n);
 

@@ -70,8 +70,35 @@ int lookahead_steps(const sfgmres_options& o) {
   return o.lookahead > 0 ? std::max(o.lookahead, p) : 2 * p;
 }
 
+struct IluWs {
+  size_t lu, kind, diag, state, order, cnt, t_rp, t_ci, t_perm, t_cursor, t_scan, total;
+};
+
+// The ILU regions of a workspace (appended to `off`).
+IluWs ilu_regions(int64_t n, int64_t nnz, size_t off) {
+  IluWs W{};
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  W.lu = take((size_t)nnz * 8);
+  W.kind = take((size_t)nnz);
+  W.diag = take((size_t)n * 4);
+  W.state = take((size_t)n * 4);
+  W.order = take((size_t)n * 4);
+  W.cnt = take((size_t)(3 * (kIluMaxColors + 1) + 8) * 4);
+  W.t_rp = take((size_t)(n + 1) * 4);
+  W.t_ci = take((size_t)nnz * 4);
+  W.t_perm = take((size_t)nnz * 4);
+  W.t_cursor = take((size_t)(n + 1) * 4);
+  W.t_scan = take(transpose_scan_tmp_ints(n) * 4);
+  W.total = off;
+  return W;
+}
+
 Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
-                   int32_t J, int32_t precision, int32_t adjoint, int32_t panel) {
+                   int32_t J, int32_t precision, int32_t adjoint, int32_t panel, int32_t precond) {
   (void)t;
   Layout L{};
   const bool f32 = precision == SFGMRES_MIXED;
@@ -118,6 +145,17 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.W64 = take((size_t)L.ld * 8);
   L.X = take((size_t)L.ld * 8);
   L.val32 = take(f32 ? (size_t)nnz * 4 : 0);
+  // ILU(0): factor values, entry kinds, diagonal positions, colouring state,
+  // rows by colour, counters (per-colour counts, cursors and starts, then
+  // the error and coloured-count words), the transposed pattern for the
+  // colouring, the FP64 work vector and the preconditioned inner vector
+  // (placed before the adjoint's regions: the adjoint solve runs on this
+  // layout without them)
+  const bool ilu = precond == SFGMRES_PRECOND_ILU0;
+  L.ilu = off;
+  if (ilu) off = ilu_regions(n, nnz, off).total;
+  L.ilu_t64 = take(ilu ? (size_t)L.ld * 8 : 0);
+  L.ilu_tmp = take(ilu ? (size_t)L.ld * vt : 0);
   if (adjoint) {
     L.at_rowptr = take((size_t)(n + 1) * 4);
     L.at_col = take((size_t)nnz * 4);
@@ -161,6 +199,7 @@ sfgmres_options defaults() {
   o.lookahead = 0;
   o.panel = 0;
   o.outer = SFGMRES_OUTER_FGMRES;
+  o.precond = SFGMRES_PRECOND_NONE;
   return o;
 }
 
@@ -199,6 +238,10 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
     return fail(h, SFGMRES_ERR_INVALID, "identity_sketch needs s == n and zeta == 1");
   if (o.phase_timers != 0 && o.phase_timers != 1)
     return fail(h, SFGMRES_ERR_INVALID, "phase_timers must be 0 or 1");
+  if (o.precond != SFGMRES_PRECOND_NONE && o.precond != SFGMRES_PRECOND_ILU0)
+    return fail(h, SFGMRES_ERR_INVALID, "precond must be SFGMRES_PRECOND_NONE or _ILU0");
+  if (o.precond != SFGMRES_PRECOND_NONE && o.outer != SFGMRES_OUTER_FGMRES)
+    return fail(h, SFGMRES_ERR_INVALID, "precond needs the FGMRES outer iteration");
   return SFGMRES_OK;
 }
 
@@ -325,6 +368,78 @@ bool spin_until(sfgmres_ctx* h, Pred pred) {
   return true;
 }
 
+// ILU(0) set-up on the device: diagonal positions and the check of the
+// pattern, the transposed pattern, Jones-Plassmann rounds until every row
+// is coloured, rows grouped by colour (level starts read back to the
+// host), then the factorisation one colour at a time.
+int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L,
+              hipStream_t st, IluFactors* F, std::vector<int32_t>* levels) {
+  const int64_t n = A->n, nnz = A->nnz;
+  double* lu = reinterpret_cast<double*>(base + L.lu);
+  int8_t* kind = reinterpret_cast<int8_t*>(base + L.kind);
+  int32_t* diag = reinterpret_cast<int32_t*>(base + L.diag);
+  int32_t* state = reinterpret_cast<int32_t*>(base + L.state);
+  int32_t* order = reinterpret_cast<int32_t*>(base + L.order);
+  int32_t* cnt = reinterpret_cast<int32_t*>(base + L.cnt);
+  int32_t* cursor = cnt + (kIluMaxColors + 1);
+  int32_t* start = cursor + (kIluMaxColors + 1);
+  int32_t* err = start + (kIluMaxColors + 1);
+  int32_t* colored = err + 1;
+  int32_t* trp = reinterpret_cast<int32_t*>(base + L.t_rp);
+  int32_t* tci = reinterpret_cast<int32_t*>(base + L.t_ci);
+  SFG_HIP(hipMemsetAsync(cnt, 0, (size_t)(3 * (kIluMaxColors + 1) + 8) * 4, st));
+  SFG_HIP(launch_ilu_init(n, A->row_ptr, A->col_idx, A->val, lu, diag, state, err, st));
+  SFG_HIP(launch_transpose(A->row_ptr, A->col_idx, nullptr, n, nnz, trp, tci, nullptr,
+                           reinterpret_cast<int32_t*>(base + L.t_perm),
+                           reinterpret_cast<int32_t*>(base + L.t_cursor),
+                           reinterpret_cast<int32_t*>(base + L.t_scan), st));
+  int32_t hv[2] = {0, 0};
+  SFG_HIP(hipMemcpyAsync(hv, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  if (hv[0] & 3)
+    return fail(h, SFGMRES_ERR_INVALID,
+                "ILU(0) needs strictly increasing columns in every row and every diagonal entry");
+  // (the globally highest-priority uncoloured vertex colours itself in every
+  // round, so at most n rounds; the round number sits above the 12 colour bits)
+  const int64_t max_rounds = std::min<int64_t>(n + 1, (int64_t)1 << 19);
+  int64_t r = 0;
+  for (;; ++r) {
+    if (r >= max_rounds) return fail(h, SFGMRES_ERR_INVALID, "ILU colouring did not finish");
+    SFG_HIP(launch_ilu_jp_round(n, A->row_ptr, A->col_idx, trp, tci, state, (int32_t)r, colored,
+                                err, st));
+    SFG_HIP(hipMemcpyAsync(hv, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    SFG_HIP(hipStreamSynchronize(st));
+    if (hv[1] >= n || hv[0]) break;
+  }
+  if (hv[0] & 4) return fail(h, SFGMRES_ERR_INVALID, "ILU colouring needs more than 4095 colours");
+  SFG_HIP(launch_ilu_count(n, state, cnt, st));
+  std::vector<int32_t> hc(kIluMaxColors + 1, 0);
+  SFG_HIP(hipMemcpyAsync(hc.data(), cnt, hc.size() * 4, hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  int nc = 0;
+  for (int c = 0; c < kIluMaxColors; ++c)
+    if (hc[c]) nc = c + 1;
+  levels->assign(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) (*levels)[c + 1] = (*levels)[c] + hc[c];
+  SFG_HIP(hipMemcpyAsync(start, levels->data(), (size_t)(nc + 1) * 4, hipMemcpyHostToDevice, st));
+  SFG_HIP(launch_ilu_scatter(n, A->row_ptr, A->col_idx, state, start, cursor, order, kind, st));
+  for (int c = 0; c < nc; ++c)
+    SFG_HIP(launch_ilu_factor(order, (*levels)[c], (*levels)[c + 1], A->row_ptr, A->col_idx, kind,
+                              diag, state, lu, err, st));
+  SFG_HIP(hipMemcpyAsync(hv, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  if (hv[0] & 8) return fail(h, SFGMRES_ERR_BREAKDOWN, "zero pivot in the ILU(0) factorisation");
+  F->rp = A->row_ptr;
+  F->ci = A->col_idx;
+  F->lu = lu;
+  F->kind = kind;
+  F->diag = diag;
+  F->order = order;
+  F->level = levels->data();
+  F->ncolors = nc;
+  return SFGMRES_OK;
+}
+
 // Timing events of the phase_timers option (created once per handle).
 constexpr int kPhaseMarks = 8;
 int ensure_marks(sfgmres_handle h) {
@@ -347,7 +462,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   if (!A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val)) || !b || !x)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
   const int pc = panel_cols(o);
-  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0, pc);
+  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0, pc, o.precond);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   char* base = static_cast<char*>(ws);
@@ -433,6 +548,15 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int32_t ntiles = tiling.ntiles;
   const int Gp = tiling.grid;
   const int Gn = rows_grid(n);
+  const bool ilu = o.precond == SFGMRES_PRECOND_ILU0;
+  IluFactors F{};
+  std::vector<int32_t> ilu_levels;
+  double* ilu_t64 = reinterpret_cast<double*>(base + L.ilu_t64);
+  void* ilu_tmp = base + L.ilu_tmp;
+  if (ilu) {
+    rc = ilu_setup(h, A, base, ilu_regions(n, nnz, L.ilu), st, &F, &ilu_levels);
+    if (rc) return rc;
+  }
   const int G2 = vec_grid(n);
   const int Ga = arnoldi_grid(n);  // the Arnoldi update (and its norm partials)
   memset((void*)hsh, 0, sizeof(HostStatus));
@@ -584,6 +708,12 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       SpmvArgs a = base_args;
       a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
       a.x = Bcol(i);
+      if (ilu) {
+        // the inner operator A M^{-1}: the SpMV reads M^{-1} u_i (the solves
+        // are predicated on the stop flag as the SpMV is)
+        SFG_HIP(launch_ilu_apply(f32, F, Bcol(i), ilu_t64, ilu_tmp, st, P.ctl));
+        a.x = ilu_tmp;
+      }
       // t = 0: y = sigma_i A u_i = A b_i is the next (unnormalised) power-basis
       // vector, sigma_i formed by the SpMV itself from the previous step's
       // norm partials (sigma_0 is set with the cycle); t > 0: y = A u_i,
@@ -732,7 +862,13 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       if (rc) return rc;
       continue;
     }
-    SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
+    if (ilu) {
+      // z_j = M^{-1} B_k y_k
+      SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, P.W64, st));
+      SFG_HIP(launch_ilu_apply(false, F, P.W64, ilu_t64, Zcol(j), st));
+    } else {
+      SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
+    }
     SFG_HIP(mark(kMarkZ));
     // w = A z_j with h_{1,j}; modified Gram-Schmidt; Givens
     {
@@ -865,6 +1001,79 @@ SmallLayout small_layout(int64_t n, int64_t nnz, int32_t s, int32_t zeta) {
 
 }  // namespace
 
+namespace sfg {
+
+int report_error(sfgmres_ctx* h, int code, const std::string& msg) { return fail(h, code, msg); }
+
+size_t spmv_sketch_workspace(int64_t n, int64_t nnz, int32_t s, int32_t zeta) {
+  return small_layout(n, nnz, s, zeta).total;
+}
+
+// The fused SpMV export on a given workspace (the entry points with and
+// without a workspace argument share it).
+int spmv_sketch_impl(sfgmres_handle h, const sfgmres_csr* A, const double* u, double scale,
+                     double* w, int32_t s, int32_t zeta, uint64_t seed, const double* U,
+                     int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2, void* ws,
+                     size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!A || !A->row_ptr || !u || !c || !norm2 || (A->nnz > 0 && (!A->col_idx || !A->val)))
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) || !sketch_args_ok(A->n, s, zeta) || nwin < 0 ||
+      nwin > SFGMRES_MAX_T || (nwin > 0 && (!U || !dots || ldu < A->n)))
+    return fail(h, SFGMRES_ERR_INVALID, "invalid sizes");
+  const SmallLayout L = small_layout(A->n, A->nnz, s, zeta);
+  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
+  int32_t* tiles = reinterpret_cast<int32_t*>(base + L.tiles);
+  int32_t* tp = reinterpret_cast<int32_t*>(base + L.tp);
+  int32_t* ipart = reinterpret_cast<int32_t*>(base + L.ipart);
+  double* part = reinterpret_cast<double*>(base + L.part);
+  double* dpart = reinterpret_cast<double*>(base + L.dpart);
+  double* red = reinterpret_cast<double*>(base + L.red);
+  SkGroup* skp = reinterpret_cast<SkGroup*>(base + L.skp);
+  Tiling tiling{};
+  const int prc = plan_tiling(h, A, tiles, tp, ipart, st, &tiling);
+  if (prc) return prc;
+  const int32_t ntiles = tiling.ntiles;
+  const int Gp = tiling.grid;
+  SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
+  SFG_HIP(launch_sketch_pack(A->n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu),
+                             (uint32_t)(seed >> 32), skp, st));
+  SpmvArgs a{};
+  a.n = A->n;
+  a.row_ptr = A->row_ptr;
+  a.col_idx = A->col_idx;
+  a.val = A->val;
+  a.tiles = tiles;
+  a.tp = tp;
+  a.ntiles = ntiles;
+  a.short_tiles = tiling.max_row <= kShortRow;
+  a.x = u;
+  a.scale_val = scale;
+  a.w = w;
+  a.s = s;
+  a.skp = skp;
+  a.zeta = zeta;
+  a.U = U;
+  a.ldu = ldu;
+  a.l0 = 0;
+  a.nwin = nwin;
+  a.part = part;
+  a.dpart = dpart;
+  a.ctl = ctl;
+  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, sk_groups(zeta), st));
+  SFG_HIP(launch_reduce_slots(part, Gp, s, s, 0, 1, 1, 0, 0, red, ctl, false, st));
+  SFG_HIP(launch_sketch_out(red, s, 1.0 / sqrt((double)zeta), dpart, Gp, nwin, c, dots, norm2,
+                            st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
+}  // namespace sfg
+
 extern "C" {
 
 int sfgmres_default_options(sfgmres_options* opt) {
@@ -882,7 +1091,7 @@ int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_
       o.lookahead < 0 || o.lookahead > 64 || o.panel < 0 || o.panel > kPanel)
     return SFGMRES_ERR_INVALID;
   *bytes = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, adjoint ? 1 : 0,
-                       panel_cols(o))
+                       panel_cols(o), o.precond)
                .total;
   return SFGMRES_OK;
 }
@@ -964,7 +1173,7 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   if ((A->nnz > 0 && (!A->col_idx || !A->val)) || !g || !lambda)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
   const Layout L = make_layout(A->n, A->nnz, m, t, s, zeta, o.max_outer, o.precision, 1,
-                               panel_cols(o));
+                               panel_cols(o), o.precond);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1042,6 +1251,37 @@ int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t
   return SFGMRES_OK;
 }
 
+int sfgmres_ilu_workspace_bytes(int64_t n, int64_t nnz, size_t* bytes) {
+  if (!bytes || n < 1 || n >= ((int64_t)1 << 31) || nnz < 0 || nnz >= ((int64_t)1 << 31))
+    return SFGMRES_ERR_INVALID;
+  *bytes = ilu_regions(n, nnz, 0).total;
+  return SFGMRES_OK;
+}
+
+int sfgmres_ilu0(sfgmres_handle h, const sfgmres_csr* A, double* lu, int32_t* color, void* ws,
+                 size_t ws_bytes, void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  if (!A || !A->row_ptr || !A->col_idx || !A->val || !lu || !color)
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  size_t need = 0;
+  if (sfgmres_ilu_workspace_bytes(A->n, A->nnz, &need) != SFGMRES_OK)
+    return fail(h, SFGMRES_ERR_INVALID, "invalid sizes");
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  h->err.clear();
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const IluWs W = ilu_regions(A->n, A->nnz, 0);
+  IluFactors F{};
+  std::vector<int32_t> levels;
+  const int rc = ilu_setup(h, A, base, W, st, &F, &levels);
+  if (rc) return rc;
+  SFG_HIP(hipMemcpyAsync(lu, base + W.lu, (size_t)A->nnz * 8, hipMemcpyDeviceToDevice, st));
+  SFG_HIP(launch_ilu_colors(A->n, reinterpret_cast<const int32_t*>(base + W.state), color, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
 int sfgmres_sketch_workspace_bytes(int64_t n, int32_t s, int32_t zeta, size_t* bytes) {
   if (!bytes || !sketch_args_ok(n, s, zeta)) return SFGMRES_ERR_INVALID;
   *bytes = small_layout(n, 0, s, zeta).total;
@@ -1104,61 +1344,8 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
                         double* w, int32_t s, int32_t zeta, uint64_t seed, const double* U,
                         int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2,
                         void* ws, size_t ws_bytes, void* stream) {
-  if (!h) return SFGMRES_ERR_INVALID;
-  if (!A || !A->row_ptr || !u || !c || !norm2 || (A->nnz > 0 && (!A->col_idx || !A->val)))
-    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
-  if (A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) || !sketch_args_ok(A->n, s, zeta) || nwin < 0 ||
-      nwin > SFGMRES_MAX_T || (nwin > 0 && (!U || !dots || ldu < A->n)))
-    return fail(h, SFGMRES_ERR_INVALID, "invalid sizes");
-  const SmallLayout L = small_layout(A->n, A->nnz, s, zeta);
-  if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
-    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
-  hipStream_t st = static_cast<hipStream_t>(stream);
-  char* base = static_cast<char*>(ws);
-  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
-  int32_t* tiles = reinterpret_cast<int32_t*>(base + L.tiles);
-  int32_t* tp = reinterpret_cast<int32_t*>(base + L.tp);
-  int32_t* ipart = reinterpret_cast<int32_t*>(base + L.ipart);
-  double* part = reinterpret_cast<double*>(base + L.part);
-  double* dpart = reinterpret_cast<double*>(base + L.dpart);
-  double* red = reinterpret_cast<double*>(base + L.red);
-  SkGroup* skp = reinterpret_cast<SkGroup*>(base + L.skp);
-  Tiling tiling{};
-  const int prc = plan_tiling(h, A, tiles, tp, ipart, st, &tiling);
-  if (prc) return prc;
-  const int32_t ntiles = tiling.ntiles;
-  const int Gp = tiling.grid;
-  SFG_HIP(launch_init_ctl(ctl, 1, 0, s, 1e15, 1.0, st));
-  SFG_HIP(launch_sketch_pack(A->n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu),
-                             (uint32_t)(seed >> 32), skp, st));
-  SpmvArgs a{};
-  a.n = A->n;
-  a.row_ptr = A->row_ptr;
-  a.col_idx = A->col_idx;
-  a.val = A->val;
-  a.tiles = tiles;
-  a.tp = tp;
-  a.ntiles = ntiles;
-  a.short_tiles = tiling.max_row <= kShortRow;
-  a.x = u;
-  a.scale_val = scale;
-  a.w = w;
-  a.s = s;
-  a.skp = skp;
-  a.zeta = zeta;
-  a.U = U;
-  a.ldu = ldu;
-  a.l0 = 0;
-  a.nwin = nwin;
-  a.part = part;
-  a.dpart = dpart;
-  a.ctl = ctl;
-  SFG_HIP(launch_spmv(kModePlain, false, Gp, a, sk_groups(zeta), st));
-  SFG_HIP(launch_reduce_slots(part, Gp, s, s, 0, 1, 1, 0, 0, red, ctl, false, st));
-  SFG_HIP(launch_sketch_out(red, s, 1.0 / sqrt((double)zeta), dpart, Gp, nwin, c, dots, norm2,
-                            st));
-  SFG_HIP(hipStreamSynchronize(st));
-  return SFGMRES_OK;
+  return sfg::spmv_sketch_impl(h, A, u, scale, w, s, zeta, seed, U, ldu, nwin, c, dots, norm2, ws,
+                               ws_bytes, stream);
 }
 
 }  // extern "C"

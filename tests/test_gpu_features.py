@@ -138,10 +138,12 @@ def test_ffom_iterate_bounds_and_delta(precision):
     xf_ref = ref.Z @ np.linalg.solve(ref.H[:J, :J], e1)
     assert np.linalg.norm(xf - xf_ref) <= 1e-9 * np.linalg.norm(xf_ref)
     hist_close(np.asarray(info["bound"]) / nb, np.asarray(ref.bound) / nb)
+    # (delta_j is built from the inner residuals ||v_j - A z_j||, compared
+    # at 1e-7 like them: a difference of nearby vectors)
     dr = np.asarray(ref.delta)
     assert np.array_equal(np.isnan(d), np.isnan(dr))
     ok = ~np.isnan(dr)
-    assert np.all(np.abs(d[ok] - dr[ok]) <= 1e-9 * dr[ok])
+    assert np.all(np.abs(d[ok] - dr[ok]) <= 1e-7 * dr[ok])
 
 
 def test_phase_timers():
