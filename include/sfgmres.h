@@ -303,6 +303,25 @@ int sfgmres_spmv_sketch(sfgmres_handle h, const sfgmres_csr* A, const double* u,
                         int64_t ldu, int32_t nwin, double* c, double* dots, double* norm2,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* Allocation-free variant of sfgmres_spmv_sketch, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): the same kernels and results (bit for
+ * bit), with no workspace argument.  Its workspace is a static device array
+ * of sfgmres_noalloc_scratch_bytes (64 MiB) that every GPU the library runs
+ * on holds until the process ends; problems whose workspace
+ * (sfgmres_spmv_workspace_bytes) exceeds it are rejected with
+ * SFGMRES_ERR_WORKSPACE before any launch.  The call allocates nothing
+ * (no hipMalloc or hipFree, no allocating library routine).  Every call on
+ * one GPU shares that GPU's array: calls that overlap on one GPU (other
+ * streams or host threads) race and must be serialised by the caller.
+ * Arguments, layouts and the other return codes as sfgmres_spmv_sketch; the
+ * handle's device must be current. */
+int sfgmres_noalloc_scratch_bytes(size_t* bytes);
+int sfgmres_spmv_sketch_noalloc(sfgmres_handle h, const sfgmres_csr* A, const double* u,
+                                double scale, double* w, int32_t s, int32_t zeta, uint64_t seed,
+                                const double* U, int64_t ldu, int32_t nwin, double* c,
+                                double* dots, double* norm2, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

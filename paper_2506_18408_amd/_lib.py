@@ -130,6 +130,11 @@ SIGNATURES = {
                                       C.c_void_p, C.c_int32, C.c_int32, C.c_uint64, C.c_void_p,
                                       C.c_int64, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                       C.c_void_p, C.c_size_t, C.c_void_p]),
+    "sfgmres_noalloc_scratch_bytes": (C.c_int, [C.POINTER(C.c_size_t)]),
+    "sfgmres_spmv_sketch_noalloc": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_void_p, C.c_double,
+                                              C.c_void_p, C.c_int32, C.c_int32, C.c_uint64,
+                                              C.c_void_p, C.c_int64, C.c_int32, C.c_void_p,
+                                              C.c_void_p, C.c_void_p, C.c_void_p]),
 }
 
 _LIB = None
