@@ -110,7 +110,7 @@ def test_full_size_c3_mixed_vs_fp64(c3):
     # the measured difference (relative to the FP64 solution) with a margin
     rel = diff / np.linalg.norm(x64.cpu().numpy())
     print(f"power-law 1M: mixed vs FP64 solution, relative difference {rel:.3e}")
-    assert rel <= 1e-6
+    assert rel <= 1e-7   # (measured 1.5e-8 on MI355X)
 
 
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
@@ -264,4 +264,4 @@ def test_full_size_c5_fp64_first_step_and_mixed_error():
     assert i64["converged"] and im["converged"]
     err = (torch.linalg.norm(xm - x64) / torch.linalg.norm(x64)).item()
     print(f"256^3: mixed vs FP64 solution, relative difference {err:.3e}")
-    assert err <= 1e-5
+    assert err <= 5e-6   # (measured 6.1e-7 on MI355X)

@@ -59,7 +59,9 @@ def test_ilu_preconditioned_solve_matches_the_oracle(name, t):
                          c2_rule="exact", **prm)
     kap = np.maximum(np.asarray(info["cond_at_stop"]), np.asarray(ref.cond_at_stop))
     p = int(np.argmax(kap > KAPPA_STRICT)) if (kap > KAPPA_STRICT).any() else info["outer_iters"]
-    assert list(info["inner_k"]) == free.inner_k
+    # (decisions agree up to the first ill-conditioned cycle, whose y, and
+    # so everything after it, is determined only to about u kappa)
+    assert list(info["inner_k"][:p + 1]) == free.inner_k[:p + 1]
     hist_close(info["residual_history"][:p + 1], ref.residual_history[:p + 1])
     hist_close(info["true_residual_history"][:p], ref.true_residual_history[:p], atol=1e-13)
     if p == info["outer_iters"]:
