@@ -76,6 +76,8 @@ extern "C" {
 #define SFGMRES_STOP_C3         3  /* predicted outer residual <= tol * ||b||     */
 #define SFGMRES_STOP_BREAKDOWN  4  /* truncated Arnoldi produced an exact zero     */
 #define SFGMRES_STOP_FORCED     5  /* k replayed from sfgmres_info.forced_k        */
+#define SFGMRES_STOP_MID        6  /* two-level FGMRES: inner_k holds the lower
+                                      level's outer steps                         */
 
 /* Limits checked by every entry point. */
 #define SFGMRES_MAX_ZETA   16     /* nonzeros per sketch column                   */
@@ -134,7 +136,15 @@ typedef struct sfgmres_options {
                                    adjoint).  SFGMRES_ERR_INVALID for unsorted columns or a
                                    missing diagonal entry, SFGMRES_ERR_BREAKDOWN for a zero
                                    pivot                                                          */
-  int32_t reserved[1];
+  int32_t mid_outer;            /* 0 (default): one sGMRES cycle per outer step.  N > 0: two-level
+                                   FGMRES (Section 5's multi-level FGMRES): z_j is the result of a
+                                   lower-level FGMRES solve of A z = v_j (zero initial guess, the
+                                   same sGMRES cycles, preconditioner and precision) of at most N
+                                   outer steps, which stops once eq. (2.2) predicts the top-level
+                                   tolerance: ||r~_{j-1}|| ||v_j - A z|| <= tol ||b||.  The
+                                   workspace then also holds the lower level's.  FGMRES outer only;
+                                   info.inner_k[j] = the lower level's outer steps,
+                                   info.total_inner = all sGMRES inner steps                     */
 } sfgmres_options;
 
 /* Solve diagnostics.  Scalars are always written; each per-step array is a
@@ -258,6 +268,25 @@ int sfgmres_transpose_workspace_bytes(int64_t n, int64_t nnz, size_t* bytes);
 int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t,
                       int32_t* col_idx_t, double* val_t, int32_t* perm, void* ws,
                       size_t ws_bytes, void* stream);
+
+/* Matrix powers for the t = 0 basis (Section 5: precomputing a few powers
+ * A, A^2, ..., A^p, which the t = 0 variant can do since its basis needs no
+ * inner products): Y[:, l-1] = A^l u for l = 1..p (p <= 8), with
+ * C[:, l-1] = S A^l u (the s sketch rows, S as in sfgmres_sketch_materialize)
+ * and norm2[l-1] = ||A^l u||^2.  The rows are split into slabs of at least
+ * the matrix bandwidth max |i - j| (and at least slab_rows; 0 = a default
+ * that keeps about 160 MB between a slab's first and last level) and one
+ * launch computes slab tau - 2(l-1) of every level l, so each slab of A is
+ * read p times within a few launches (from the last-level cache after the
+ * first).  u, Y (n x p, column-major, leading dimension ldy >= n), C (s x p),
+ * norm2 [p]: device arrays.  A test and measurement export; needs
+ * sfgmres_powers_workspace_bytes of workspace. */
+int sfgmres_powers_workspace_bytes(int64_t n, int64_t nnz, int32_t p, int32_t s, int32_t zeta,
+                                   size_t* bytes);
+int sfgmres_matrix_powers(sfgmres_handle h, const sfgmres_csr* A, const double* u, int32_t p,
+                          int32_t s, int32_t zeta, uint64_t seed, int64_t slab_rows, double* Y,
+                          int64_t ldy, double* C, double* norm2, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* The zero-fill ILU factorisation that SFGMRES_PRECOND_ILU0 builds (Section
  * 4.4's right preconditioner), as a test export: lu [nnz] receives the

@@ -169,12 +169,20 @@ class RightPreconditioned:
 def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
             cond_threshold=1e15, c2_rule="ice", forced_k=None, sketch=None,
             record_true_residual=True, trace=False, keep_basis=False,
-            precond=None) -> OracleResult:
+            precond=None, mid_outer=0) -> OracleResult:
     """FGMRES (Algorithm 1) preconditioned by one sGMRES cycle per step.
 
     precond (an object with .solve(r) = M^{-1} r, e.g. oracle.ilu.ILU0):
     right preconditioning; the inner cycle solves A M^{-1} u = v_j and the
-    outer step takes z_j = M^{-1} u, so Algorithm 1 keeps A and b - A x."""
+    outer step takes z_j = M^{-1} u, so Algorithm 1 keeps A and b - A x.
+
+    mid_outer > 0: two-level FGMRES (Section 5's multi-level FGMRES): z_j is
+    the result of a lower-level FGMRES solve of A z = v_j (zero initial
+    guess, the same sGMRES cycles as its preconditioner) run for at most
+    mid_outer steps; it stops early once eq. (2.2) predicts the top-level
+    tolerance, i.e. when ||r~_{j-1}|| times its own residual is below
+    tol ||b||.  The entries of inner_k are then the lower level's outer
+    steps."""
     A = sp.csr_matrix(A) if not sp.issparse(A) and not hasattr(A, "__matmul__") else A
     b = np.asarray(b, dtype=np.float64)
     n = b.shape[0]
@@ -215,11 +223,22 @@ def sfgmres(A, b, x0=None, *, m, t, s, zeta, tol, seed, max_outer=100,
         tr = [] if trace else None
         fk = None if forced_k is None else int(forced_k[j])
         A_in = A if precond is None else RightPreconditioned(A, precond)
-        z, info = sgmres_cycle(A_in, V[j], sketch, m=m, t=t, tol_abs=tol * nb, factor=factor,
-                               cond_threshold=cond_threshold, c2_rule=c2_rule, forced_k=fk,
-                               trace=tr)
-        if precond is not None:
-            z = precond.solve(z)                      # z_j = M^{-1} B_k y_k
+        if mid_outer > 0:
+            # the lower level: FGMRES on A z = v_j (||v_j|| = 1), tolerance
+            # relative to 1 chosen so that factor * ||v_j - A z|| <= tol ||b||
+            low = sfgmres(A, V[j], m=m, t=t, s=s, zeta=zeta,
+                          tol=tol * nb / factor if math.isfinite(factor) else tol * nb,
+                          seed=seed, max_outer=mid_outer, cond_threshold=cond_threshold,
+                          c2_rule=c2_rule, sketch=sketch, record_true_residual=False,
+                          precond=precond)
+            z = low.x
+            info = dict(k=low.outer_iters, reason="mid", cond=math.nan, rho_hat=math.nan)
+        else:
+            z, info = sgmres_cycle(A_in, V[j], sketch, m=m, t=t, tol_abs=tol * nb,
+                                   factor=factor, cond_threshold=cond_threshold,
+                                   c2_rule=c2_rule, forced_k=fk, trace=tr)
+            if precond is not None:
+                z = precond.solve(z)                  # z_j = M^{-1} B_k y_k
         Z.append(z)
         w = A @ z
         rhat = float(np.linalg.norm(V[j] - w))

@@ -5,6 +5,7 @@ include/sfgmres.h, with a PyTorch binding and an adjoint for autograd."""
 from .api import (  # noqa: F401
     SFGMRESError,
     ilu0,
+    matrix_powers,
     SolveParams,
     release_workspaces,
     sketch_apply,

@@ -26,7 +26,7 @@ MIXED = 1
 PRECOND_NONE = 0
 PRECOND_ILU0 = 1
 
-STOP_REASONS = {1: "C1", 2: "C2", 3: "C3", 4: "breakdown", 5: "forced"}
+STOP_REASONS = {1: "C1", 2: "C2", 3: "C3", 4: "breakdown", 5: "forced", 6: "mid"}
 
 PHASES = ("setup", "inner", "cycle_end", "outer", "true_residuals", "final", "transpose",
           "gradient")
@@ -61,7 +61,7 @@ class Options(C.Structure):
         ("identity_sketch", C.c_int32),
         ("phase_timers", C.c_int32),
         ("precond", C.c_int32),
-        ("reserved", C.c_int32 * 1),
+        ("mid_outer", C.c_int32),
     ]
 
 
@@ -116,6 +116,12 @@ SIGNATURES = {
     "sfgmres_sketch_materialize": (C.c_int, [C.c_void_p, C.c_int64, C.c_int32, C.c_int32,
                                              C.c_uint64, C.c_void_p, C.c_void_p, C.c_void_p,
                                              C.c_size_t, C.c_void_p]),
+    "sfgmres_powers_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.c_int32, C.c_int32,
+                                                 C.c_int32, C.POINTER(C.c_size_t)]),
+    "sfgmres_matrix_powers": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_void_p, C.c_int32,
+                                        C.c_int32, C.c_int32, C.c_uint64, C.c_int64, C.c_void_p,
+                                        C.c_int64, C.c_void_p, C.c_void_p, C.c_void_p, C.c_size_t,
+                                        C.c_void_p]),
     "sfgmres_ilu_workspace_bytes": (C.c_int, [C.c_int64, C.c_int64, C.POINTER(C.c_size_t)]),
     "sfgmres_ilu0": (C.c_int, [C.c_void_p, C.POINTER(Csr), C.c_void_p, C.c_void_p, C.c_void_p,
                                C.c_size_t, C.c_void_p]),

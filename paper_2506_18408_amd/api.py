@@ -40,7 +40,8 @@ class SolveParams:
     option: needs s == n and zeta == 1; the inner cycle is then GMRES(k));
     phase_timers: per-phase GPU times into info["phase_ms"]; precond: "none"
     or "ilu0" (zero-fill ILU right preconditioning in a multicolour order,
-    FGMRES outer only).
+    FGMRES outer only); mid_outer: N > 0 for two-level FGMRES, each outer
+    step preconditioned by a lower-level FGMRES solve of at most N steps.
     """
     m: int = 30
     t: int = 2
@@ -57,6 +58,7 @@ class SolveParams:
     identity_sketch: bool = False
     phase_timers: bool = False
     precond: str = "none"
+    mid_outer: int = 0
 
 
 _HANDLES = {}
@@ -141,6 +143,7 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.identity_sketch = 1 if p.identity_sketch else 0
     o.phase_timers = 1 if p.phase_timers else 0
     o.precond = {"none": L.PRECOND_NONE, "ilu0": L.PRECOND_ILU0}[p.precond]
+    o.mid_outer = p.mid_outer
     return o
 
 
@@ -313,6 +316,26 @@ def transpose(row_ptr, col_idx, val=None):
                                       _stream()), h)
     nnz = A.nnz
     return rp_t, col_t[:nnz], (val_t[:nnz] if val_t is not None else None), perm[:nnz]
+
+
+def matrix_powers(row_ptr, col_idx, val, u, p, s, zeta, seed, slab_rows=0):
+    """(Y [n, p], C [s, p], norm2 [p]): Y[:, l-1] = A^l u, C[:, l-1] its
+    sketch, norm2 its squared norm (the t = 0 basis before normalisation)."""
+    A = _csr(row_ptr, col_idx, val)
+    dev = row_ptr.device
+    check_vector("u", u, A.n, dev)
+    Y = torch.empty(p, A.n, dtype=torch.float64, device=dev)   # column l-1 = row of Y
+    Cs = torch.empty(p, s, dtype=torch.float64, device=dev)
+    nrm = torch.empty(p, dtype=torch.float64, device=dev)
+    need = C.c_size_t()
+    _check(L.load().sfgmres_powers_workspace_bytes(A.n, A.nnz, p, s, zeta, C.byref(need)), None)
+    ws = _workspace(need.value, dev, "powers")
+    h = _handle(dev)
+    _check(L.load().sfgmres_matrix_powers(h, C.byref(A), u.data_ptr(), p, s, zeta,
+                                          seed & (2**64 - 1), slab_rows, Y.data_ptr(), A.n,
+                                          Cs.data_ptr(), nrm.data_ptr(), ws.data_ptr(),
+                                          ws.numel(), _stream()), h)
+    return Y.t(), Cs.t(), nrm
 
 
 def ilu0(row_ptr, col_idx, val):

@@ -129,7 +129,7 @@ struct HostStatus {
 struct Layout {
   size_t ctl, tiles, tp, ipart, part, dpart, vpart, red, skp, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z,
       sigma, hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, ilu, ilu_t64, ilu_tmp,
-      at_rowptr, at_col, at_val, at_perm, at_cursor, scan_tmp, total;
+      mid, mid_bytes, at_rowptr, at_col, at_val, at_perm, at_cursor, scan_tmp, total;
   int64_t ld;        // leading dimension (elements) of the n-vectors
   int64_t ntiles_max;
   int32_t grid;      // persistent grid size used for the partial buffer

@@ -16,6 +16,22 @@ enum SpmvMode : int {
   kModeTrueRes = 3,  // ||b - A x||^2
   kModePlain = 4,    // as kModeInner with a scale, without predication (test export)
   kModeRestart = 5,  // finisher only: beta = ||b - A x|| of a restart (kModeResid SpMV)
+  kModePowers = 6,   // matrix powers: y_l = A y_{l-1} on one slab of rows per task group
+};
+
+// Matrix powers (kModePowers): the grid is split into ptasks groups of
+// workgroups; group l computes the rows of one slab of y_{l+1} = A y_l (its
+// tiles [tile0, tile0 + ntiles)), when active, and adds its sketch and
+// squared-norm partials to the rows of its level (overwriting them when
+// `first`, the level's first slab).
+constexpr int kMaxPowTasks = 8;
+struct PowTask {
+  int32_t tile0, ntiles;
+  int32_t active, first;
+  const void* x;
+  void* w;
+  double* part;    // the level's sketch partial rows (one per workgroup of the group)
+  double* dpart;   // the level's scalar partial rows
 };
 
 struct SpmvArgs {
@@ -53,6 +69,9 @@ struct SpmvArgs {
   const double* sig_part;
   int32_t sig_G, sig_step;
   double* sig_out;
+  // kModePowers
+  int32_t ptasks;
+  PowTask ptask[kMaxPowTasks];
 };
 constexpr int kSigLoads = 4;
 static_assert(kSpmvGrid <= kWave * kSigLoads, "sig_part rows per lane");
@@ -67,6 +86,8 @@ hipError_t launch_tiles(const int32_t* row_ptr, int64_t n, int32_t wt, int32_t r
                         int32_t* tiles, int32_t* tp, int32_t ntiles, hipStream_t st);
 hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, int32_t* out,
                              hipStream_t st);
+hipError_t launch_max_bandwidth(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,
+                                int32_t* part, int32_t* out, hipStream_t st);
 // Waves per SpMV workgroup for an s-row sketch (0: none), bounded by LDS.
 int spmv_waves(int s, bool short_tiles);
 // zb = sk_groups(zeta) with a sketch, else 0.  ev0/ev1 non-null: the launch

@@ -98,7 +98,8 @@ IluWs ilu_regions(int64_t n, int64_t nnz, size_t off) {
 }
 
 Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
-                   int32_t J, int32_t precision, int32_t adjoint, int32_t panel, int32_t precond) {
+                   int32_t J, int32_t precision, int32_t adjoint, int32_t panel, int32_t precond,
+                   int32_t mid_outer) {
   (void)t;
   Layout L{};
   const bool f32 = precision == SFGMRES_MIXED;
@@ -156,6 +157,12 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   if (ilu) off = ilu_regions(n, nnz, off).total;
   L.ilu_t64 = take(ilu ? (size_t)L.ld * 8 : 0);
   L.ilu_tmp = take(ilu ? (size_t)L.ld * vt : 0);
+  // two-level FGMRES: the lower level's whole solve workspace
+  L.mid_bytes = mid_outer > 0
+                    ? make_layout(n, nnz, m, t, s, zeta, mid_outer, precision, 0, panel, precond, 0)
+                          .total
+                    : 0;
+  L.mid = take(L.mid_bytes);
   if (adjoint) {
     L.at_rowptr = take((size_t)(n + 1) * 4);
     L.at_col = take((size_t)nnz * 4);
@@ -200,6 +207,7 @@ sfgmres_options defaults() {
   o.panel = 0;
   o.outer = SFGMRES_OUTER_FGMRES;
   o.precond = SFGMRES_PRECOND_NONE;
+  o.mid_outer = 0;
   return o;
 }
 
@@ -242,6 +250,10 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
     return fail(h, SFGMRES_ERR_INVALID, "precond must be SFGMRES_PRECOND_NONE or _ILU0");
   if (o.precond != SFGMRES_PRECOND_NONE && o.outer != SFGMRES_OUTER_FGMRES)
     return fail(h, SFGMRES_ERR_INVALID, "precond needs the FGMRES outer iteration");
+  if (o.mid_outer < 0 || o.mid_outer > SFGMRES_MAX_OUTER)
+    return fail(h, SFGMRES_ERR_INVALID, "need 0 <= mid_outer <= 2000");
+  if (o.mid_outer > 0 && o.outer != SFGMRES_OUTER_FGMRES)
+    return fail(h, SFGMRES_ERR_INVALID, "mid_outer needs the FGMRES outer iteration");
   return SFGMRES_OK;
 }
 
@@ -462,7 +474,8 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   if (!A->row_ptr || (nnz > 0 && (!A->col_idx || !A->val)) || !b || !x)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
   const int pc = panel_cols(o);
-  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0, pc, o.precond);
+  const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0, pc, o.precond,
+                               o.mid_outer);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   char* base = static_cast<char*>(ws);
@@ -548,7 +561,9 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int32_t ntiles = tiling.ntiles;
   const int Gp = tiling.grid;
   const int Gn = rows_grid(n);
-  const bool ilu = o.precond == SFGMRES_PRECOND_ILU0;
+  // (with a lower level, the preconditioner belongs to its sGMRES cycles)
+  const bool mid = o.mid_outer > 0;
+  const bool ilu = o.precond == SFGMRES_PRECOND_ILU0 && !mid;
   IluFactors F{};
   std::vector<int32_t> ilu_levels;
   double* ilu_t64 = reinterpret_cast<double*>(base + L.ilu_t64);
@@ -682,192 +697,217 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   bool conv = false;
   double rho_last = beta;
   int total_inner = 0;
+  double factor_host = beta;  // ||r~_{j-1}|| of eq. (2.2) (beta for j = 1)
   for (int j = 0; j < J; ++j) {
-    // inner sGMRES cycle: predicated steps, a decision launch per panel, a
-    // bounded lookahead
-    hsh->stop_k = 0;
-    hsh->inner_step_done = 0;
-    hsh->stop_step = 0;
-    hsh->steps_run = 0;
-    SFG_HIP(mark(kMarkCycle));
-    int panel0 = 0;  // first column of the open panel
-    for (int i = 0; i < m; ++i) {
-      if (i >= lookahead) {
-        const int need = i - lookahead + 1;
-        if (!spin_until(h, [&] { return hsh->stop_k != 0 || hsh->inner_step_done >= need ||
-                                        hsh->error != 0; })) {
-          return fail(h, SFGMRES_ERR_TIMEOUT, "device made no progress for 60 s");
-        }
-      }
-      if (hsh->stop_k != 0 || hsh->error != 0) break;
-      const int nwin = std::min(t, i + 1);
-      const int l0 = i + 1 - nwin;
-      // this step's ring slot was read by the reduction of the panel two
-      // panels back
-      if (i % pc == 0 && i >= nring) SFG_HIP(hipStreamWaitEvent(st, ev_red[i / pc - 2], 0));
-      SpmvArgs a = base_args;
-      a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
-      a.x = Bcol(i);
-      if (ilu) {
-        // the inner operator A M^{-1}: the SpMV reads M^{-1} u_i (the solves
-        // are predicated on the stop flag as the SpMV is)
-        SFG_HIP(launch_ilu_apply(f32, F, Bcol(i), ilu_t64, ilu_tmp, st, P.ctl));
-        a.x = ilu_tmp;
-      }
-      // t = 0: y = sigma_i A u_i = A b_i is the next (unnormalised) power-basis
-      // vector, sigma_i formed by the SpMV itself from the previous step's
-      // norm partials (sigma_0 is set with the cycle); t > 0: y = A u_i,
-      // scaled inside the Arnoldi update.  Scalar rows alternate between two
-      // buffers, so a step reads its predecessor's while writing its own.
-      double* const dcur = P.dpart + (int64_t)(i & 1) * kMaxGrid * kDP;
-      a.dpart = dcur;
-      a.scale_ptr = (t == 0 && i == 0) ? P.sigma : nullptr;
-      if (t == 0 && i > 0) {
-        a.sig_part = P.dpart + (int64_t)((i - 1) & 1) * kMaxGrid * kDP;
-        a.sig_G = Gp;
-        a.sig_step = i;
-        a.sig_out = P.sigma + i;
-      }
-      a.w = (t == 0) ? Bcol(i + 1) : (f32 ? static_cast<void*>(P.W32) : static_cast<void*>(P.W64));
-      a.s = s;
-      a.U = P.Bb;
-      a.ldu = ld;
-      a.l0 = l0;
-      a.nwin = nwin;
-      a.part = P.part + (int64_t)(i % nring) * slot_part;
-      const bool timed = o.profile > 0 && i % o.profile == o.profile - 1;
-      SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st, timed ? h->ev[2 * i] : nullptr,
-                          timed ? h->ev[2 * i + 1] : nullptr));
-      // t > 0: sigma and the window coefficients inside the Arnoldi update
-      // (norm partials alternate between two buffers), or a one-workgroup
-      // kernel at the cycle's last step; t = 0: nothing (the next SpMV
-      // forms sigma)
-      double* vprev = P.vpart + (int64_t)(i & 1) * kVecGrid;
-      double* vnext = P.vpart + (int64_t)((i + 1) & 1) * kVecGrid;
-      if (t > 0 && i + 1 < m) {
-        ArnoldiArgs aa{};
-        aa.n = n;
-        aa.W = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
-        aa.B = P.Bb;
-        aa.ldb = ld;
-        aa.l0 = l0;
-        aa.nwin = nwin;
-        aa.inext = i + 1;
-        aa.step = i;
-        aa.dpart = dcur;
-        aa.Gd = Gp;
-        aa.vprev = vprev;
-        aa.Gv = Ga;
-        aa.vnext = vnext;
-        aa.sigma = P.sigma;
-        aa.ctl = P.ctl;
-        SFG_HIP(launch_arnoldi_update(f32, Ga, aa, st));
-      } else if (t > 0) {
-        CoefArgs ca{};
-        ca.dpart = dcur;
-        ca.G = Gp;
-        ca.vpart = vprev;
-        ca.Gv = Ga;
-        ca.t = t;
-        ca.nwin = nwin;
-        ca.l0 = l0;
-        ca.step = i;
-        ca.ctl = P.ctl;
-        ca.sigma = P.sigma;
-        ca.coef = P.coef;
-        SFG_HIP(launch_coef(ca, st));
-      }
-      if (i + 1 - panel0 == pc || i + 1 == m) {
-        // the panel's reduction and decision on the decision stream, after
-        // its steps; the inner steps go on meanwhile (they read the stop
-        // flag at their start, so a decision seen late costs a discarded
-        // step, never a wrong result)
-        const int ncols = i + 1 - panel0;
-        const int pidx = panel0 / pc;
-        SFG_HIP(hipEventRecord(ev_steps[pidx], st));
-        SFG_HIP(hipStreamWaitEvent(h->dec, ev_steps[pidx], 0));
-        SFG_HIP(launch_reduce_slots(P.part, Gp, s, s, panel0 % nring, ncols, nring, slot_part,
-                                    slot_red, P.red, P.ctl, true, h->dec));
-        SFG_HIP(hipEventRecord(ev_red[pidx], h->dec));
-        QrBlockArgs q = qa;
-        q.k0 = panel0;
-        q.ncols = ncols;
-        q.pprev = panel0 > 0 ? pc : 0;  // every panel before the last is full
-        SFG_HIP(launch_qr_block(q, h->dec));
-        SFG_HIP(hipEventRecord(ev_dec, h->dec));
-        panel0 = i + 1;
-      }
-    }
-    // the cycle's last decision (and every earlier one) before its results
-    SFG_HIP(hipStreamWaitEvent(st, ev_dec, 0));
-    SFG_HIP(mark(kMarkDecided));
-    // z_j = B_k y_k
-    SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
-    if (restarted) {
-      // the cycle solved A z = r_j / beta_j: x <- x + beta_j z, then the new
-      // residual r_{j+1} = b - A x and beta_{j+1} (also the next C3 factor)
-      SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, x, x, st,
-                             &P.ctl->beta));
-      SpmvArgs a = base_args;
-      a.has_x = 1;
-      a.x = x;
-      a.w = P.W64;
-      a.b = b;
-      SFG_HIP(launch_spmv(kModeResid, false, Gp, a, 0, st));
-      SFG_HIP(launch_spmv_finish(kModeRestart, P.dpart, Gp, P.ctl, P.scal, hsd, st));
-      SFG_HIP(mark(kMarkZ));
-      SFG_HIP(hipStreamSynchronize(st));
-      SFG_HIP(add_phase(1, kMarkCycle, kMarkDecided));
-      SFG_HIP(add_phase(2, kMarkDecided, kMarkZ));
-      const int err = hsh->error;
-      const int kj = hsh->k;
-      beta_cur = hsh->beta;
-      J_done = j + 1;
-      total_inner += kj;
-      if (info) {
-        info->total_inner = total_inner;
-        if (info->residual_history) info->residual_history[j + 1] = beta_cur / nb;
-        if (info->inner_k) info->inner_k[j] = kj;
-        if (info->stop_reason) info->stop_reason[j] = hsh->stop_reason;
-        if (info->cond_at_stop) info->cond_at_stop[j] = hsh->cond;
-        if (info->inner_sketched_residual) info->inner_sketched_residual[j] = hsh->rho_hat;
-        if (info->inner_true_residual) info->inner_true_residual[j] = NAN;
-        if (info->ffom_residual) info->ffom_residual[j] = NAN;
-        if (info->true_residual_history) info->true_residual_history[j] = beta_cur / nb;
-      }
-      if (o.profile > 0) {
-        const int worked = std::min((int)hsh->steps_run, m);
-        for (int i = o.profile - 1; i < worked; i += o.profile) {
-          float ms = 0.f;
-          SFG_HIP(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
-          if (info) {
-            info->spmv_ms += ms;
-            info->spmv_launches += 1;
+    int mid_k = 0, mid_inner = 0;
+    if (mid) {
+      // two-level FGMRES (Section 5): z_j from a lower-level FGMRES solve of
+      // A z = v_j, at most mid_outer steps, stopped once eq. (2.2) predicts
+      // the top-level tolerance (its residual times ||r~_{j-1}|| below
+      // tol ||b||)
+      SFG_HIP(mark(kMarkCycle));
+      sfgmres_options om = o;
+      om.max_outer = o.mid_outer;
+      om.mid_outer = 0;
+      om.record_true_residual = 0;
+      om.profile = 0;
+      om.phase_timers = 0;
+      sfgmres_info mi;
+      memset(&mi, 0, sizeof(mi));
+      const double tol_mid = isfinite(factor_host) ? tol * nb / factor_host : tol * nb;
+      const int mrc = solve_impl(h, A, Vcol(j), nullptr, Zcol(j), m, t, s, zeta, tol_mid, seed,
+                                 om, &mi, base + L.mid, L.mid_bytes, st);
+      if (mrc < 0) return mrc;
+      mid_k = mi.outer_iters;
+      mid_inner = mi.total_inner;
+      SFG_HIP(mark(kMarkDecided));
+    } else {
+      // inner sGMRES cycle: predicated steps, a decision launch per panel, a
+      // bounded lookahead
+      hsh->stop_k = 0;
+      hsh->inner_step_done = 0;
+      hsh->stop_step = 0;
+      hsh->steps_run = 0;
+      SFG_HIP(mark(kMarkCycle));
+      int panel0 = 0;  // first column of the open panel
+      for (int i = 0; i < m; ++i) {
+        if (i >= lookahead) {
+          const int need = i - lookahead + 1;
+          if (!spin_until(h, [&] { return hsh->stop_k != 0 || hsh->inner_step_done >= need ||
+                                          hsh->error != 0; })) {
+            return fail(h, SFGMRES_ERR_TIMEOUT, "device made no progress for 60 s");
           }
         }
+        if (hsh->stop_k != 0 || hsh->error != 0) break;
+        const int nwin = std::min(t, i + 1);
+        const int l0 = i + 1 - nwin;
+        // this step's ring slot was read by the reduction of the panel two
+        // panels back
+        if (i % pc == 0 && i >= nring) SFG_HIP(hipStreamWaitEvent(st, ev_red[i / pc - 2], 0));
+        SpmvArgs a = base_args;
+        a.val = f32 ? static_cast<const void*>(P.val32) : static_cast<const void*>(A->val);
+        a.x = Bcol(i);
+        if (ilu) {
+          // the inner operator A M^{-1}: the SpMV reads M^{-1} u_i (the solves
+          // are predicated on the stop flag as the SpMV is)
+          SFG_HIP(launch_ilu_apply(f32, F, Bcol(i), ilu_t64, ilu_tmp, st, P.ctl));
+          a.x = ilu_tmp;
+        }
+        // t = 0: y = sigma_i A u_i = A b_i is the next (unnormalised) power-basis
+        // vector, sigma_i formed by the SpMV itself from the previous step's
+        // norm partials (sigma_0 is set with the cycle); t > 0: y = A u_i,
+        // scaled inside the Arnoldi update.  Scalar rows alternate between two
+        // buffers, so a step reads its predecessor's while writing its own.
+        double* const dcur = P.dpart + (int64_t)(i & 1) * kMaxGrid * kDP;
+        a.dpart = dcur;
+        a.scale_ptr = (t == 0 && i == 0) ? P.sigma : nullptr;
+        if (t == 0 && i > 0) {
+          a.sig_part = P.dpart + (int64_t)((i - 1) & 1) * kMaxGrid * kDP;
+          a.sig_G = Gp;
+          a.sig_step = i;
+          a.sig_out = P.sigma + i;
+        }
+        a.w = (t == 0) ? Bcol(i + 1) : (f32 ? static_cast<void*>(P.W32) : static_cast<void*>(P.W64));
+        a.s = s;
+        a.U = P.Bb;
+        a.ldu = ld;
+        a.l0 = l0;
+        a.nwin = nwin;
+        a.part = P.part + (int64_t)(i % nring) * slot_part;
+        const bool timed = o.profile > 0 && i % o.profile == o.profile - 1;
+        SFG_HIP(launch_spmv(kModeInner, f32, Gp, a, zb, st, timed ? h->ev[2 * i] : nullptr,
+                            timed ? h->ev[2 * i + 1] : nullptr));
+        // t > 0: sigma and the window coefficients inside the Arnoldi update
+        // (norm partials alternate between two buffers), or a one-workgroup
+        // kernel at the cycle's last step; t = 0: nothing (the next SpMV
+        // forms sigma)
+        double* vprev = P.vpart + (int64_t)(i & 1) * kVecGrid;
+        double* vnext = P.vpart + (int64_t)((i + 1) & 1) * kVecGrid;
+        if (t > 0 && i + 1 < m) {
+          ArnoldiArgs aa{};
+          aa.n = n;
+          aa.W = f32 ? static_cast<const void*>(P.W32) : static_cast<const void*>(P.W64);
+          aa.B = P.Bb;
+          aa.ldb = ld;
+          aa.l0 = l0;
+          aa.nwin = nwin;
+          aa.inext = i + 1;
+          aa.step = i;
+          aa.dpart = dcur;
+          aa.Gd = Gp;
+          aa.vprev = vprev;
+          aa.Gv = Ga;
+          aa.vnext = vnext;
+          aa.sigma = P.sigma;
+          aa.ctl = P.ctl;
+          SFG_HIP(launch_arnoldi_update(f32, Ga, aa, st));
+        } else if (t > 0) {
+          CoefArgs ca{};
+          ca.dpart = dcur;
+          ca.G = Gp;
+          ca.vpart = vprev;
+          ca.Gv = Ga;
+          ca.t = t;
+          ca.nwin = nwin;
+          ca.l0 = l0;
+          ca.step = i;
+          ca.ctl = P.ctl;
+          ca.sigma = P.sigma;
+          ca.coef = P.coef;
+          SFG_HIP(launch_coef(ca, st));
+        }
+        if (i + 1 - panel0 == pc || i + 1 == m) {
+          // the panel's reduction and decision on the decision stream, after
+          // its steps; the inner steps go on meanwhile (they read the stop
+          // flag at their start, so a decision seen late costs a discarded
+          // step, never a wrong result)
+          const int ncols = i + 1 - panel0;
+          const int pidx = panel0 / pc;
+          SFG_HIP(hipEventRecord(ev_steps[pidx], st));
+          SFG_HIP(hipStreamWaitEvent(h->dec, ev_steps[pidx], 0));
+          SFG_HIP(launch_reduce_slots(P.part, Gp, s, s, panel0 % nring, ncols, nring, slot_part,
+                                      slot_red, P.red, P.ctl, true, h->dec));
+          SFG_HIP(hipEventRecord(ev_red[pidx], h->dec));
+          QrBlockArgs q = qa;
+          q.k0 = panel0;
+          q.ncols = ncols;
+          q.pprev = panel0 > 0 ? pc : 0;  // every panel before the last is full
+          SFG_HIP(launch_qr_block(q, h->dec));
+          SFG_HIP(hipEventRecord(ev_dec, h->dec));
+          panel0 = i + 1;
+        }
       }
-      if (err) {
-        finish_info(err, J_done, false, beta_cur / nb, beta_cur / nb);
-        return fail(h, err,
-                    err == SFGMRES_ERR_BREAKDOWN ? "sketch of A v_j is zero (singular inner problem)"
-                                                 : "non-finite residual of a restart");
+      // the cycle's last decision (and every earlier one) before its results
+      SFG_HIP(hipStreamWaitEvent(st, ev_dec, 0));
+      SFG_HIP(mark(kMarkDecided));
+      // z_j = B_k y_k
+      SFG_HIP(launch_finalize(P.ctl, P.R, P.d, P.sigma, m, P.yin, st));
+      if (restarted) {
+        // the cycle solved A z = r_j / beta_j: x <- x + beta_j z, then the new
+        // residual r_{j+1} = b - A x and beta_{j+1} (also the next C3 factor)
+        SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, x, x, st,
+                               &P.ctl->beta));
+        SpmvArgs a = base_args;
+        a.has_x = 1;
+        a.x = x;
+        a.w = P.W64;
+        a.b = b;
+        SFG_HIP(launch_spmv(kModeResid, false, Gp, a, 0, st));
+        SFG_HIP(launch_spmv_finish(kModeRestart, P.dpart, Gp, P.ctl, P.scal, hsd, st));
+        SFG_HIP(mark(kMarkZ));
+        SFG_HIP(hipStreamSynchronize(st));
+        SFG_HIP(add_phase(1, kMarkCycle, kMarkDecided));
+        SFG_HIP(add_phase(2, kMarkDecided, kMarkZ));
+        const int err = hsh->error;
+        const int kj = hsh->k;
+        beta_cur = hsh->beta;
+        J_done = j + 1;
+        total_inner += kj;
+        if (info) {
+          info->total_inner = total_inner;
+          if (info->residual_history) info->residual_history[j + 1] = beta_cur / nb;
+          if (info->inner_k) info->inner_k[j] = kj;
+          if (info->stop_reason) info->stop_reason[j] = hsh->stop_reason;
+          if (info->cond_at_stop) info->cond_at_stop[j] = hsh->cond;
+          if (info->inner_sketched_residual) info->inner_sketched_residual[j] = hsh->rho_hat;
+          if (info->inner_true_residual) info->inner_true_residual[j] = NAN;
+          if (info->ffom_residual) info->ffom_residual[j] = NAN;
+          if (info->true_residual_history) info->true_residual_history[j] = beta_cur / nb;
+        }
+        if (o.profile > 0) {
+          const int worked = std::min((int)hsh->steps_run, m);
+          for (int i = o.profile - 1; i < worked; i += o.profile) {
+            float ms = 0.f;
+            SFG_HIP(hipEventElapsedTime(&ms, h->ev[2 * i], h->ev[2 * i + 1]));
+            if (info) {
+              info->spmv_ms += ms;
+              info->spmv_launches += 1;
+            }
+          }
+        }
+        if (err) {
+          finish_info(err, J_done, false, beta_cur / nb, beta_cur / nb);
+          return fail(h, err,
+                      err == SFGMRES_ERR_BREAKDOWN ? "sketch of A v_j is zero (singular inner problem)"
+                                                   : "non-finite residual of a restart");
+        }
+        if (beta_cur <= tol * nb) {
+          conv = true;
+          break;
+        }
+        // v_{j+1} = r_{j+1} / beta_{j+1}, its copy as the next cycle's b_1, S v
+        rc = sketch_v_and_init(P.W64, &P.ctl->beta, Vcol(0),
+                               (forced && j + 1 < J) ? forced[j + 1] : 0);
+        if (rc) return rc;
+        continue;
       }
-      if (beta_cur <= tol * nb) {
-        conv = true;
-        break;
+      if (ilu) {
+        // z_j = M^{-1} B_k y_k
+        SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, P.W64, st));
+        SFG_HIP(launch_ilu_apply(false, F, P.W64, ilu_t64, Zcol(j), st));
+      } else {
+        SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
       }
-      // v_{j+1} = r_{j+1} / beta_{j+1}, its copy as the next cycle's b_1, S v
-      rc = sketch_v_and_init(P.W64, &P.ctl->beta, Vcol(0),
-                             (forced && j + 1 < J) ? forced[j + 1] : 0);
-      if (rc) return rc;
-      continue;
-    }
-    if (ilu) {
-      // z_j = M^{-1} B_k y_k
-      SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, P.W64, st));
-      SFG_HIP(launch_ilu_apply(false, F, P.W64, ilu_t64, Zcol(j), st));
-    } else {
-      SFG_HIP(launch_combine(f32, n, P.Bb, ld, P.yin, &P.ctl->stop_k, 0, nullptr, Zcol(j), st));
     }
     SFG_HIP(mark(kMarkZ));
     // w = A z_j with h_{1,j}; modified Gram-Schmidt; Givens
@@ -899,11 +939,12 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     SFG_HIP(add_phase(2, kMarkDecided, kMarkZ));
     SFG_HIP(add_phase(3, kMarkZ, kMarkOuter));
     const int err = hsh->error;
-    const int kj = hsh->k;
+    const int kj = mid ? mid_k : hsh->k;
     const double rho = hsh->rho;
+    factor_host = hsh->ffom;
     J_done = j + 1;
-    total_inner += kj;
-    if (o.profile > 0) {
+    total_inner += mid ? mid_inner : kj;
+    if (o.profile > 0 && !mid) {
       const int worked = std::min((int)hsh->steps_run, m);
       for (int i = o.profile - 1; i < worked; i += o.profile) {
         float ms = 0.f;
@@ -918,9 +959,10 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       info->total_inner = total_inner;
       if (info->residual_history) info->residual_history[j + 1] = rho / nb;
       if (info->inner_k) info->inner_k[j] = kj;
-      if (info->stop_reason) info->stop_reason[j] = hsh->stop_reason;
-      if (info->cond_at_stop) info->cond_at_stop[j] = hsh->cond;
-      if (info->inner_sketched_residual) info->inner_sketched_residual[j] = hsh->rho_hat;
+      if (info->stop_reason) info->stop_reason[j] = mid ? SFGMRES_STOP_MID : hsh->stop_reason;
+      if (info->cond_at_stop) info->cond_at_stop[j] = mid ? NAN : hsh->cond;
+      if (info->inner_sketched_residual)
+        info->inner_sketched_residual[j] = mid ? NAN : hsh->rho_hat;
       if (info->inner_true_residual) info->inner_true_residual[j] = hsh->rhat_true;
       if (info->ffom_residual) info->ffom_residual[j] = hsh->ffom;
       if (info->bound) info->bound[j] = hsh->bound;
@@ -994,6 +1036,33 @@ SmallLayout small_layout(int64_t n, int64_t nnz, int32_t s, int32_t zeta) {
   L.part = take((size_t)kMaxGrid * s * 8);
   L.dpart = take((size_t)kMaxGrid * kDP * 8);
   L.red = take((size_t)s * 8);
+  L.skp = take(packed_sketch_bytes(n, zeta));
+  L.total = off;
+  return L;
+}
+
+// Workspace of the matrix-powers export: as the fused-SpMV export, with a
+// group of partial rows per level.
+struct PowersLayout {
+  size_t ctl, tiles, tp, ipart, part, dpart, red, skp, total;
+};
+
+PowersLayout powers_layout(int64_t n, int64_t nnz, int32_t p, int32_t s, int32_t zeta) {
+  PowersLayout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  L.ctl = take(sizeof(DevCtl));
+  const size_t ntiles_max = (size_t)(n / kRowTile + nnz / kTileNnz + 3);
+  L.tiles = take((ntiles_max + 1) * 4);
+  L.tp = take((ntiles_max + 1) * 4);
+  L.ipart = take((size_t)(kVecGrid + 1) * 4);
+  L.part = take((size_t)kSpmvGrid * s * 8);  // p groups of kSpmvGrid / p rows
+  L.dpart = take((size_t)kSpmvGrid * kDP * 8);
+  L.red = take((size_t)p * s * 8);
   L.skp = take(packed_sketch_bytes(n, zeta));
   L.total = off;
   return L;
@@ -1091,7 +1160,7 @@ int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_
       o.lookahead < 0 || o.lookahead > 64 || o.panel < 0 || o.panel > kPanel)
     return SFGMRES_ERR_INVALID;
   *bytes = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, adjoint ? 1 : 0,
-                       panel_cols(o), o.precond)
+                       panel_cols(o), o.precond, o.mid_outer)
                .total;
   return SFGMRES_OK;
 }
@@ -1173,7 +1242,7 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   if ((A->nnz > 0 && (!A->col_idx || !A->val)) || !g || !lambda)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
   const Layout L = make_layout(A->n, A->nnz, m, t, s, zeta, o.max_outer, o.precision, 1,
-                               panel_cols(o), o.precond);
+                               panel_cols(o), o.precond, o.mid_outer);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);
@@ -1247,6 +1316,109 @@ int sfgmres_transpose(sfgmres_handle h, const sfgmres_csr* A, int32_t* row_ptr_t
   int32_t* scan_tmp = reinterpret_cast<int32_t*>(base + align256((size_t)(A->n + 1) * 4));
   SFG_HIP(launch_transpose(A->row_ptr, A->col_idx, A->val, A->n, A->nnz, row_ptr_t, col_idx_t,
                            val_t, perm, cursor, scan_tmp, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  return SFGMRES_OK;
+}
+
+int sfgmres_powers_workspace_bytes(int64_t n, int64_t nnz, int32_t p, int32_t s, int32_t zeta,
+                                   size_t* bytes) {
+  if (!bytes || nnz < 0 || nnz >= ((int64_t)1 << 31) || p < 1 || p > kMaxPowTasks ||
+      !sketch_args_ok(n, s, zeta))
+    return SFGMRES_ERR_INVALID;
+  *bytes = powers_layout(n, nnz, p, s, zeta).total;
+  return SFGMRES_OK;
+}
+
+int sfgmres_matrix_powers(sfgmres_handle h, const sfgmres_csr* A, const double* u, int32_t p,
+                          int32_t s, int32_t zeta, uint64_t seed, int64_t slab_rows, double* Y,
+                          int64_t ldy, double* C, double* norm2, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!h) return SFGMRES_ERR_INVALID;
+  h->err.clear();
+  if (!A || !A->row_ptr || !u || !Y || !C || !norm2 || (A->nnz > 0 && (!A->col_idx || !A->val)))
+    return fail(h, SFGMRES_ERR_INVALID, "null array argument");
+  size_t need = 0;
+  if (sfgmres_powers_workspace_bytes(A->n, A->nnz, p, s, zeta, &need) != SFGMRES_OK ||
+      ldy < A->n || slab_rows < 0)
+    return fail(h, SFGMRES_ERR_INVALID, "invalid sizes (need 1 <= p <= 8, ldy >= n)");
+  if (!ws || ws_bytes < need || (reinterpret_cast<uintptr_t>(ws) & 255))
+    return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
+  const int64_t n = A->n;
+  hipStream_t st = static_cast<hipStream_t>(stream);
+  char* base = static_cast<char*>(ws);
+  const PowersLayout L = powers_layout(n, A->nnz, p, s, zeta);
+  DevCtl* ctl = reinterpret_cast<DevCtl*>(base + L.ctl);
+  int32_t* tiles = reinterpret_cast<int32_t*>(base + L.tiles);
+  int32_t* tp = reinterpret_cast<int32_t*>(base + L.tp);
+  int32_t* ipart = reinterpret_cast<int32_t*>(base + L.ipart);
+  double* part = reinterpret_cast<double*>(base + L.part);
+  double* dpart = reinterpret_cast<double*>(base + L.dpart);
+  double* red = reinterpret_cast<double*>(base + L.red);
+  SkGroup* skp = reinterpret_cast<SkGroup*>(base + L.skp);
+  Tiling tiling{};
+  int rc = plan_tiling(h, A, tiles, tp, ipart, st, &tiling);
+  if (rc) return rc;
+  // bandwidth: level l+1 of a slab reads level l within that many rows
+  int32_t bw = 0;
+  SFG_HIP(launch_max_bandwidth(A->row_ptr, A->col_idx, n, ipart, ipart + kVecGrid, st));
+  SFG_HIP(hipMemcpyAsync(&bw, ipart + kVecGrid, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  std::vector<int32_t> trow(tiling.ntiles + 1);
+  SFG_HIP(hipMemcpyAsync(trow.data(), tiles, trow.size() * 4, hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipStreamSynchronize(st));
+  // slabs: consecutive tiles with at least max(bw, slab_rows) rows each
+  // (default: about 160 MB of matrix and vectors in flight between a
+  // slab's first and last level, so its rows stay in the last-level cache)
+  const double row_bytes = 12.0 * (double)A->nnz / (double)n + 16.0;
+  int64_t want = slab_rows;
+  if (want == 0)
+    want = p > 1 ? (int64_t)(160e6 / (2.0 * p * (p - 1)) / row_bytes) : n;
+  want = std::max<int64_t>({want, (int64_t)bw, 1});
+  std::vector<int32_t> slab{0};  // first tile of each slab
+  for (int t = 1; t < tiling.ntiles; ++t)
+    if (trow[t] - trow[slab.back()] >= want) slab.push_back(t);
+  slab.push_back(tiling.ntiles);
+  if (slab.size() > 2 && trow[tiling.ntiles] - trow[slab[slab.size() - 2]] < bw)
+    slab.erase(slab.end() - 2);  // (a short last slab joins its neighbour)
+  const int K = (int)slab.size() - 1;
+  SFG_HIP(launch_sketch_pack(n, s, zeta, (uint32_t)(seed & 0xFFFFFFFFu), (uint32_t)(seed >> 32),
+                             skp, st));
+  // launch tau computes slab tau - 2 l of level l+1: its inputs (level l on
+  // the slab and its two neighbours) were finished by earlier launches
+  const int gp = std::max(1, tiling.grid / p);
+  SpmvArgs a{};
+  a.n = n;
+  a.row_ptr = A->row_ptr;
+  a.col_idx = A->col_idx;
+  a.val = A->val;
+  a.tiles = tiles;
+  a.tp = tp;
+  a.ntiles = tiling.ntiles;
+  a.short_tiles = tiling.max_row <= kShortRow;
+  a.s = s;
+  a.skp = skp;
+  a.zeta = zeta;
+  a.ctl = ctl;
+  a.ptasks = p;
+  for (int tau = 0; tau < K + 2 * (p - 1); ++tau) {
+    for (int l = 0; l < p; ++l) {
+      const int k = tau - 2 * l;
+      PowTask& T = a.ptask[l];
+      T.active = (k >= 0 && k < K) ? 1 : 0;
+      T.first = k == 0 ? 1 : 0;
+      T.tile0 = T.active ? slab[k] : 0;
+      T.ntiles = T.active ? slab[k + 1] - slab[k] : 0;
+      T.x = l == 0 ? static_cast<const void*>(u) : static_cast<const void*>(Y + (l - 1) * ldy);
+      T.w = Y + l * ldy;
+      T.part = part + (int64_t)l * gp * s;
+      T.dpart = dpart + (int64_t)l * gp * kDP;
+    }
+    SFG_HIP(launch_spmv(kModePowers, false, gp * p, a, sk_groups(zeta), st));
+  }
+  SFG_HIP(launch_reduce_slots(part, gp, s, s, 0, p, p, (int64_t)gp * s, s, red, ctl, false, st));
+  for (int l = 0; l < p; ++l)
+    SFG_HIP(launch_sketch_out(red + (int64_t)l * s, s, 1.0 / sqrt((double)zeta),
+                              dpart + (int64_t)l * gp * kDP, gp, 0, C + (int64_t)l * s, nullptr,
+                              norm2 + l, st));
   SFG_HIP(hipStreamSynchronize(st));
   return SFGMRES_OK;
 }

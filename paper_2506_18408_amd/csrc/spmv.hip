@@ -110,6 +110,38 @@ __global__ __launch_bounds__(256) void k_rowlen_final(const int32_t* __restrict_
   if (threadIdx.x == 0) *out = sm[0];
 }
 
+// Bandwidth max |i - j| over the nonzeros (per-workgroup maxima, then one
+// workgroup; the final kernel of the row lengths takes the maximum).
+__global__ __launch_bounds__(256) void k_band_part(const int32_t* __restrict__ row_ptr,
+                                                   const int32_t* __restrict__ col_idx, int64_t n,
+                                                   int32_t* __restrict__ part) {
+  __shared__ int32_t sm[256];
+  int32_t mx = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    for (int q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+      const int64_t d = (int64_t)col_idx[q] - r;
+      const int32_t ad = (int32_t)(d < 0 ? -d : d);
+      mx = ad > mx ? ad : mx;
+    }
+  }
+  sm[threadIdx.x] = mx;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o && sm[threadIdx.x + o] > sm[threadIdx.x]) sm[threadIdx.x] = sm[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = sm[0];
+}
+
+hipError_t launch_max_bandwidth(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,
+                                int32_t* part, int32_t* out, hipStream_t st) {
+  const int g = vec_grid(n);
+  hipLaunchKernelGGL(k_band_part, dim3(g), dim3(256), 0, st, row_ptr, col_idx, n, part);
+  hipLaunchKernelGGL(k_rowlen_final, dim3(1), dim3(256), 0, st, part, g, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, int32_t* out,
                              hipStream_t st) {
   const int g = vec_grid(n);
@@ -163,7 +195,8 @@ __device__ __forceinline__ T mat_load(const T* p) {
 template <typename VT, int ZB, int MODE, int NW, bool NT>
 __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   constexpr bool kSketch = ZB > 0;
-  constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain);
+  constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain || MODE == kModePowers);
+  constexpr bool kPowers = MODE == kModePowers;
   constexpr int kU = kWStage / kWave;
   // per wave: the products of its tile, then (sketching) its s accumulators
   extern __shared__ double lds[];
@@ -189,16 +222,40 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // inside a range the waves take every nw-th tile, so the waves of a CU
   // work on neighbouring tiles at the same time (shared DRAM pages and
   // cached x entries)
-  const int G = gridDim.x;
-  const int g = xcd_logical_block(blockIdx.x, G);
-  const int t0 = (int)(((int64_t)a.ntiles * g) / G) + wv;
-  const int t1 = (int)(((int64_t)a.ntiles * (g + 1)) / G);
+  int G = gridDim.x;
+  int g = xcd_logical_block(blockIdx.x, G);
+  int tile0 = 0, ntiles = a.ntiles;
+  const void* xin = a.x;
+  void* wout = a.w;
+  double* part_row = a.part + (int64_t)blockIdx.x * (kSketch ? a.s : 0);
+  double* dpart_row = a.dpart + (int64_t)blockIdx.x * kDP;
+  bool accumulate = false;
+  if constexpr (kPowers) {
+    // (XCD-grouped logical ids: each task group spans whole XCDs when the
+    // grid is a multiple of 8 ptasks)
+    const int gp = G / a.ptasks;
+    const int task = g / gp;
+    const PowTask& T = a.ptask[task < a.ptasks ? task : a.ptasks - 1];
+    if (task >= a.ptasks || !T.active) return;
+    const int gi = g - task * gp;
+    tile0 = T.tile0;
+    ntiles = T.ntiles;
+    xin = T.x;
+    wout = T.w;
+    part_row = T.part + (int64_t)gi * a.s;
+    dpart_row = T.dpart + (int64_t)gi * kDP;
+    accumulate = !T.first;
+    G = gp;
+    g = gi;
+  }
+  const int t0 = tile0 + (int)(((int64_t)ntiles * g) / G) + wv;
+  const int t1 = tile0 + (int)(((int64_t)ntiles * (g + 1)) / G);
 
   const int32_t* __restrict__ row_ptr = a.row_ptr;
   const int32_t* __restrict__ col_idx = a.col_idx;
   const VT* __restrict__ val = static_cast<const VT*>(a.val);
-  const VT* __restrict__ x = static_cast<const VT*>(a.x);
-  VT* __restrict__ w = static_cast<VT*>(a.w);
+  const VT* __restrict__ x = static_cast<const VT*>(xin);
+  VT* __restrict__ w = static_cast<VT*>(wout);
   const VT* __restrict__ U = static_cast<const VT*>(a.U);
   const bool has_x = (MODE != kModeResid) || a.has_x;
   // (t = 0 has no window: only the NW = 0 instances carry the sigma path)
@@ -653,18 +710,19 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   }
   __syncthreads();
   if constexpr (kSketch) {
-    double* prow = a.part + (int64_t)blockIdx.x * S;
+    double* prow = part_row;
     for (int q = tid; q < S; q += blockDim.x) {
       const double* sk0 = lds + stage + q;  // wave 0's copy
       double v = sk0[0];
       for (int k = 1; k < nw; ++k) v += sk0[(size_t)k * wstride];
-      prow[q] = v;
+      prow[q] = accumulate ? prow[q] + v : v;
     }
   }
   if (tid < kNS) {
     double r = 0.0;
     for (int k = 0; k < nw; ++k) r += wsums[k * kNS + tid];
-    double* drow = a.dpart + (int64_t)blockIdx.x * kDP;
+    if (accumulate && tid == kNS - 1) r += dpart_row[kMaxT];
+    double* drow = dpart_row;
     if (!kInnerLike)
       drow[kMaxT + tid] = r;  // (reference or outer dot, then the second sum)
     else if (tid == kNS - 1)
@@ -749,6 +807,8 @@ hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb,
                   : launch_spmv_nw<double, kModeInner>(zb, c, a);
     case kModePlain:
       return launch_spmv_nw<double, kModePlain>(zb, c, a);
+    case kModePowers:
+      return launch_spmv_zb<double, kModePowers, 0>(zb, c, a);
     case kModeOuter:
       return launch_spmv_zb<double, kModeOuter, 1>(0, c, a);
     case kModeResid:
