@@ -54,13 +54,15 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 TARGET_FRAC = 0.60      # the fused kernel's target fraction of HBM peak
-# HBM bytes per dispatch of the headline fused kernel (FP64, 256^3 system)
-# from rocprofv3 FETCH_SIZE and WRITE_SIZE (KiB), each scaled by the factor
-# measured on a plain device copy of known size (bench.py --copy-calibration):
-# FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0, averaged over the working dispatches of
-# one forward solve.  Valid only for the kernel source it was measured on;
+# HBM bytes per dispatch of the headline fused kernel (FP64, 256^3 system,
+# sketch columns generated in the kernel) from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (KiB), each scaled by the factor measured on a plain device copy
+# of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 (2205.9 MB,
+# equal to the 128-byte read requests counted directly) + WRITE_SIZE x 1.0
+# (135.8 MB), averaged over the 6042 working dispatches of one FP64 forward
+# and adjoint solve.  Valid only for the kernel source it was measured on;
 # None whenever that kernel changes.
-PMC_TRAFFIC_BYTES = None
+PMC_TRAFFIC_BYTES = 2341.8e6
 
 
 def log(*a):
@@ -146,7 +148,8 @@ def fused_rate(infos, A, t, m, zeta, fp32):
     """Mean duration of the timed working fused launches, their algorithmic
     bytes (matrix values and indices, row pointers, input, output and the
     window vectors of the fused dots; S counts 0 bytes) and the bytes of the
-    packed sketch the kernel also reads (implementation traffic)."""
+    packed sketch the kernel also reads (implementation traffic; 0 when it
+    generates the columns of S itself)."""
     launches = sum(i["spmv_launches"] for i in infos)
     ms = sum(i["spmv_ms"] for i in infos)
     win, wl = 0, 0
@@ -159,7 +162,7 @@ def fused_rate(infos, A, t, m, zeta, fp32):
     vb = 4 if fp32 else 8
     zg = (zeta + 7) // 8  # packed sketch: groups of 12 bytes per column
     alg = (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches)
-    sk = 12 * zg * A.n
+    sk = 0 if infos[-1].get("sketch_generated") else 12 * zg * A.n
     avg = ms * 1e-3 / launches
     return avg, alg, sk, launches
 
@@ -400,8 +403,9 @@ def headline(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": PMC_TRAFFIC_BYTES,
                      "target_frac": TARGET_FRAC,
-                     "kernel": "k_spmv<double, 1, kModeInner, 2, false> (fused SpMV+sketch+window "
-                               "dots, FP64, forward solve; ZB = ceil(zeta/8) = 1, window 2)",
+                     "kernel": "k_spmv<double, 1, kModeInner, 2, kLdGen> (fused SpMV + sketch with "
+                               "columns generated in the kernel + window dots, FP64, forward "
+                               "solve; ZB = ceil(zeta/8) = 1, window 2)",
                      "bytes_per_launch": alg, "packed_sketch_bytes_per_launch": sk,
                      "mean_launch_us": avg_s * 1e6, "launches": launches},
     }
@@ -429,7 +433,7 @@ def headline(args):
             "rel_error_vs_fp64_solution": err, "rel_error_vs_fp64_adjoint": lerr,
             "fused_mean_launch_us": mavg * 1e6, "fused_alg_bytes": malg,
             "fused_alg_gbs": malg / mavg / 1e9, "frac": malg / mavg / 1e9 / HBM_PEAK_GBS,
-            "kernel": "k_spmv<float, 1, kModeInner, 2, false>",
+            "kernel": "k_spmv<float, 1, kModeInner, 2, kLdCached>",
         }
         log(f"mixed: {msec:.3f} s per forward+adjoint (x{sec / msec:.2f}), outer={im['outer_iters']} "
             f"inner={im['total_inner']} true_rel_res={im['true_rel_residual']:.3e} err={err:.2e} "

@@ -70,6 +70,16 @@ extern "C" {
                                       order; needs sorted columns and every diagonal entry
                                       in the pattern; FGMRES outer only                     */
 
+/* ---- sketch operand of the inner SpMV (sfgmres_options.sketch_source) - */
+#define SFGMRES_SKETCH_AUTO     0  /* (default) GEN for an FP64 solve with zeta <= 8 and short
+                                      rows (at most 8 nonzeros) whose matrix has more than
+                                      512 MiB of values and indices, else TABLE            */
+#define SFGMRES_SKETCH_TABLE    1  /* read each column of S from a packed table (12 bytes per
+                                      column per 8 nonzeros) built at the start of the solve */
+#define SFGMRES_SKETCH_GEN      2  /* generate each column of S (Philox + Floyd) inside the
+                                      fused SpMV: FP64 and zeta <= 8 only.  The same S, so
+                                      results are bit for bit those of TABLE               */
+
 /* ---- inner stop reasons (sfgmres_info.stop_reason) ------------------- */
 #define SFGMRES_STOP_C1         1  /* k reached m                                  */
 #define SFGMRES_STOP_C2         2  /* cond estimate of S A B_i exceeded threshold: k = i-1 */
@@ -145,6 +155,8 @@ typedef struct sfgmres_options {
                                    workspace then also holds the lower level's.  FGMRES outer only;
                                    info.inner_k[j] = the lower level's outer steps,
                                    info.total_inner = all sGMRES inner steps                     */
+  int32_t sketch_source;        /* SFGMRES_SKETCH_AUTO (default), _TABLE or _GEN: where the fused
+                                   inner SpMV takes the columns of S from (a speed choice only)  */
 } sfgmres_options;
 
 /* Solve diagnostics.  Scalars are always written; each per-step array is a
@@ -192,7 +204,10 @@ typedef struct sfgmres_info {
                                        [4] diagnostic true residuals (record_true_residual),
                                        [5] final iterate, its true residual, FFOM iterate,
                                        [6] adjoint: CSR(A^T), [7] adjoint: dL/dA            */
-  double  reserved[4];
+  int32_t sketch_generated;         /* 1 if the inner SpMV generated the columns of S
+                                       (sketch_source), 0 if it read the packed table    */
+  int32_t reserved_i;
+  double  reserved[3];
 } sfgmres_info;
 
 typedef struct sfgmres_ctx* sfgmres_handle;

@@ -25,6 +25,9 @@ MIXED = 1
 
 PRECOND_NONE = 0
 PRECOND_ILU0 = 1
+SKETCH_AUTO = 0
+SKETCH_TABLE = 1
+SKETCH_GEN = 2
 
 STOP_REASONS = {1: "C1", 2: "C2", 3: "C3", 4: "breakdown", 5: "forced", 6: "mid"}
 
@@ -62,6 +65,7 @@ class Options(C.Structure):
         ("phase_timers", C.c_int32),
         ("precond", C.c_int32),
         ("mid_outer", C.c_int32),
+        ("sketch_source", C.c_int32),
     ]
 
 
@@ -89,7 +93,9 @@ class Info(C.Structure):
         ("delta_bound", C.POINTER(C.c_double)),
         ("ffom_x", C.c_void_p),
         ("phase_ms", C.c_double * 8),
-        ("reserved", C.c_double * 4),
+        ("sketch_generated", C.c_int32),
+        ("reserved_i", C.c_int32),
+        ("reserved", C.c_double * 3),
     ]
 
 

@@ -41,7 +41,10 @@ class SolveParams:
     phase_timers: per-phase GPU times into info["phase_ms"]; precond: "none"
     or "ilu0" (zero-fill ILU right preconditioning in a multicolour order,
     FGMRES outer only); mid_outer: N > 0 for two-level FGMRES, each outer
-    step preconditioned by a lower-level FGMRES solve of at most N steps.
+    step preconditioned by a lower-level FGMRES solve of at most N steps;
+    sketch_source: "auto", "table" (packed columns of S read by the fused
+    SpMV) or "gen" (columns generated inside it; FP64, zeta <= 8) -- the
+    same S either way.
     """
     m: int = 30
     t: int = 2
@@ -59,6 +62,7 @@ class SolveParams:
     phase_timers: bool = False
     precond: str = "none"
     mid_outer: int = 0
+    sketch_source: str = "auto"
 
 
 _HANDLES = {}
@@ -144,6 +148,8 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.phase_timers = 1 if p.phase_timers else 0
     o.precond = {"none": L.PRECOND_NONE, "ilu0": L.PRECOND_ILU0}[p.precond]
     o.mid_outer = p.mid_outer
+    o.sketch_source = {"auto": L.SKETCH_AUTO, "table": L.SKETCH_TABLE,
+                       "gen": L.SKETCH_GEN}[p.sketch_source]
     return o
 
 
@@ -202,6 +208,7 @@ class _InfoBuffers:
             spmv_launches=self.info.spmv_launches,
             solve_ms=self.info.solve_ms,
             phase_ms=dict(zip(L.PHASES, list(self.info.phase_ms))),
+            sketch_generated=bool(self.info.sketch_generated),
         )
 
 

@@ -42,6 +42,13 @@ constexpr int kTileNnz = kWStage / 2;
 // the FP64 inner SpMV with streaming loads, so that it does not evict the x
 // entries its gathers reuse.
 constexpr size_t kStreamMatrixBytes = (size_t)300 << 20;
+// An FP64 matrix of more bytes than this per SpMV (twice the last-level
+// cache) with short rows has its inner SpMV generate the sketch columns
+// (Philox + Floyd, zeta <= 8) instead of reading the packed table: the
+// FP64 stream leaves the vector units idle long enough to hide the
+// generator, and the 12 bytes per row of the table are saved.  (The FP32
+// stream and cache-resident matrices are faster with the table.)
+constexpr size_t kGenSketchBytes = (size_t)512 << 20;
 constexpr int kSpmvLdsMax = 150 * 1024;  // dynamic LDS of one SpMV workgroup (bytes)
 // Bound on the number of partial rows any multi-workgroup kernel writes.
 constexpr int kMaxGrid = 1024;
@@ -201,6 +208,35 @@ __device__ __forceinline__ void sketch_column(uint32_t col, int s, int zeta, uin
       rows[d] = -1;
     }
   }
+}
+
+// Packed group b of a column from its rows and sign flags (the fields of
+// SkGroup: row bits 0-7 in bytes of w[0..1], row bits 8-10 and the sign in
+// the nibbles of w[2]).
+template <int NR>
+__device__ __forceinline__ SkGroup sk_pack(const int (&rows)[NR], uint32_t neg, int zeta, int b) {
+  SkGroup q{{0u, 0u, 0u}};
+#pragma unroll
+  for (int e = 0; e < kSkGroup; ++e) {
+    const int d = kSkGroup * b + e;
+    if (d < zeta && d < NR) {
+      const uint32_t row = (uint32_t)rows[d];
+      q.w[e >> 2] |= (row & 0xFFu) << ((e & 3) * 8);
+      q.w[2] |= (((row >> 8) & 7u) | (((neg >> d) & 1u) << 3)) << (e * 4);
+    }
+  }
+  return q;
+}
+
+// The single packed group of column `col` for zeta <= 8 (two Philox
+// blocks), generated where it is used: equal to what the packing kernel
+// stores for that column.
+__device__ __forceinline__ SkGroup sketch_group8(uint32_t col, int s, int zeta, uint32_t k0,
+                                                 uint32_t k1) {
+  int rows[8];
+  uint32_t neg;
+  sketch_column<2>(col, s, zeta, k0, k1, rows, neg);
+  return sk_pack(rows, neg, zeta, 0);
 }
 
 // Scatter of v (the value of entry `col` of a vector) into the s LDS

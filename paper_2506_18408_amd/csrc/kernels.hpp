@@ -55,6 +55,8 @@ struct SpmvArgs {
   int32_t s;                // sketch rows (0: no sketch)
   int32_t zeta;             // nonzeros per sketch column
   const SkGroup* skp;       // packed sketch
+  int32_t sketch_gen;       // kModeInner, FP64, zeta <= 8: generate the sketch columns
+  uint32_t sk_k0, sk_k1;    // the sketch's Philox key (sketch_gen)
   const void* U;            // window base (same type as val), column-major
   int64_t ldu;
   int32_t l0, nwin;         // window columns [l0, l0 + nwin)
@@ -223,34 +225,60 @@ size_t transpose_scan_tmp_ints(int64_t n);
 
 // Zero-fill ILU right preconditioner in a multicolour order (ilu.hip).
 constexpr int kIluMaxColors = 4095;  // (12-bit colour field of the colouring state)
+constexpr int kIluChunk = 8192;      // rows per wave when the rows are grouped by colour
+constexpr int kIluLongRow = 32;      // longest row factored one thread per row
+inline int64_t ilu_chunks(int64_t n) { return (n + kIluChunk - 1) / kIluChunk; }
+// Factors for the triangular solves, by position p in the colour order
+// (row order[p]): the off-diagonal entries of L in oci/oval[orp[p] ..
+// omid[p]), those of U in [omid[p] .. orp[p+1]), each in the row's column
+// order; U's diagonal in udiag[p].  Column indices are row numbers of A.
 struct IluFactors {
-  const int32_t* rp;       // A's pattern (sorted columns)
-  const int32_t* ci;
-  const double* lu;        // factor values on A's pattern: L below (by colour), U above
-  const int8_t* kind;      // per nonzero: -1 L, 0 diagonal, +1 U
-  const int32_t* diag;     // position of the diagonal in each row
-  const int32_t* order;    // rows grouped by colour
-  const int32_t* level;    // host array: order[level[c] .. level[c+1]) has colour c
+  const int32_t* order;      // rows by colour, increasing within a colour
+  const int32_t* orp;        // n+1
+  const int32_t* omid;       // n
+  const int32_t* oci;
+  const double* oval;
+  const double* udiag;
+  const int32_t* level;      // host: order[level[c] .. level[c+1]) has colour c
+  const int8_t* group;       // host: lanes per row in colour c, [2c] for L and [2c+1] for U
   int32_t ncolors;
 };
 hipError_t launch_ilu_init(int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                            double* lu, int32_t* diag, int32_t* state, int32_t* err,
-                           hipStream_t st);
+                           int32_t* maxrow, hipStream_t st);
 hipError_t launch_ilu_jp_round(int64_t n, const int32_t* rp, const int32_t* ci,
                                const int32_t* rpt, const int32_t* cit, int32_t* state,
                                int32_t round, int32_t* colored, int32_t* err, hipStream_t st);
 hipError_t launch_ilu_count(int64_t n, const int32_t* state, int32_t* cnt, hipStream_t st);
 hipError_t launch_ilu_colors(int64_t n, const int32_t* state, int32_t* color, hipStream_t st);
-hipError_t launch_ilu_scatter(int64_t n, const int32_t* rp, const int32_t* ci,
-                              const int32_t* state, const int32_t* start, int32_t* cursor,
-                              int32_t* order, int8_t* kind, hipStream_t st);
+// order: the rows grouped by colour (start[c] = first position of colour c),
+// increasing within a colour; kind: per nonzero -1 (L), 0 (diagonal), +1 (U).
+// hist holds nc * ilu_chunks(n) ints.
+hipError_t launch_ilu_order(int64_t n, const int32_t* rp, const int32_t* ci,
+                            const int32_t* state, int32_t nc, const int32_t* start,
+                            int32_t* hist, int32_t* order, int8_t* kind, hipStream_t st);
 hipError_t launch_ilu_factor(const int32_t* order, int32_t begin, int32_t end, const int32_t* rp,
                              const int32_t* ci, const int8_t* kind, const int32_t* diag,
-                             const int32_t* state, double* lu, int32_t* err, hipStream_t st);
+                             const int32_t* state, double* lu, int32_t* err, bool wave_per_row,
+                             hipStream_t st);
+// The solve copies (orp, omid, oci, oval, udiag) from the factors on A's
+// pattern; lsum[c] = L entries of colour c (lsum zero on entry), usum[c] = U
+// entries (nc each).
+hipError_t launch_ilu_split(int64_t n, const int32_t* rp, const int32_t* ci, const int8_t* kind,
+                            const int32_t* diag, const double* lu, const int32_t* order,
+                            int32_t nc, const int32_t* start, int32_t* orp, int32_t* omid,
+                            int32_t* oci, double* oval, double* udiag, int32_t* lsum,
+                            int32_t* usum, int32_t* scan_tmp, hipStream_t st);
+// Lanes per row for a colour whose rows hold `entries` off-diagonal entries
+// of the solved factor in all.
+int ilu_group(int64_t rows, int64_t entries);
 // out = M^{-1} in (VT = float when fp32), through the FP64 work vector t;
 // with ctl, every launch does nothing once the inner cycle has stopped.
 hipError_t launch_ilu_apply(bool fp32, const IluFactors& f, const void* in, double* t, void* out,
                             hipStream_t st, const DevCtl* ctl = nullptr);
+// In-place exclusive scan of cnt[0 .. n) with the total stored to cnt[n]
+// (vec.hip; scan_tmp holds transpose_scan_tmp_ints(n) ints).
+hipError_t launch_exclusive_scan(int32_t* cnt, int64_t n, int32_t* scan_tmp, hipStream_t st);
 
 // The fused SpMV export (sfgmres_spmv_sketch) on a workspace of ws_bytes
 // bytes, and the bytes it needs (solver.hip).

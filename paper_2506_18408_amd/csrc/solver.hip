@@ -71,8 +71,12 @@ int lookahead_steps(const sfgmres_options& o) {
 }
 
 struct IluWs {
-  size_t lu, kind, diag, state, order, cnt, t_rp, t_ci, t_perm, t_cursor, t_scan, total;
+  size_t lu, kind, diag, state, order, cnt, t_rp, t_ci, t_perm, t_cursor, t_scan, hist, orp, omid,
+      oci, oval, udiag, total;
 };
+// Ints of the ILU counter block: counts, level starts, L and U entries per
+// colour, then the error flags, coloured rows and the longest row.
+constexpr size_t kIluCntInts = 4 * (kIluMaxColors + 1) + 8;
 
 // The ILU regions of a workspace (appended to `off`).
 IluWs ilu_regions(int64_t n, int64_t nnz, size_t off) {
@@ -87,12 +91,18 @@ IluWs ilu_regions(int64_t n, int64_t nnz, size_t off) {
   W.diag = take((size_t)n * 4);
   W.state = take((size_t)n * 4);
   W.order = take((size_t)n * 4);
-  W.cnt = take((size_t)(3 * (kIluMaxColors + 1) + 8) * 4);
+  W.cnt = take(kIluCntInts * 4);
   W.t_rp = take((size_t)(n + 1) * 4);
   W.t_ci = take((size_t)nnz * 4);
   W.t_perm = take((size_t)nnz * 4);
   W.t_cursor = take((size_t)(n + 1) * 4);
   W.t_scan = take(transpose_scan_tmp_ints(n) * 4);
+  W.hist = take((size_t)kIluMaxColors * (size_t)ilu_chunks(n) * 4);
+  W.orp = take((size_t)(n + 1) * 4);
+  W.omid = take((size_t)n * 4);
+  W.oci = take((size_t)nnz * 4);
+  W.oval = take((size_t)nnz * 8);
+  W.udiag = take((size_t)n * 8);
   W.total = off;
   return W;
 }
@@ -208,6 +218,7 @@ sfgmres_options defaults() {
   o.outer = SFGMRES_OUTER_FGMRES;
   o.precond = SFGMRES_PRECOND_NONE;
   o.mid_outer = 0;
+  o.sketch_source = SFGMRES_SKETCH_AUTO;
   return o;
 }
 
@@ -254,6 +265,12 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
     return fail(h, SFGMRES_ERR_INVALID, "need 0 <= mid_outer <= 2000");
   if (o.mid_outer > 0 && o.outer != SFGMRES_OUTER_FGMRES)
     return fail(h, SFGMRES_ERR_INVALID, "mid_outer needs the FGMRES outer iteration");
+  if (o.sketch_source < SFGMRES_SKETCH_AUTO || o.sketch_source > SFGMRES_SKETCH_GEN)
+    return fail(h, SFGMRES_ERR_INVALID, "sketch_source must be AUTO, TABLE or GEN");
+  if (o.sketch_source == SFGMRES_SKETCH_GEN &&
+      (o.precision != SFGMRES_FP64 || zeta > kSkGroup || o.identity_sketch))
+    return fail(h, SFGMRES_ERR_INVALID,
+                "sketch_source GEN needs FP64, zeta <= 8 and the random sketch");
   return SFGMRES_OK;
 }
 
@@ -380,12 +397,19 @@ bool spin_until(sfgmres_ctx* h, Pred pred) {
   return true;
 }
 
+// Host side of the ILU factors: level starts and lanes per row per colour.
+struct IluHost {
+  std::vector<int32_t> level;
+  std::vector<int8_t> group;
+};
+
 // ILU(0) set-up on the device: diagonal positions and the check of the
 // pattern, the transposed pattern, Jones-Plassmann rounds until every row
 // is coloured, rows grouped by colour (level starts read back to the
-// host), then the factorisation one colour at a time.
+// host), the factorisation one colour at a time, and the copies of the
+// factors in the colour order for the triangular solves.
 int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L,
-              hipStream_t st, IluFactors* F, std::vector<int32_t>* levels) {
+              hipStream_t st, IluFactors* F, IluHost* host) {
   const int64_t n = A->n, nnz = A->nnz;
   double* lu = reinterpret_cast<double*>(base + L.lu);
   int8_t* kind = reinterpret_cast<int8_t*>(base + L.kind);
@@ -393,24 +417,27 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
   int32_t* state = reinterpret_cast<int32_t*>(base + L.state);
   int32_t* order = reinterpret_cast<int32_t*>(base + L.order);
   int32_t* cnt = reinterpret_cast<int32_t*>(base + L.cnt);
-  int32_t* cursor = cnt + (kIluMaxColors + 1);
-  int32_t* start = cursor + (kIluMaxColors + 1);
-  int32_t* err = start + (kIluMaxColors + 1);
+  int32_t* start = cnt + (kIluMaxColors + 1);
+  int32_t* lsum = start + (kIluMaxColors + 1);
+  int32_t* usum = lsum + (kIluMaxColors + 1);
+  int32_t* err = usum + (kIluMaxColors + 1);
   int32_t* colored = err + 1;
+  int32_t* maxrow = err + 2;
   int32_t* trp = reinterpret_cast<int32_t*>(base + L.t_rp);
   int32_t* tci = reinterpret_cast<int32_t*>(base + L.t_ci);
-  SFG_HIP(hipMemsetAsync(cnt, 0, (size_t)(3 * (kIluMaxColors + 1) + 8) * 4, st));
-  SFG_HIP(launch_ilu_init(n, A->row_ptr, A->col_idx, A->val, lu, diag, state, err, st));
+  int32_t* scan_tmp = reinterpret_cast<int32_t*>(base + L.t_scan);
+  SFG_HIP(hipMemsetAsync(cnt, 0, kIluCntInts * 4, st));
+  SFG_HIP(launch_ilu_init(n, A->row_ptr, A->col_idx, A->val, lu, diag, state, err, maxrow, st));
   SFG_HIP(launch_transpose(A->row_ptr, A->col_idx, nullptr, n, nnz, trp, tci, nullptr,
                            reinterpret_cast<int32_t*>(base + L.t_perm),
-                           reinterpret_cast<int32_t*>(base + L.t_cursor),
-                           reinterpret_cast<int32_t*>(base + L.t_scan), st));
-  int32_t hv[2] = {0, 0};
-  SFG_HIP(hipMemcpyAsync(hv, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                           reinterpret_cast<int32_t*>(base + L.t_cursor), scan_tmp, st));
+  int32_t hv[3] = {0, 0, 0};
+  SFG_HIP(hipMemcpyAsync(hv, err, 3 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
   SFG_HIP(hipStreamSynchronize(st));
   if (hv[0] & 3)
     return fail(h, SFGMRES_ERR_INVALID,
                 "ILU(0) needs strictly increasing columns in every row and every diagonal entry");
+  const bool long_rows = hv[2] > kIluLongRow;
   // (the globally highest-priority uncoloured vertex colours itself in every
   // round, so at most n rounds; the round number sits above the 12 colour bits)
   const int64_t max_rounds = std::min<int64_t>(n + 1, (int64_t)1 << 19);
@@ -431,23 +458,41 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
   int nc = 0;
   for (int c = 0; c < kIluMaxColors; ++c)
     if (hc[c]) nc = c + 1;
-  levels->assign(nc + 1, 0);
-  for (int c = 0; c < nc; ++c) (*levels)[c + 1] = (*levels)[c] + hc[c];
-  SFG_HIP(hipMemcpyAsync(start, levels->data(), (size_t)(nc + 1) * 4, hipMemcpyHostToDevice, st));
-  SFG_HIP(launch_ilu_scatter(n, A->row_ptr, A->col_idx, state, start, cursor, order, kind, st));
+  std::vector<int32_t>& lev = host->level;
+  lev.assign(nc + 1, 0);
+  for (int c = 0; c < nc; ++c) lev[c + 1] = lev[c] + hc[c];
+  SFG_HIP(hipMemcpyAsync(start, lev.data(), (size_t)(nc + 1) * 4, hipMemcpyHostToDevice, st));
+  SFG_HIP(launch_ilu_order(n, A->row_ptr, A->col_idx, state, nc, start,
+                           reinterpret_cast<int32_t*>(base + L.hist), order, kind, st));
   for (int c = 0; c < nc; ++c)
-    SFG_HIP(launch_ilu_factor(order, (*levels)[c], (*levels)[c + 1], A->row_ptr, A->col_idx, kind,
-                              diag, state, lu, err, st));
+    SFG_HIP(launch_ilu_factor(order, lev[c], lev[c + 1], A->row_ptr, A->col_idx, kind, diag, state,
+                              lu, err, long_rows, st));
+  int32_t* orp = reinterpret_cast<int32_t*>(base + L.orp);
+  int32_t* omid = reinterpret_cast<int32_t*>(base + L.omid);
+  int32_t* oci = reinterpret_cast<int32_t*>(base + L.oci);
+  double* oval = reinterpret_cast<double*>(base + L.oval);
+  double* udiag = reinterpret_cast<double*>(base + L.udiag);
+  SFG_HIP(launch_ilu_split(n, A->row_ptr, A->col_idx, kind, diag, lu, order, nc, start, orp, omid,
+                           oci, oval, udiag, lsum, usum, scan_tmp, st));
+  std::vector<int32_t> sums(2 * (size_t)(kIluMaxColors + 1));
   SFG_HIP(hipMemcpyAsync(hv, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  SFG_HIP(hipMemcpyAsync(sums.data(), lsum, sums.size() * 4, hipMemcpyDeviceToHost, st));
   SFG_HIP(hipStreamSynchronize(st));
   if (hv[0] & 8) return fail(h, SFGMRES_ERR_BREAKDOWN, "zero pivot in the ILU(0) factorisation");
-  F->rp = A->row_ptr;
-  F->ci = A->col_idx;
-  F->lu = lu;
-  F->kind = kind;
-  F->diag = diag;
+  host->group.assign(2 * (size_t)nc, 1);
+  for (int c = 0; c < nc; ++c) {
+    const int64_t rows = lev[c + 1] - lev[c];
+    host->group[2 * c] = (int8_t)ilu_group(rows, sums[c]);
+    host->group[2 * c + 1] = (int8_t)ilu_group(rows, sums[(kIluMaxColors + 1) + c]);
+  }
   F->order = order;
-  F->level = levels->data();
+  F->orp = orp;
+  F->omid = omid;
+  F->oci = oci;
+  F->oval = oval;
+  F->udiag = udiag;
+  F->level = lev.data();
+  F->group = host->group.data();
   F->ncolors = nc;
   return SFGMRES_OK;
 }
@@ -466,7 +511,7 @@ int ensure_marks(sfgmres_handle h) {
 int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const double* x0,
                double* x, int32_t m, int32_t t, int32_t s, int32_t zeta, double tol,
                uint64_t seed, const sfgmres_options& o, sfgmres_info* info, void* ws,
-               size_t ws_bytes, hipStream_t st) {
+               size_t ws_bytes, hipStream_t st, const IluFactors* shared_ilu = nullptr) {
   const double t_start = now_ms();
   const int64_t n = A->n, nnz = A->nnz;
   int rc = check_params(h, n, nnz, m, t, s, zeta, tol, o);
@@ -561,16 +606,21 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   const int32_t ntiles = tiling.ntiles;
   const int Gp = tiling.grid;
   const int Gn = rows_grid(n);
-  // (with a lower level, the preconditioner belongs to its sGMRES cycles)
+  // (with a lower level, the preconditioner belongs to its sGMRES cycles;
+  // the top level factors A once and hands the factors down)
   const bool mid = o.mid_outer > 0;
   const bool ilu = o.precond == SFGMRES_PRECOND_ILU0 && !mid;
   IluFactors F{};
-  std::vector<int32_t> ilu_levels;
+  IluHost ilu_host;
   double* ilu_t64 = reinterpret_cast<double*>(base + L.ilu_t64);
   void* ilu_tmp = base + L.ilu_tmp;
-  if (ilu) {
-    rc = ilu_setup(h, A, base, ilu_regions(n, nnz, L.ilu), st, &F, &ilu_levels);
-    if (rc) return rc;
+  if (o.precond == SFGMRES_PRECOND_ILU0) {
+    if (shared_ilu) {
+      F = *shared_ilu;
+    } else {
+      rc = ilu_setup(h, A, base, ilu_regions(n, nnz, L.ilu), st, &F, &ilu_host);
+      if (rc) return rc;
+    }
   }
   const int G2 = vec_grid(n);
   const int Ga = arnoldi_grid(n);  // the Arnoldi update (and its norm partials)
@@ -599,6 +649,14 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
   base_args.scale_val = 1.0;
   base_args.skp = P.skp;
   base_args.zeta = zeta;
+  base_args.sketch_gen =
+      o.sketch_source == SFGMRES_SKETCH_GEN ||
+      (o.sketch_source == SFGMRES_SKETCH_AUTO && !f32 && zb == 1 && !o.identity_sketch &&
+       tiling.max_row <= kShortRow && (size_t)nnz * 12 > kGenSketchBytes);
+  if (base_args.sketch_gen) base_args.stream_matrix = 0;
+  if (info) info->sketch_generated = base_args.sketch_gen;
+  base_args.sk_k0 = k0;
+  base_args.sk_k1 = k1;
 
   QrBlockArgs qa{};
   qa.red = P.red;
@@ -716,7 +774,8 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
       memset(&mi, 0, sizeof(mi));
       const double tol_mid = isfinite(factor_host) ? tol * nb / factor_host : tol * nb;
       const int mrc = solve_impl(h, A, Vcol(j), nullptr, Zcol(j), m, t, s, zeta, tol_mid, seed,
-                                 om, &mi, base + L.mid, L.mid_bytes, st);
+                                 om, &mi, base + L.mid, L.mid_bytes, st,
+                                 o.precond == SFGMRES_PRECOND_ILU0 ? &F : nullptr);
       if (mrc < 0) return mrc;
       mid_k = mi.outer_iters;
       mid_inner = mi.total_inner;
@@ -1445,8 +1504,8 @@ int sfgmres_ilu0(sfgmres_handle h, const sfgmres_csr* A, double* lu, int32_t* co
   char* base = static_cast<char*>(ws);
   const IluWs W = ilu_regions(A->n, A->nnz, 0);
   IluFactors F{};
-  std::vector<int32_t> levels;
-  const int rc = ilu_setup(h, A, base, W, st, &F, &levels);
+  IluHost host;
+  const int rc = ilu_setup(h, A, base, W, st, &F, &host);
   if (rc) return rc;
   SFG_HIP(hipMemcpyAsync(lu, base + W.lu, (size_t)A->nnz * 8, hipMemcpyDeviceToDevice, st));
   SFG_HIP(launch_ilu_colors(A->n, reinterpret_cast<const int32_t*>(base + W.state), color, st));

@@ -28,7 +28,8 @@
 // does not finish far ahead of the youngest while the final barrier waits.
 // At t = 0 the kernel forms its own scale sigma_i = 1/||u_i|| from the
 // previous step's norm partials; an FP64 matrix far beyond the last-level
-// cache with irregular rows is read through a streaming-load instance.
+// cache is read through a streaming-load instance (irregular rows) or has
+// its sketch columns generated in the kernel (short rows).
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -182,6 +183,14 @@ __device__ __forceinline__ void wave_sync() {
 template <int NW>
 constexpr int spmv_max_threads() { return NW > 4 ? 12 * kWave : kSpmvMaxThreads; }
 
+// How the inner SpMV reads its operands (an instance parameter): cached
+// matrix loads and the packed sketch; streaming matrix loads (a matrix that
+// cannot stay in the last-level cache); or cached loads with the sketch
+// columns generated in the epilogue's prefetch.
+constexpr int kLdCached = 0;
+constexpr int kLdStream = 1;
+constexpr int kLdGen = 2;
+
 // A matrix load: cached, or streaming (NT) for a matrix that cannot stay in
 // the last-level cache.
 template <bool NT, typename T>
@@ -192,8 +201,10 @@ __device__ __forceinline__ T mat_load(const T* p) {
     return *p;
 }
 
-template <typename VT, int ZB, int MODE, int NW, bool NT>
+template <typename VT, int ZB, int MODE, int NW, int LD>
 __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
+  constexpr bool NT = LD == kLdStream;
+  static_assert(LD != kLdGen || (ZB == 1 && MODE == kModeInner), "generated sketch: zeta <= 8");
   constexpr bool kSketch = ZB > 0;
   constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain || MODE == kModePowers);
   constexpr bool kPowers = MODE == kModePowers;
@@ -284,8 +295,12 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
 #pragma unroll
       for (int l = 0; l < NW; ++l)
         p.u[l] = l < nwin ? U[(int64_t)(a.l0 + l) * a.ldu + r] : VT(0);
+      if constexpr (LD == kLdGen) {
+        p.sk[0] = sketch_group8((uint32_t)r, a.s, a.zeta, a.sk_k0, a.sk_k1);
+      } else {
 #pragma unroll
-      for (int b = 0; b < ZB; ++b) p.sk[b] = a.skp[(int64_t)r * ZB + b];
+        for (int b = 0; b < ZB; ++b) p.sk[b] = a.skp[(int64_t)r * ZB + b];
+      }
     } else if constexpr (MODE == kModeOuter) {
       p.b0 = a.v0[r];
       p.b1 = a.vj[r];
@@ -740,31 +755,35 @@ struct LaunchCfg {
   hipEvent_t ev0, ev1;
 };
 
-template <typename VT, int ZB, int MODE, int NW, bool NT>
-static hipError_t launch_nt(const LaunchCfg& c, const SpmvArgs& a) {
+template <typename VT, int ZB, int MODE, int NW, int LD>
+static hipError_t launch_ld(const LaunchCfg& c, const SpmvArgs& a) {
   static bool attr_set = false;  // dynamic LDS above the default limit
   if (!attr_set) {
     const hipError_t e =
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<VT, ZB, MODE, NW, NT>),
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_spmv<VT, ZB, MODE, NW, LD>),
                             hipFuncAttributeMaxDynamicSharedMemorySize, kSpmvLdsMax);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
   const dim3 block(c.waves * kWave);
   if (c.ev0)
-    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW, NT>), dim3(c.grid), block, c.lds, c.st,
+    hipExtLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW, LD>), dim3(c.grid), block, c.lds, c.st,
                           c.ev0, c.ev1, 0, a);
   else
-    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW, NT>), dim3(c.grid), block, c.lds, c.st, a);
+    hipLaunchKernelGGL((k_spmv<VT, ZB, MODE, NW, LD>), dim3(c.grid), block, c.lds, c.st, a);
   return hipGetLastError();
 }
 
-// (only the FP64 inner SpMV has a streaming-load instance)
+// (only the FP64 inner SpMV has streaming-load and generated-sketch
+// instances)
 template <typename VT, int ZB, int MODE, int NW>
 static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
-  if constexpr (sizeof(VT) == 8 && MODE == kModeInner)
-    if (a.stream_matrix) return launch_nt<VT, ZB, MODE, NW, true>(c, a);
-  return launch_nt<VT, ZB, MODE, NW, false>(c, a);
+  if constexpr (sizeof(VT) == 8 && MODE == kModeInner) {
+    if (a.stream_matrix) return launch_ld<VT, ZB, MODE, NW, kLdStream>(c, a);
+    if constexpr (ZB == 1)
+      if (a.sketch_gen) return launch_ld<VT, ZB, MODE, NW, kLdGen>(c, a);
+  }
+  return launch_ld<VT, ZB, MODE, NW, kLdCached>(c, a);
 }
 
 template <typename VT, int MODE, int NW>
@@ -888,17 +907,7 @@ __global__ void k_sketch_pack(int64_t n, int32_t s, int32_t zeta, uint32_t k0, u
 #pragma unroll
     for (int b = 0; b < kG; ++b) {
       if (b >= ng) break;
-      SkGroup q{{0u, 0u, 0u}};
-#pragma unroll
-      for (int e = 0; e < kSkGroup; ++e) {
-        const int d = kSkGroup * b + e;
-        if (d < zeta && d < 4 * ZB) {
-          const uint32_t row = (uint32_t)rows[d];
-          q.w[e >> 2] |= (row & 0xFFu) << ((e & 3) * 8);
-          q.w[2] |= (((row >> 8) & 7u) | (((neg >> d) & 1u) << 3)) << (e * 4);
-        }
-      }
-      skp[r * ng + b] = q;
+      skp[r * ng + b] = sk_pack(rows, neg, zeta, b);
     }
   }
 }

@@ -879,6 +879,22 @@ __global__ void k_sort_rows(const int32_t* __restrict__ rp_t, int64_t n, int32_t
 
 __global__ void k_copy_i32_last(const int32_t* src, int32_t* dst) { *dst = *src; }
 
+hipError_t launch_exclusive_scan(int32_t* cnt, int64_t n, int32_t* scan_tmp, hipStream_t st) {
+  const int64_t nb = (n + kScanChunk - 1) / kScanChunk;
+  if (nb > 0) {
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nb), dim3(kScanThreads), 0, st, cnt, n,
+                       scan_tmp);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(kScanThreads), 0, st, scan_tmp, nb);
+    // (each thread reads its own items before it writes them)
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kScanThreads), 0, st, cnt, n,
+                       scan_tmp, cnt);
+  } else {
+    hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kVecThreads), 0, st, scan_tmp, (int64_t)1);
+  }
+  hipLaunchKernelGGL(k_copy_i32_last, dim3(1), dim3(1), 0, st, scan_tmp + nb, cnt + n);
+  return hipGetLastError();
+}
+
 hipError_t launch_transpose(const int32_t* row_ptr, const int32_t* col_idx, const double* val,
                             int64_t n, int64_t nnz, int32_t* rp_t, int32_t* col_t,
                             double* val_t, int32_t* perm, int32_t* cursor, int32_t* scan_tmp,

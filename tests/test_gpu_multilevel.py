@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import oracle
+import oracle.ilu as OI
 import paper_2506_18408_amd as P
 import workloads as W
 from tests.gpu_common import requires_gpu, to_dev, tvec, hist_close
@@ -45,3 +46,17 @@ def test_two_level_mixed_precision_reaches_tol():
     x, info = P.solve(*to_dev(A), tvec(b), mid_outer=4, precision="mixed", **prm)
     assert info["converged"] and info["true_rel_residual"] <= 1e-8 * (1 + 1e-6)
     assert info["total_inner"] >= sum(info["inner_k"])
+
+
+def test_two_level_with_ilu_matches_the_oracle():
+    """ILU(0) inside the lower level's sGMRES cycles: the top level factors A
+    once and every lower-level solve applies those factors."""
+    A, b = _sys()
+    prm = dict(m=12, t=2, s=48, zeta=8, tol=1e-9, seed=21, max_outer=60)
+    x, info = P.solve(*to_dev(A), tvec(b), mid_outer=3, precond="ilu0", **prm)
+    M = OI.ILU0(A.to_scipy(), "multicolor")
+    ref = oracle.sfgmres(A.to_scipy(), b, mid_outer=3, precond=M, **prm)
+    assert info["converged"] and ref.status == 0
+    assert list(info["inner_k"]) == ref.inner_k
+    hist_close(info["residual_history"], ref.residual_history)
+    assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)

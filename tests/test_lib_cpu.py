@@ -41,6 +41,7 @@ def test_default_options(lib):
     assert lib.sfgmres_default_options(C.byref(o)) == 0
     # cond_threshold 0 selects the precision's default (1e15 in FP64)
     assert o.precision == L.FP64 and o.max_outer == 100 and o.cond_threshold == 0.0
+    assert o.sketch_source == L.SKETCH_AUTO
     assert lib.sfgmres_default_options(None) == L.ERR_INVALID
 
 
