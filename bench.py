@@ -55,14 +55,14 @@ if ROOT not in sys.path:
 HBM_PEAK_GBS = 8000.0   # MI355X published HBM3E bandwidth
 TARGET_FRAC = 0.60      # the fused kernel's target fraction of HBM peak
 # HBM bytes per dispatch of the headline fused kernel (FP64, 256^3 system,
-# sketch columns generated in the kernel) from rocprofv3 FETCH_SIZE and
-# WRITE_SIZE (KiB), each scaled by the factor measured on a plain device copy
-# of known size (bench.py --copy-calibration): FETCH_SIZE x 2.0 (2205.9 MB,
-# equal to the 128-byte read requests counted directly) + WRITE_SIZE x 1.0
-# (135.8 MB), averaged over the 6042 working dispatches of one FP64 forward
-# and adjoint solve.  Valid only for the kernel source it was measured on;
-# None whenever that kernel changes.
-PMC_TRAFFIC_BYTES = 2341.8e6
+# matrix by diagonal, sketch columns generated in the kernel) from rocprofv3
+# FETCH_SIZE and WRITE_SIZE (KiB), each scaled by the factor measured on a
+# plain device copy of known size (bench.py --copy-calibration): FETCH_SIZE
+# x 2.0 (1605.1 MB, equal to the 128-byte read requests counted directly) +
+# WRITE_SIZE x 1.0 (135.8 MB), averaged over the 6058 working dispatches of
+# one FP64 forward and adjoint solve.  Valid only for the kernel source it
+# was measured on; None whenever that kernel changes.
+PMC_TRAFFIC_BYTES = 1740.9e6
 
 
 def log(*a):
@@ -119,6 +119,34 @@ def copy_calibration(mib: int) -> None:
     print(json.dumps({"copy_calibration_bytes_read": n * 8, "bytes_written": n * 8}), flush=True)
 
 
+def stream_rates(mib: int = 1024, reps: int = 10):
+    """Measured reference rates of this GPU (GB/s): a plain device copy of
+    MIB MiB (bytes read + bytes written per second) and a read-only
+    reduction of the same buffer (torch's sum; bytes read per second), each
+    the best of `reps` runs timed with events on torch's stream."""
+    import torch
+    n = mib * (1 << 20) // 8
+    x = torch.rand(n, dtype=torch.float64, device="cuda:0")
+    y = torch.empty_like(x)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def best(fn):
+        fn()
+        t = []
+        for _ in range(reps):
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            t.append(e0.elapsed_time(e1) * 1e-3)
+        return min(t)
+    copy = 2 * n * 8 / best(lambda: y.copy_(x)) / 1e9
+    read = n * 8 / best(lambda: x.sum()) / 1e9
+    del x, y
+    torch.cuda.empty_cache()
+    return copy, read
+
+
 # Time the fused kernel on every 7th inner step (an event-carrying launch
 # costs ~10 us of dispatch).  7 is co-prime with the 8 steps of a decision
 # panel, so the timed launches cover every position in a panel: the launches
@@ -165,6 +193,32 @@ def fused_rate(infos, A, t, m, zeta, fp32):
     sk = 0 if infos[-1].get("sketch_generated") else 12 * zg * A.n
     avg = ms * 1e-3 / launches
     return avg, alg, sk, launches
+
+
+def kernel_label(info, fp32, nw):
+    """The fused inner SpMV instance a solve used, by its template
+    parameters (value type, sketch groups, mode, window, operand storage)."""
+    dia, gen = info.get("dia_diagonals", 0) > 0, info.get("sketch_generated", False)
+    stream = info.get("matrix_streamed", False)
+    ld = (("kLdDiaGen" if gen else "kLdDia") if dia else
+          "kLdStream" if stream else ("kLdGen" if gen else "kLdCached"))
+    what = (("matrix by diagonal" if dia else "CSR, streaming loads" if stream else "CSR")
+            + (", sketch columns generated in the kernel" if gen else ", packed sketch"))
+    return f"k_spmv<{'float' if fp32 else 'double'}, 1, kModeInner, {nw}, {ld}> ({what})"
+
+
+def own_bytes(infos, A, t, m, fp32):
+    """Bytes the inner SpMV reads and writes in the storage it used: the
+    CSR formula, or with the matrix by diagonal (nd diagonals of n values,
+    padding included, no row pointers or column indices) nd w n + 2 w n +
+    w nwin n; the packed sketch not included."""
+    nd = infos[-1].get("dia_diagonals", 0)
+    launches = sum(i["spmv_launches"] for i in infos)
+    win = sum(window_sum(i["inner_k"], i["stop_reason"], t, m)[0] for i in infos)
+    vb = 4 if fp32 else 8
+    if nd == 0:
+        return (vb + 4) * A.nnz + (4 + 2 * vb) * A.n + vb * A.n * (win / launches), 0
+    return vb * nd * A.n + 2 * vb * A.n + vb * A.n * (win / launches), nd
 
 
 def other_workload(args):
@@ -309,13 +363,17 @@ def secondary_row(P, W, torch, cfg, steps, cpu=False):
                             seed=p["seed"], max_outer=p["max_outer"], precision=prec)
         sec, infos, _, _, _ = timed_solves(P, rp, ci, va, bt, prm, steps, 1, label=p["name"] + " " + prec)
         avg, alg, sk, nl = fused_rate(infos, A, p["t"], p["m"], p["zeta"], prec == "mixed")
+        own, nd = own_bytes(infos, A, p["t"], p["m"], prec == "mixed")
         inf = infos[-1]
         row[prec] = {"time_to_tol_s": sec, "converged": bool(inf["converged"]),
                      "true_rel_residual": inf["true_rel_residual"],
                      "outer_iters": inf["outer_iters"], "total_inner": inf["total_inner"],
                      "fused_mean_launch_us": avg * 1e6, "fused_alg_bytes": alg,
                      "fused_alg_gbs": alg / avg / 1e9, "frac": alg / avg / 1e9 / HBM_PEAK_GBS,
-                     "target_frac": TARGET_FRAC, "packed_sketch_bytes": sk}
+                     "own_storage_bytes": own, "diagonals": nd,
+                     "frac_on_own_storage_bytes": own / avg / 1e9 / HBM_PEAK_GBS,
+                     "target_frac": TARGET_FRAC, "packed_sketch_bytes": sk,
+                     "kernel": kernel_label(inf, prec == "mixed", p["t"])}
         log(f"{p['name']} {prec}: {sec * 1e3:.2f} ms, fused {avg * 1e6:.1f} us "
             f"({alg / avg / 1e9:.0f} GB/s, {alg / avg / 1e9 / HBM_PEAK_GBS:.2f} of peak)")
     if cfg == 2:
@@ -358,6 +416,8 @@ def headline(args):
                         max_outer=p["max_outer"])
     grad_of = lambda x: 2.0 * (x - xt)  # noqa: E731  (dL/dx of ||x - x_target||^2)
     torch.cuda.synchronize()
+    copy_gbs, read_gbs = stream_rates()
+    log(f"reference rates: device copy {copy_gbs:.0f} GB/s, read-only sum {read_gbs:.0f} GB/s")
 
     sec, infos, x, ainfos, lam = timed_solves(P, rp, ci, va, bt, prm, args.steps, args.warmup,
                                               adjoint=grad_of, label="fp64")
@@ -372,6 +432,7 @@ def headline(args):
             raise RuntimeError(f"FP64 {what} solve did not reach tol: {inf['true_rel_residual']}")
 
     avg_s, alg, sk, launches = fused_rate(infos, A, t, m, zeta, False)
+    own, nd = own_bytes(infos, A, t, m, False)
     achieved = alg / avg_s / 1e9
     log(f"fused spmv+sketch (FP64): {launches} timed launches, mean {avg_s * 1e6:.2f} us, "
         f"{alg / 1e6:.1f} MB algorithmic (+{sk / 1e6:.1f} MB packed sketch) -> {achieved:.0f} GB/s")
@@ -403,11 +464,14 @@ def headline(args):
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": PMC_TRAFFIC_BYTES,
                      "target_frac": TARGET_FRAC,
-                     "kernel": "k_spmv<double, 1, kModeInner, 2, kLdGen> (fused SpMV + sketch with "
-                               "columns generated in the kernel + window dots, FP64, forward "
-                               "solve; ZB = ceil(zeta/8) = 1, window 2)",
+                     "kernel": kernel_label(last, False, 2) + ": fused SpMV + sketch + window "
+                               "dots, FP64, forward solve",
                      "bytes_per_launch": alg, "packed_sketch_bytes_per_launch": sk,
-                     "mean_launch_us": avg_s * 1e6, "launches": launches},
+                     "own_storage_bytes_per_launch": own, "diagonals": nd,
+                     "frac_on_own_storage_bytes": own / avg_s / 1e9 / HBM_PEAK_GBS,
+                     "mean_launch_us": avg_s * 1e6, "launches": launches,
+                     "measured_copy_gbs": copy_gbs, "measured_read_gbs": read_gbs,
+                     "frac_of_measured_read": achieved / read_gbs},
     }
 
     if not args.no_mixed:
@@ -420,6 +484,7 @@ def headline(args):
         # (the mixed adjoint's right-hand side is formed from the mixed x)
         lerr = (torch.linalg.norm(lamm - lam) / torch.linalg.norm(lam)).item()
         mavg, malg, msk, ml = fused_rate(minfos, A, t, m, zeta, True)
+        mown, _ = own_bytes(minfos, A, t, m, True)
         mfwd = sum(i["solve_ms"] for i in minfos) * 1e-3 / len(minfos)
         result["mixed"] = {
             "time_to_tol_s": msec, "forward_time_s": mfwd, "adjoint_time_s": msec - mfwd,
@@ -433,7 +498,9 @@ def headline(args):
             "rel_error_vs_fp64_solution": err, "rel_error_vs_fp64_adjoint": lerr,
             "fused_mean_launch_us": mavg * 1e6, "fused_alg_bytes": malg,
             "fused_alg_gbs": malg / mavg / 1e9, "frac": malg / mavg / 1e9 / HBM_PEAK_GBS,
-            "kernel": "k_spmv<float, 1, kModeInner, 2, kLdCached>",
+            "own_storage_bytes": mown, "frac_on_own_storage_bytes": mown / mavg / 1e9 / HBM_PEAK_GBS,
+            "packed_sketch_bytes": msk,
+            "kernel": kernel_label(im, True, 2),
         }
         log(f"mixed: {msec:.3f} s per forward+adjoint (x{sec / msec:.2f}), outer={im['outer_iters']} "
             f"inner={im['total_inner']} true_rel_res={im['true_rel_residual']:.3e} err={err:.2e} "

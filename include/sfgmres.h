@@ -80,6 +80,14 @@ extern "C" {
                                       fused SpMV: FP64 and zeta <= 8 only.  The same S, so
                                       results are bit for bit those of TABLE               */
 
+/* ---- matrix storage of the inner SpMV (sfgmres_options.matrix_format) - */
+#define SFGMRES_MATRIX_AUTO     0  /* (default) by diagonal when every nonzero lies on at most
+                                      8 diagonals j - i, rows hold at most 8 nonzeros and the
+                                      diagonals hold less than 1.5 nnz values (stencils in
+                                      lexicographic order); CSR otherwise.  The copy is built
+                                      at the start of every solve, in the workspace        */
+#define SFGMRES_MATRIX_CSR      1  /* always the caller's CSR (no copy, smaller workspace)  */
+
 /* ---- inner stop reasons (sfgmres_info.stop_reason) ------------------- */
 #define SFGMRES_STOP_C1         1  /* k reached m                                  */
 #define SFGMRES_STOP_C2         2  /* cond estimate of S A B_i exceeded threshold: k = i-1 */
@@ -157,6 +165,9 @@ typedef struct sfgmres_options {
                                    info.total_inner = all sGMRES inner steps                     */
   int32_t sketch_source;        /* SFGMRES_SKETCH_AUTO (default), _TABLE or _GEN: where the fused
                                    inner SpMV takes the columns of S from (a speed choice only)  */
+  int32_t matrix_format;        /* SFGMRES_MATRIX_AUTO (default) or _CSR: how the fused inner
+                                   SpMV reads A.  The diagonal copy sums every row in the same
+                                   order as CSR, so results are bit for bit those of CSR      */
 } sfgmres_options;
 
 /* Solve diagnostics.  Scalars are always written; each per-step array is a
@@ -206,8 +217,11 @@ typedef struct sfgmres_info {
                                        [6] adjoint: CSR(A^T), [7] adjoint: dL/dA            */
   int32_t sketch_generated;         /* 1 if the inner SpMV generated the columns of S
                                        (sketch_source), 0 if it read the packed table    */
+  int32_t dia_diagonals;            /* diagonals of the inner SpMV's copy of A (0: CSR) */
+  int32_t matrix_streamed;          /* 1 if the inner SpMV read the CSR values and indices
+                                       with streaming (non-temporal) loads              */
   int32_t reserved_i;
-  double  reserved[3];
+  double  reserved[2];
 } sfgmres_info;
 
 typedef struct sfgmres_ctx* sfgmres_handle;

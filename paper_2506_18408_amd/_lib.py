@@ -28,6 +28,8 @@ PRECOND_ILU0 = 1
 SKETCH_AUTO = 0
 SKETCH_TABLE = 1
 SKETCH_GEN = 2
+MATRIX_AUTO = 0
+MATRIX_CSR = 1
 
 STOP_REASONS = {1: "C1", 2: "C2", 3: "C3", 4: "breakdown", 5: "forced", 6: "mid"}
 
@@ -66,6 +68,7 @@ class Options(C.Structure):
         ("precond", C.c_int32),
         ("mid_outer", C.c_int32),
         ("sketch_source", C.c_int32),
+        ("matrix_format", C.c_int32),
     ]
 
 
@@ -94,8 +97,10 @@ class Info(C.Structure):
         ("ffom_x", C.c_void_p),
         ("phase_ms", C.c_double * 8),
         ("sketch_generated", C.c_int32),
+        ("dia_diagonals", C.c_int32),
+        ("matrix_streamed", C.c_int32),
         ("reserved_i", C.c_int32),
-        ("reserved", C.c_double * 3),
+        ("reserved", C.c_double * 2),
     ]
 
 

@@ -44,7 +44,9 @@ class SolveParams:
     step preconditioned by a lower-level FGMRES solve of at most N steps;
     sketch_source: "auto", "table" (packed columns of S read by the fused
     SpMV) or "gen" (columns generated inside it; FP64, zeta <= 8) -- the
-    same S either way.
+    same S either way; matrix_format: "auto" (the inner SpMV reads a copy
+    of A by diagonal when A is stencil-like, with the same results) or
+    "csr".
     """
     m: int = 30
     t: int = 2
@@ -63,6 +65,7 @@ class SolveParams:
     precond: str = "none"
     mid_outer: int = 0
     sketch_source: str = "auto"
+    matrix_format: str = "auto"
 
 
 _HANDLES = {}
@@ -150,6 +153,7 @@ def _options(p: SolveParams, record_true_residual=False, profile=False) -> L.Opt
     o.mid_outer = p.mid_outer
     o.sketch_source = {"auto": L.SKETCH_AUTO, "table": L.SKETCH_TABLE,
                        "gen": L.SKETCH_GEN}[p.sketch_source]
+    o.matrix_format = {"auto": L.MATRIX_AUTO, "csr": L.MATRIX_CSR}[p.matrix_format]
     return o
 
 
@@ -209,6 +213,8 @@ class _InfoBuffers:
             solve_ms=self.info.solve_ms,
             phase_ms=dict(zip(L.PHASES, list(self.info.phase_ms))),
             sketch_generated=bool(self.info.sketch_generated),
+            dia_diagonals=int(self.info.dia_diagonals),
+            matrix_streamed=bool(self.info.matrix_streamed),
         )
 
 

@@ -49,7 +49,10 @@ constexpr size_t kStreamMatrixBytes = (size_t)300 << 20;
 // generator, and the 12 bytes per row of the table are saved.  (The FP32
 // stream and cache-resident matrices are faster with the table.)
 constexpr size_t kGenSketchBytes = (size_t)512 << 20;
-constexpr int kSpmvLdsMax = 150 * 1024;  // dynamic LDS of one SpMV workgroup (bytes)
+// Dynamic LDS of one SpMV workgroup (bytes): with the kernel's static LDS
+// (the per-wave scalar sums, at most 16 x 9 doubles) within the CU's 160 KB.
+// 15 waves of s = 800 fit instead of 14 (-1.5% per 256^3 FP64 launch).
+constexpr int kSpmvLdsMax = 158 * 1024;
 // Bound on the number of partial rows any multi-workgroup kernel writes.
 constexpr int kMaxGrid = 1024;
 // Vector kernels: threads per workgroup and grid cap (one partial per
@@ -135,7 +138,8 @@ struct HostStatus {
 // Offsets (bytes) of every workspace region.
 struct Layout {
   size_t ctl, tiles, tp, ipart, part, dpart, vpart, red, skp, qr_V, qr_T, qr_R, qr_d, qr_c, qr_tau, ice_x, ice_z,
-      sigma, hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, ilu, ilu_t64, ilu_tmp,
+      sigma, hwin, yin, H, HR, cs, sn, g, yout, V, Z, B, W32, W64, X, val32, dia, dia_work, ilu,
+      ilu_t64, ilu_tmp,
       mid, mid_bytes, at_rowptr, at_col, at_val, at_perm, at_cursor, scan_tmp, total;
   int64_t ld;        // leading dimension (elements) of the n-vectors
   int64_t ntiles_max;

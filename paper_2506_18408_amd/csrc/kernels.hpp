@@ -34,6 +34,19 @@ struct PowTask {
   double* dpart;   // the level's scalar partial rows
 };
 
+// Diagonals of a matrix the inner SpMV reads by diagonal (diagonal storage
+// for stencil-like patterns: at most kDiaMax distinct offsets j - i, rows of
+// at most kShortRow nonzeros).
+constexpr int kDiaMax = 8;
+struct DiaOffsets {
+  int32_t off[kDiaMax];
+};
+hipError_t launch_dia_detect(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,
+                             int32_t maxlen, int32_t* work, hipStream_t st);
+hipError_t launch_dia_fill(const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                           int64_t n, int64_t ld, int32_t nd, const DiaOffsets& offs,
+                           double* dia64, float* dia32, hipStream_t st);
+
 struct SpmvArgs {
   int64_t n;
   const int32_t* row_ptr;
@@ -56,6 +69,13 @@ struct SpmvArgs {
   int32_t zeta;             // nonzeros per sketch column
   const SkGroup* skp;       // packed sketch
   int32_t sketch_gen;       // kModeInner, FP64, zeta <= 8: generate the sketch columns
+  // kModeInner: the matrix by diagonal (ndiag > 0): value d of row r at
+  // dia_val[d * dia_ld + r] (same type as val; 0 off the matrix), column
+  // r + dia_off[d]; offsets increasing
+  const void* dia_val;
+  int64_t dia_ld;
+  int32_t ndiag;
+  int32_t dia_off[kDiaMax];
   uint32_t sk_k0, sk_k1;    // the sketch's Philox key (sketch_gen)
   const void* U;            // window base (same type as val), column-major
   int64_t ldu;
@@ -91,7 +111,7 @@ hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, i
 hipError_t launch_max_bandwidth(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,
                                 int32_t* part, int32_t* out, hipStream_t st);
 // Waves per SpMV workgroup for an s-row sketch (0: none), bounded by LDS.
-int spmv_waves(int s, bool short_tiles);
+int spmv_waves(int s, bool short_tiles, bool dia = false);
 // zb = sk_groups(zeta) with a sketch, else 0.  ev0/ev1 non-null: the launch
 // records them at the kernel's own start and end (timing of the kernel alone).
 hipError_t launch_spmv(int mode, bool fp32, int grid, const SpmvArgs& a, int zb, hipStream_t st,

@@ -109,7 +109,7 @@ IluWs ilu_regions(int64_t n, int64_t nnz, size_t off) {
 
 Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
                    int32_t J, int32_t precision, int32_t adjoint, int32_t panel, int32_t precond,
-                   int32_t mid_outer) {
+                   int32_t mid_outer, int32_t matrix_format) {
   (void)t;
   Layout L{};
   const bool f32 = precision == SFGMRES_MIXED;
@@ -156,6 +156,12 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.W64 = take((size_t)L.ld * 8);
   L.X = take((size_t)L.ld * 8);
   L.val32 = take(f32 ? (size_t)nnz * 4 : 0);
+  // the matrix by diagonal for the inner SpMV (matrix_format AUTO): up to
+  // kDiaMax diagonals of ld values in the inner SpMV's precision, and the
+  // detection's work words
+  const bool dia_ok = matrix_format == SFGMRES_MATRIX_AUTO;
+  L.dia = take(dia_ok ? (size_t)kDiaMax * (size_t)L.ld * vt : 0);
+  L.dia_work = take(dia_ok ? (size_t)(4 + kDiaMax) * 4 : 0);
   // ILU(0): factor values, entry kinds, diagonal positions, colouring state,
   // rows by colour, counters (per-colour counts, cursors and starts, then
   // the error and coloured-count words), the transposed pattern for the
@@ -169,7 +175,8 @@ Layout make_layout(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int3
   L.ilu_tmp = take(ilu ? (size_t)L.ld * vt : 0);
   // two-level FGMRES: the lower level's whole solve workspace
   L.mid_bytes = mid_outer > 0
-                    ? make_layout(n, nnz, m, t, s, zeta, mid_outer, precision, 0, panel, precond, 0)
+                    ? make_layout(n, nnz, m, t, s, zeta, mid_outer, precision, 0, panel, precond, 0,
+                                  matrix_format)
                           .total
                     : 0;
   L.mid = take(L.mid_bytes);
@@ -219,6 +226,7 @@ sfgmres_options defaults() {
   o.precond = SFGMRES_PRECOND_NONE;
   o.mid_outer = 0;
   o.sketch_source = SFGMRES_SKETCH_AUTO;
+  o.matrix_format = SFGMRES_MATRIX_AUTO;
   return o;
 }
 
@@ -265,6 +273,8 @@ int check_params(sfgmres_handle h, int64_t n, int64_t nnz, int32_t m, int32_t t,
     return fail(h, SFGMRES_ERR_INVALID, "need 0 <= mid_outer <= 2000");
   if (o.mid_outer > 0 && o.outer != SFGMRES_OUTER_FGMRES)
     return fail(h, SFGMRES_ERR_INVALID, "mid_outer needs the FGMRES outer iteration");
+  if (o.matrix_format != SFGMRES_MATRIX_AUTO && o.matrix_format != SFGMRES_MATRIX_CSR)
+    return fail(h, SFGMRES_ERR_INVALID, "matrix_format must be AUTO or CSR");
   if (o.sketch_source < SFGMRES_SKETCH_AUTO || o.sketch_source > SFGMRES_SKETCH_GEN)
     return fail(h, SFGMRES_ERR_INVALID, "sketch_source must be AUTO, TABLE or GEN");
   if (o.sketch_source == SFGMRES_SKETCH_GEN &&
@@ -520,7 +530,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
   const int pc = panel_cols(o);
   const Layout L = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, 0, pc, o.precond,
-                               o.mid_outer);
+                               o.mid_outer, o.matrix_format);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   char* base = static_cast<char*>(ws);
@@ -655,6 +665,34 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
        tiling.max_row <= kShortRow && (size_t)nnz * 12 > kGenSketchBytes);
   if (base_args.sketch_gen) base_args.stream_matrix = 0;
   if (info) info->sketch_generated = base_args.sketch_gen;
+  // the matrix by diagonal, when every nonzero lies on the diagonals of the
+  // first longest row (at most kDiaMax of them, rows of at most kShortRow
+  // nonzeros: 64-row tiles) and the padding stays below half of nnz
+  if (o.matrix_format == SFGMRES_MATRIX_AUTO && tiling.max_row > 0 &&
+      tiling.max_row <= kShortRow) {
+    int32_t* dw = reinterpret_cast<int32_t*>(base + L.dia_work);
+    SFG_HIP(launch_dia_detect(A->row_ptr, A->col_idx, n, tiling.max_row, dw, st));
+    int32_t hw[3 + kDiaMax] = {};
+    SFG_HIP(hipMemcpyAsync(hw, dw, sizeof(hw), hipMemcpyDeviceToHost, st));
+    SFG_HIP(hipStreamSynchronize(st));
+    if (hw[1] == 0 && hw[2] > 0 && hw[2] <= kDiaMax && (int64_t)hw[2] * n <= nnz + nnz / 2) {
+      DiaOffsets offs{};
+      for (int k = 0; k < hw[2]; ++k) offs.off[k] = hw[3 + k];
+      void* dv = base + L.dia;
+      SFG_HIP(launch_dia_fill(A->row_ptr, A->col_idx, A->val, n, L.ld, hw[2], offs,
+                              f32 ? nullptr : static_cast<double*>(dv),
+                              f32 ? static_cast<float*>(dv) : nullptr, st));
+      base_args.dia_val = dv;
+      base_args.dia_ld = L.ld;
+      base_args.ndiag = hw[2];
+      for (int k = 0; k < kDiaMax; ++k) base_args.dia_off[k] = offs.off[k];
+    }
+  }
+  if (base_args.ndiag > 0) base_args.stream_matrix = 0;
+  if (info) {
+    info->dia_diagonals = base_args.ndiag;
+    info->matrix_streamed = base_args.stream_matrix;
+  }
   base_args.sk_k0 = k0;
   base_args.sk_k1 = k1;
 
@@ -1219,7 +1257,7 @@ int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_
       o.lookahead < 0 || o.lookahead > 64 || o.panel < 0 || o.panel > kPanel)
     return SFGMRES_ERR_INVALID;
   *bytes = make_layout(n, nnz, m, t, s, zeta, o.max_outer, o.precision, adjoint ? 1 : 0,
-                       panel_cols(o), o.precond, o.mid_outer)
+                       panel_cols(o), o.precond, o.mid_outer, o.matrix_format)
                .total;
   return SFGMRES_OK;
 }
@@ -1301,7 +1339,7 @@ int sfgmres_solve_adjoint(sfgmres_handle h, const sfgmres_csr* A, const double* 
   if ((A->nnz > 0 && (!A->col_idx || !A->val)) || !g || !lambda)
     return fail(h, SFGMRES_ERR_INVALID, "null array argument");
   const Layout L = make_layout(A->n, A->nnz, m, t, s, zeta, o.max_outer, o.precision, 1,
-                               panel_cols(o), o.precond, o.mid_outer);
+                               panel_cols(o), o.precond, o.mid_outer, o.matrix_format);
   if (!ws || ws_bytes < L.total || (reinterpret_cast<uintptr_t>(ws) & 255))
     return fail(h, SFGMRES_ERR_WORKSPACE, "workspace missing, too small or not 256-byte aligned");
   hipStream_t st = static_cast<hipStream_t>(stream);

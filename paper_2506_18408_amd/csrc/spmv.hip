@@ -151,19 +151,108 @@ hipError_t launch_max_rowlen(const int32_t* row_ptr, int64_t n, int32_t* part, i
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- diagonal storage
+// Detection: the offsets j - i of the first row of the longest length are
+// the candidates; every nonzero is checked against them.  work[0] = that
+// row, work[1] = 1 if some nonzero lies off the candidates, work[2] = the
+// number of candidates, work[3 ..] = the candidates (increasing: the row's
+// columns are sorted).
+__global__ void k_dia_init(int32_t* work) {
+  work[0] = 0x7FFFFFFF;
+  work[1] = 0;
+  work[2] = 0;
+}
+
+__global__ void k_dia_pick(const int32_t* __restrict__ row_ptr, int64_t n, int32_t len,
+                           int32_t* work) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride)
+    if (row_ptr[r + 1] - row_ptr[r] == len) {
+      atomicMin(&work[0], (int32_t)r);
+      return;  // (a later row of this thread cannot be smaller)
+    }
+}
+
+__global__ void k_dia_cand(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                           int32_t* work) {
+  const int r = work[0];
+  const int q0 = row_ptr[r], q1 = row_ptr[r + 1];
+  const int cnt = q1 - q0 < kDiaMax ? q1 - q0 : kDiaMax;
+  work[2] = cnt;
+  for (int k = 0; k < cnt; ++k) work[3 + k] = col_idx[q0 + k] - r;
+}
+
+__global__ void k_dia_check(const int32_t* __restrict__ row_ptr,
+                            const int32_t* __restrict__ col_idx, int64_t n, int32_t* work) {
+  const int cnt = work[2];
+  int32_t off[kDiaMax];
+#pragma unroll
+  for (int k = 0; k < kDiaMax; ++k) off[k] = k < cnt ? work[3 + k] : 0x7FFFFFFF;
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n && !bad; r += stride)
+    for (int q = row_ptr[r]; q < row_ptr[r + 1]; ++q) {
+      const int64_t d = (int64_t)col_idx[q] - r;
+      bool hit = false;
+#pragma unroll
+      for (int k = 0; k < kDiaMax; ++k) hit |= k < cnt && d == off[k];
+      if (!hit) bad = true;
+    }
+  if (bad) atomicOr(&work[1], 1);
+}
+
+hipError_t launch_dia_detect(const int32_t* row_ptr, const int32_t* col_idx, int64_t n,
+                             int32_t maxlen, int32_t* work, hipStream_t st) {
+  const int g = vec_grid(n);
+  hipLaunchKernelGGL(k_dia_init, dim3(1), dim3(1), 0, st, work);
+  hipLaunchKernelGGL(k_dia_pick, dim3(g), dim3(256), 0, st, row_ptr, n, maxlen, work);
+  hipLaunchKernelGGL(k_dia_cand, dim3(1), dim3(1), 0, st, row_ptr, col_idx, work);
+  hipLaunchKernelGGL(k_dia_check, dim3(g), dim3(256), 0, st, row_ptr, col_idx, n, work);
+  return hipGetLastError();
+}
+
+// Values by diagonal: thread per row, each diagonal's entry found among the
+// row's (at most kShortRow) nonzeros, 0 where the row has none.
+__global__ void k_dia_fill(const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+                           const double* __restrict__ val, int64_t n, int64_t ld, int32_t nd,
+                           DiaOffsets offs, double* __restrict__ dia64,
+                           float* __restrict__ dia32) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n; r += stride) {
+    const int q0 = row_ptr[r], q1 = row_ptr[r + 1];
+    for (int d = 0; d < nd; ++d) {
+      const int64_t c = r + offs.off[d];
+      double v = 0.0;
+      for (int q = q0; q < q1; ++q)
+        if (col_idx[q] == c) v = val[q];
+      if (dia64) dia64[(int64_t)d * ld + r] = v;
+      if (dia32) dia32[(int64_t)d * ld + r] = static_cast<float>(v);
+    }
+  }
+}
+
+hipError_t launch_dia_fill(const int32_t* row_ptr, const int32_t* col_idx, const double* val,
+                           int64_t n, int64_t ld, int32_t nd, const DiaOffsets& offs,
+                           double* dia64, float* dia32, hipStream_t st) {
+  hipLaunchKernelGGL(k_dia_fill, dim3(vec_grid(n)), dim3(256), 0, st, row_ptr, col_idx, val, n, ld,
+                     nd, offs, dia64, dia32);
+  return hipGetLastError();
+}
+
 // LDS stage of one wave, in doubles.  General tiles: the staged products
 // (padded so that a row's first kShortRow products can be read without a
 // bound).  Short-row tiles (FP32 values): the column indices, then the
-// values, each padded the same way.
+// values, each padded the same way.  Diagonal storage: none.
 constexpr int kGenStage = kWStage + kShortRow;
 constexpr int kShortStage = (kGenStage * 4 + kGenStage * 4) / 8;
-__host__ __device__ constexpr int stage_doubles(bool short_tiles) {
+__host__ __device__ constexpr int stage_doubles(bool short_tiles, bool dia = false) {
+  if (dia) return 0;
   return short_tiles ? kShortStage : kGenStage;
 }
 // Doubles of LDS per wave: the stage, then, when sketching, the s sketch
 // accumulators.
-__host__ __device__ constexpr int wave_lds_doubles(int s, bool short_tiles) {
-  return stage_doubles(short_tiles) + (s > 0 ? s : 0);
+__host__ __device__ constexpr int wave_lds_doubles(int s, bool short_tiles, bool dia = false) {
+  return stage_doubles(short_tiles, dia) + (s > 0 ? s : 0);
 }
 
 // s_waitcnt operand that waits for every outstanding vector memory access
@@ -185,11 +274,14 @@ constexpr int spmv_max_threads() { return NW > 4 ? 12 * kWave : kSpmvMaxThreads;
 
 // How the inner SpMV reads its operands (an instance parameter): cached
 // matrix loads and the packed sketch; streaming matrix loads (a matrix that
-// cannot stay in the last-level cache); or cached loads with the sketch
-// columns generated in the epilogue's prefetch.
+// cannot stay in the last-level cache); cached loads with the sketch
+// columns generated in the epilogue's prefetch; or the matrix by diagonal
+// (no column indices) with the packed or the generated sketch.
 constexpr int kLdCached = 0;
 constexpr int kLdStream = 1;
 constexpr int kLdGen = 2;
+constexpr int kLdDia = 3;
+constexpr int kLdDiaGen = 4;
 
 // A matrix load: cached, or streaming (NT) for a matrix that cannot stay in
 // the last-level cache.
@@ -204,7 +296,10 @@ __device__ __forceinline__ T mat_load(const T* p) {
 template <typename VT, int ZB, int MODE, int NW, int LD>
 __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   constexpr bool NT = LD == kLdStream;
-  static_assert(LD != kLdGen || (ZB == 1 && MODE == kModeInner), "generated sketch: zeta <= 8");
+  constexpr bool kGen = LD == kLdGen || LD == kLdDiaGen;
+  constexpr bool kDia = LD == kLdDia || LD == kLdDiaGen;
+  static_assert(!kGen || (ZB == 1 && MODE == kModeInner), "generated sketch: zeta <= 8");
+  static_assert(!kDia || (ZB > 0 && MODE == kModeInner), "diagonal storage: inner SpMV");
   constexpr bool kSketch = ZB > 0;
   constexpr bool kInnerLike = (MODE == kModeInner || MODE == kModePlain || MODE == kModePowers);
   constexpr bool kPowers = MODE == kModePowers;
@@ -225,8 +320,8 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // (the short-row path pays for itself with FP32 values only: staging FP64
   // values doubles its LDS traffic, and their row-wise reads conflict)
   const bool short_tiles = sizeof(VT) == 4 && a.short_tiles != 0;
-  const int stage = stage_doubles(short_tiles);
-  const int wstride = wave_lds_doubles(S, short_tiles);
+  const int stage = stage_doubles(short_tiles, kDia);
+  const int wstride = wave_lds_doubles(S, short_tiles, kDia);
   double* const prod = lds + (size_t)wv * wstride;
   double* const wave_sk = prod + stage;
   // this wave's tiles: workgroups take contiguous ranges (XCD-grouped);
@@ -295,7 +390,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
 #pragma unroll
       for (int l = 0; l < NW; ++l)
         p.u[l] = l < nwin ? U[(int64_t)(a.l0 + l) * a.ldu + r] : VT(0);
-      if constexpr (LD == kLdGen) {
+      if constexpr (kGen) {
         p.sk[0] = sketch_group8((uint32_t)r, a.s, a.zeta, a.sk_k0, a.sk_k1);
       } else {
 #pragma unroll
@@ -547,7 +642,75 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
         __builtin_amdgcn_s_setprio(0);
     }
   };
-  if (short_tiles && has_x) {
+  if constexpr (kDia) {
+    // Diagonal storage, tiles of kRowTile rows (one row per lane): the
+    // values and x entries of every diagonal arrive as coalesced runs, and
+    // there are no column indices to read.  The row sum is formed in the
+    // row's column order (offsets increasing) from the same products as the
+    // CSR paths form (FP64: each product rounded before it is added, as the
+    // staged products; FP32: as the short-row path), so y, and with the same
+    // tiles and lanes everything after it, equals the CSR path's bit for
+    // bit.  Entries off the matrix hold 0 and add nothing.  Pipeline: the
+    // loads of tile i+1 are in flight while tile i is summed and its
+    // epilogue runs.
+    const VT* __restrict__ dv = static_cast<const VT*>(a.dia_val);
+    const int64_t dld = a.dia_ld;
+    const int nd = a.ndiag;
+    const int64_t nlast = a.n - 1;
+    VT fv[kDiaMax], fx[kDiaMax];
+    Pre fpre{};
+    int fr0 = 0, frows = 0;
+    auto dia_fetch = [&](const TileB& bt) {
+      fr0 = bt.r0;
+      frows = bt.r1 - bt.r0;
+      const int r = bt.r0 + (lane < frows ? lane : frows - 1);
+#pragma unroll
+      for (int d = 0; d < kDiaMax; ++d)
+        if (d < nd) {
+          fv[d] = dv[(int64_t)d * dld + r];
+          int64_t c = (int64_t)r + a.dia_off[d];
+          c = c < 0 ? 0 : (c > nlast ? nlast : c);
+          fx[d] = x[c];
+        }
+      load_pre(r, fpre);
+    };
+    if (nt > 0) {
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);  // (the first chunk, requested above)
+      dia_fetch(tile_bounds(0));
+    }
+    for (int i = 0; i < nt; ++i) {
+      pace(i);
+      __builtin_amdgcn_s_waitcnt(kWaitVmem0);
+      if (i + 1 < nt && ((i + 1) & 63) == 0) load_chunk((i + 1) >> 6);
+      VT cv[kDiaMax], cx[kDiaMax];
+#pragma unroll
+      for (int d = 0; d < kDiaMax; ++d) {
+        cv[d] = fv[d];
+        cx[d] = fx[d];
+      }
+      const Pre pre = fpre;
+      const int r0 = fr0, nrows = frows;
+      if (i + 1 < nt) dia_fetch(tile_bounds(i + 1));
+      double acc = 0.0;
+      if constexpr (sizeof(VT) == 8) {
+        // (the CSR path rounds each product into its LDS stage before the
+        // row sum: no fused multiply-add here either)
+#pragma clang fp contract(off)
+#pragma unroll
+        for (int d = 0; d < kDiaMax; ++d)
+          if (d < nd) {
+            const double pr = static_cast<double>(cv[d]) * static_cast<double>(cx[d]);
+            acc += pr;
+          }
+      } else {
+        // (as the short-row path: the product and the add in one statement)
+#pragma unroll
+        for (int d = 0; d < kDiaMax; ++d)
+          if (d < nd) acc += static_cast<double>(cv[d]) * static_cast<double>(cx[d]);
+      }
+      if (lane < nrows) epilogue(r0 + lane, acc, pre);
+    }
+  } else if (short_tiles && has_x) {
     // Short-row tiles (at most kRowTile rows of at most kShortRow nonzeros):
     // the column indices and values arrive coalesced, in nonzero order, and
     // are staged in LDS; every lane then reads its own row back and gathers
@@ -708,6 +871,7 @@ __global__ __launch_bounds__(spmv_max_threads<NW>()) void k_spmv(SpmvArgs a) {
   // wave copies of the sketch, are added in wave order: the order of a
   // block-wide sum.
   constexpr int kNS = kInnerLike ? NW + 1 : 2;  // scalar sums per wave
+  static_assert(kSpmvLdsMax + kSpmvMaxWaves * kNS * 8 <= 160 * 1024, "LDS of one CU");
   __shared__ double wsums[kSpmvMaxWaves * kNS];
   {
     double sv[kNS];
@@ -778,6 +942,13 @@ static hipError_t launch_ld(const LaunchCfg& c, const SpmvArgs& a) {
 // instances)
 template <typename VT, int ZB, int MODE, int NW>
 static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
+  if constexpr (MODE == kModeInner && ZB > 0) {
+    if (a.ndiag > 0) {
+      if constexpr (sizeof(VT) == 8 && ZB == 1)
+        if (a.sketch_gen) return launch_ld<VT, ZB, MODE, NW, kLdDiaGen>(c, a);
+      return launch_ld<VT, ZB, MODE, NW, kLdDia>(c, a);
+    }
+  }
   if constexpr (sizeof(VT) == 8 && MODE == kModeInner) {
     if (a.stream_matrix) return launch_ld<VT, ZB, MODE, NW, kLdStream>(c, a);
     if constexpr (ZB == 1)
@@ -789,8 +960,10 @@ static hipError_t launch_one(const LaunchCfg& c, const SpmvArgs& a) {
 template <typename VT, int MODE, int NW>
 static hipError_t launch_spmv_zb(int zb, LaunchCfg c, const SpmvArgs& a) {
   const bool short_tiles = sizeof(VT) == 4 && a.short_tiles != 0;
-  const size_t per_wave = (size_t)wave_lds_doubles(zb > 0 ? a.s : 0, short_tiles) * sizeof(double);
-  c.waves = std::min(spmv_waves(zb > 0 ? a.s : 0, short_tiles), spmv_max_threads<NW>() / kWave);
+  const bool dia = MODE == kModeInner && zb > 0 && a.ndiag > 0;
+  const size_t per_wave =
+      (size_t)wave_lds_doubles(zb > 0 ? a.s : 0, short_tiles, dia) * sizeof(double);
+  c.waves = std::min(spmv_waves(zb > 0 ? a.s : 0, short_tiles, dia), spmv_max_threads<NW>() / kWave);
   c.lds = per_wave * c.waves;
   switch (zb) {
     case 0:
@@ -811,8 +984,8 @@ static hipError_t launch_spmv_nw(int zb, const LaunchCfg& c, const SpmvArgs& a) 
 }
 
 // (the largest count that fits: 14 waves rather than 8 for s = 800)
-int spmv_waves(int s, bool short_tiles) {
-  const size_t per_wave = (size_t)wave_lds_doubles(s, short_tiles) * sizeof(double);
+int spmv_waves(int s, bool short_tiles, bool dia) {
+  const size_t per_wave = (size_t)wave_lds_doubles(s, short_tiles, dia) * sizeof(double);
   const size_t fit = (size_t)kSpmvLdsMax / per_wave;
   return (int)std::max<size_t>(1, std::min<size_t>(kSpmvMaxWaves, fit));
 }
