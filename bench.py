@@ -78,7 +78,9 @@ def parse():
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-precision comparison")
     ap.add_argument("--no-secondary", action="store_true",
                     help="skip the 128^3 and power-law rows of the benchmark line")
-    ap.add_argument("--workload", type=int, default=5, choices=[2, 3, 4, 5],
+    ap.add_argument("--matrix-format", default=None, choices=["auto", "csr"],
+                    help="the inner SpMV's storage of A (--info runs; default auto)")
+    ap.add_argument("--workload", type=int, default=5, choices=[1, 2, 3, 4, 5],
                     help="5 = the benchmark line (256^3, forward + adjoint, FP64 vs mixed); "
                          "2 = 128^3, 3 = 1M power-law, 4 = 512^2 parameterised operator: "
                          "informational timings of the other workloads")
@@ -259,6 +261,8 @@ def other_workload(args):
             prm.precond = args.precond
         if args.mid_outer is not None:
             prm.mid_outer = args.mid_outer
+        if args.matrix_format is not None:
+            prm.matrix_format = args.matrix_format
         x = torch.empty_like(bt)
         for _ in range(args.warmup):
             P.solve(rp, ci, va, bt, params=prm, out=x)

@@ -701,15 +701,37 @@ hipError_t launch_copy_or_zero(const double* src, double* dst, int64_t n, hipStr
   return hipGetLastError();
 }
 
-// grad[p] = -lam[row(p)] * x[col(p)]
-__global__ void k_gradient(const int32_t* __restrict__ row_ptr,
-                           const int32_t* __restrict__ col_idx, int64_t n,
-                           const double* __restrict__ lam, const double* __restrict__ x,
-                           double* __restrict__ grad) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-    const double li = lam[i];
-    for (int p = row_ptr[i]; p < row_ptr[i + 1]; ++p) grad[p] = -li * x[col_idx[p]];
+// grad[p] = -lam[row(p)] * x[col(p)].  A workgroup takes kVecThreads rows
+// at a time: their bounds in LDS, then the rows' nonzeros (one contiguous
+// range) one per thread, each thread finding its row by binary search over
+// the bounds, so that the column indices are read and the gradient written
+// in whole runs.
+__global__ __launch_bounds__(kVecThreads) void k_gradient(const int32_t* __restrict__ row_ptr,
+                                                          const int32_t* __restrict__ col_idx,
+                                                          int64_t n, const double* __restrict__ lam,
+                                                          const double* __restrict__ x,
+                                                          double* __restrict__ grad) {
+  __shared__ int32_t rb[kVecThreads + 1];
+  for (int64_t r0 = (int64_t)blockIdx.x * kVecThreads; r0 < n;
+       r0 += (int64_t)gridDim.x * kVecThreads) {
+    const int nr = (int)(n - r0 < kVecThreads ? n - r0 : kVecThreads);
+    const int64_t rr = r0 + threadIdx.x;
+    rb[threadIdx.x] = row_ptr[rr < n ? rr : n];
+    if (threadIdx.x == 0) rb[kVecThreads] = row_ptr[r0 + kVecThreads < n ? r0 + kVecThreads : n];
+    __syncthreads();
+    const int p0 = rb[0], p1 = rb[nr];
+    for (int p = p0 + threadIdx.x; p < p1; p += kVecThreads) {
+      int lo = 0, hi = nr;  // the row: the last k with rb[k] <= p
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rb[mid] <= p)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      grad[p] = -lam[r0 + lo] * x[col_idx[p]];
+    }
+    __syncthreads();
   }
 }
 
@@ -895,10 +917,88 @@ hipError_t launch_exclusive_scan(int32_t* cnt, int64_t n, int32_t* scan_tmp, hip
   return hipGetLastError();
 }
 
+// A pattern equal to its transpose (every stencil): row c of A^T has the
+// columns of row c of A, so the transpose needs no counting or sorting;
+// entry q = (c, r) of A^T takes the value of entry (r, c) of A, found in row
+// r (a linear scan of a short row, else a binary search; perm[q] = its
+// position).  *bad is set when a mirror entry is missing or a row's columns
+// are not increasing; the caller then builds the transpose the general way,
+// which overwrites everything.
+__global__ __launch_bounds__(kVecThreads) void k_transpose_sym(
+    const int32_t* __restrict__ row_ptr, const int32_t* __restrict__ col_idx,
+    const double* __restrict__ val, int64_t n, int32_t* __restrict__ rp_t,
+    int32_t* __restrict__ col_t, double* __restrict__ val_t, int32_t* __restrict__ perm,
+    int32_t* bad) {
+  // (a workgroup takes kVecThreads rows at a time, their bounds in LDS, and
+  // their nonzeros one per thread, so that every array is read and written
+  // in whole runs)
+  __shared__ int32_t rb[kVecThreads + 1];
+  bool ok = true;
+  for (int64_t r0 = (int64_t)blockIdx.x * kVecThreads; r0 < n;
+       r0 += (int64_t)gridDim.x * kVecThreads) {
+    const int nr = (int)(n - r0 < kVecThreads ? n - r0 : kVecThreads);
+    const int64_t rr = r0 + threadIdx.x;
+    const int32_t b = row_ptr[rr < n ? rr : n];
+    rb[threadIdx.x] = b;
+    if (rr < n) rp_t[rr] = b;
+    if (threadIdx.x == 0 && r0 + nr == n) rp_t[n] = row_ptr[n];
+    if (threadIdx.x == 0) rb[kVecThreads] = row_ptr[r0 + kVecThreads < n ? r0 + kVecThreads : n];
+    __syncthreads();
+    const int q0 = rb[0], q1 = rb[nr];
+    for (int q = q0 + threadIdx.x; q < q1; q += kVecThreads) {
+      int lo = 0, hi = nr;  // the row: the last k with rb[k] <= q
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rb[mid] <= q)
+          lo = mid;
+        else
+          hi = mid;
+      }
+      const int c = (int)(r0 + lo);
+      const int r = col_idx[q];
+      ok &= q == rb[lo] || col_idx[q - 1] < r;
+      col_t[q] = r;
+      const int a0 = row_ptr[r], a1 = row_ptr[r + 1];
+      int p = -1;
+      if (a1 - a0 <= kShortRow) {
+        // (a short row: its columns requested together)
+#pragma unroll
+        for (int k = 0; k < kShortRow; ++k)
+          if (a0 + k < a1 && col_idx[a0 + k] == c) p = a0 + k;
+      } else {
+        int l = a0, h = a1;
+        while (l < h) {
+          const int mid = (l + h) >> 1;
+          if (col_idx[mid] < c)
+            l = mid + 1;
+          else
+            h = mid;
+        }
+        if (l < a1 && col_idx[l] == c) p = l;
+      }
+      ok &= p >= 0;
+      p = p >= 0 ? p : q;
+      perm[q] = p;
+      if (val_t) val_t[q] = val[p];
+    }
+    __syncthreads();
+  }
+  if (!ok) atomicOr(bad, 1);
+}
+
 hipError_t launch_transpose(const int32_t* row_ptr, const int32_t* col_idx, const double* val,
                             int64_t n, int64_t nnz, int32_t* rp_t, int32_t* col_t,
                             double* val_t, int32_t* perm, int32_t* cursor, int32_t* scan_tmp,
                             hipStream_t st) {
+  // (cursor[0] holds the flag of the symmetric-pattern attempt)
+  hipLaunchKernelGGL(k_zero_i32, dim3(1), dim3(kVecThreads), 0, st, cursor, (int64_t)1);
+  hipLaunchKernelGGL(k_transpose_sym, dim3(vec_grid(n)), dim3(kVecThreads), 0, st, row_ptr,
+                     col_idx, val, n, rp_t, col_t, val_t, perm, cursor);
+  int32_t bad = 1;
+  hipError_t e = hipMemcpyAsync(&bad, cursor, sizeof(int32_t), hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  if (e != hipSuccess) return e;
+  if (!bad) return hipGetLastError();
   const int g = vec_grid(n + 1);
   hipLaunchKernelGGL(k_zero_i32, dim3(g), dim3(kVecThreads), 0, st, cursor, n + 1);
   hipLaunchKernelGGL(k_count_cols, dim3(vec_grid(nnz > 0 ? nnz : 1)), dim3(kVecThreads), 0, st,
