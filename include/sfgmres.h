@@ -235,8 +235,11 @@ int sfgmres_default_options(sfgmres_options* opt);
  * sketch column under *opt (NULL = defaults).  Writes the size to *bytes.
  * The workspace holds, among others, the inner basis (n x (m+1), float64 or
  * float32), the outer bases V and Z (n x (max_outer+1) each, float64), the
- * packed sketch (12 ceil(zeta/8) bytes per column of S) and, for the adjoint,
- * CSR(A^T). */
+ * packed sketch (12 ceil(zeta/8) bytes per column of S), with matrix_format
+ * AUTO room for the matrix by diagonal (8 diagonals of n values in the inner
+ * SpMV's precision), with precond ILU0 the factors and their colour-ordered
+ * copy, with mid_outer the lower level's whole workspace and, for the
+ * adjoint, CSR(A^T). */
 int sfgmres_workspace_bytes(int64_t n, int64_t nnz, int32_t m, int32_t t, int32_t s, int32_t zeta,
                             const sfgmres_options* opt, int32_t adjoint, size_t* bytes);
 
