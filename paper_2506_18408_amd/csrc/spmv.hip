@@ -1,9 +1,10 @@
-// Fused CSR SpMV kernels: y = A u with the sketch S y, the truncated-Arnoldi
+// Fused SpMV kernels: y = A u with the sketch S y, the truncated-Arnoldi
 // dot products and the squared norm computed in the same pass (the inner
 // step of sketched GMRES, Section 3 with the sketch and truncated Arnoldi of
 // Section 4.1), plus the outer-loop variants of Algorithm 1 (A z_j with the
 // first Gram-Schmidt dot; the initial residual b - A x0; a true residual),
-// and the generation of the packed sketch.
+// the generation of the packed sketch, and the detection and copy of a
+// matrix whose nonzeros lie on a few diagonals.
 //
 // Design (gfx950): a persistent grid of at most one workgroup per CU (248:
 // one CU per XCD stays free for the decision kernel on its own stream), of
@@ -17,10 +18,13 @@
 // wave waits once per tile.  General tiles stage their products in the
 // wave's own LDS region and reduce each row with a group of 1..64 lanes;
 // short-row tiles with FP32 values stage indices and values instead and
-// let every lane gather x for its own row.  The row's lane then runs the
+// let every lane gather x for its own row; a matrix copied by diagonal is
+// read without indices, one row per lane, every diagonal's values and x
+// entries as coalesced runs.  The row's lane then runs the
 // epilogue: store, scatter +-y_r into the wave's own LDS sketch
 // accumulators (the zeta rows and signs of column r of S come from the
-// packed sketch) and accumulate the dot products in registers.  At the end
+// packed sketch, or are generated) and accumulate the dot products in
+// registers.  At the end
 // the workgroup adds its wave copies in wave order and writes one row of
 // sketch partials and one row of scalar partials; later kernels combine the
 // rows in a fixed order, so results do not depend on timing.  Waves lower
