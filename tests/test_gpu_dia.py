@@ -111,3 +111,14 @@ def test_matrix_format_is_checked():
     A, b, _ = _system("convdiff2d_64")
     with pytest.raises(KeyError):
         P.solve(*to_dev(A), tvec(b), m=30, t=2, s=90, matrix_format="ell")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("name", ["convdiff2d_64", "convdiff3d_10", "varcoef3d_16"])
+def test_ilu_preconditioned_solve_by_diagonal_equals_csr_bit_for_bit(name, precision):
+    """ILU(0) right preconditioning: the inner SpMV reads M^{-1} u_i, by
+    diagonal or through CSR, with the same results."""
+    A, b, _ = _system(name)
+    out = _pair(A, b, m=30, t=2, s=90, zeta=8, tol=1e-10, seed=13, max_outer=15,
+                precision=precision, precond="ilu0")
+    _same(out)
