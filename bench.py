@@ -475,7 +475,7 @@ def headline(args):
                      "frac_on_own_storage_bytes": own / avg_s / 1e9 / HBM_PEAK_GBS,
                      "mean_launch_us": avg_s * 1e6, "launches": launches,
                      "measured_copy_gbs": copy_gbs, "measured_read_gbs": read_gbs,
-                     "frac_of_measured_read": achieved / read_gbs},
+                     "own_storage_rate_of_measured_read": own / avg_s / 1e9 / read_gbs},
     }
 
     if not args.no_mixed:
