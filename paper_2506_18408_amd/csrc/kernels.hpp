@@ -251,8 +251,11 @@ inline int64_t ilu_chunks(int64_t n) { return (n + kIluChunk - 1) / kIluChunk; }
 // Factors for the triangular solves, by position p in the colour order
 // (row order[p]): the off-diagonal entries of L in oci/oval[orp[p] ..
 // omid[p]), those of U in [omid[p] .. orp[p+1]), each in the row's column
-// order; U's diagonal in udiag[p].  Column indices are row numbers of A.
+// order; U's diagonal in udiag[p].  The column of an entry is given by its
+// position in the colour order too (the solves run on a work vector in that
+// order).
 struct IluFactors {
+  int64_t n;
   const int32_t* order;      // rows by colour, increasing within a colour
   const int32_t* orp;        // n+1
   const int32_t* omid;       // n
@@ -282,17 +285,20 @@ hipError_t launch_ilu_factor(const int32_t* order, int32_t begin, int32_t end, c
                              const int32_t* state, double* lu, int32_t* err, bool wave_per_row,
                              hipStream_t st);
 // The solve copies (orp, omid, oci, oval, udiag) from the factors on A's
-// pattern; lsum[c] = L entries of colour c (lsum zero on entry), usum[c] = U
-// entries (nc each).
-hipError_t launch_ilu_split(int64_t n, const int32_t* rp, const int32_t* ci, const int8_t* kind,
-                            const int32_t* diag, const double* lu, const int32_t* order,
-                            int32_t nc, const int32_t* start, int32_t* orp, int32_t* omid,
-                            int32_t* oci, double* oval, double* udiag, int32_t* lsum,
-                            int32_t* usum, int32_t* scan_tmp, hipStream_t st);
+// pattern (every row with its diagonal: nnz - n off-diagonal entries);
+// lsum[c] = L entries of colour c (lsum zero on entry), usum[c] = U entries
+// (nc each); pos (n ints) receives each row's position in the colour order.
+hipError_t launch_ilu_split(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
+                            const int8_t* kind, const int32_t* diag, const double* lu,
+                            const int32_t* order, int32_t nc, const int32_t* start, int32_t* orp,
+                            int32_t* omid, int32_t* oci, double* oval, double* udiag,
+                            int32_t* lsum, int32_t* usum, int32_t* pos, int32_t* scan_tmp,
+                            hipStream_t st);
 // Lanes per row for a colour whose rows hold `entries` off-diagonal entries
 // of the solved factor in all.
 int ilu_group(int64_t rows, int64_t entries);
-// out = M^{-1} in (VT = float when fp32), through the FP64 work vector t;
+// out = M^{-1} in (VT = float when fp32), through the FP64 work vector t
+// (n doubles, in the colour order);
 // with ctl, every launch does nothing once the inner cycle has stopped.
 hipError_t launch_ilu_apply(bool fp32, const IluFactors& f, const void* in, double* t, void* out,
                             hipStream_t st, const DevCtl* ctl = nullptr);

@@ -482,8 +482,10 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
   int32_t* oci = reinterpret_cast<int32_t*>(base + L.oci);
   double* oval = reinterpret_cast<double*>(base + L.oval);
   double* udiag = reinterpret_cast<double*>(base + L.udiag);
-  SFG_HIP(launch_ilu_split(n, A->row_ptr, A->col_idx, kind, diag, lu, order, nc, start, orp, omid,
-                           oci, oval, udiag, lsum, usum, scan_tmp, st));
+  // (the transpose's cursor array is free again and holds the positions)
+  SFG_HIP(launch_ilu_split(n, nnz, A->row_ptr, A->col_idx, kind, diag, lu, order, nc, start, orp,
+                           omid, oci, oval, udiag, lsum, usum,
+                           reinterpret_cast<int32_t*>(base + L.t_cursor), scan_tmp, st));
   std::vector<int32_t> sums(2 * (size_t)(kIluMaxColors + 1));
   SFG_HIP(hipMemcpyAsync(hv, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
   SFG_HIP(hipMemcpyAsync(sums.data(), lsum, sums.size() * 4, hipMemcpyDeviceToHost, st));
@@ -495,6 +497,7 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
     host->group[2 * c] = (int8_t)ilu_group(rows, sums[c]);
     host->group[2 * c + 1] = (int8_t)ilu_group(rows, sums[(kIluMaxColors + 1) + c]);
   }
+  F->n = n;
   F->order = order;
   F->orp = orp;
   F->omid = omid;
