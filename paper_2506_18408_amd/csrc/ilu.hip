@@ -436,18 +436,19 @@ __global__ void k_ilu_level_usum(int32_t nc, const int32_t* __restrict__ start,
     usum[c] = (orp[start[c + 1]] - orp[start[c]]) - lsum[c];
 }
 
-// One colour of the forward solve L t = t or of the backward solve U t = t,
-// in the colour order: t[p] belongs to row order[p] (the caller gathers the
-// input into that order first and scatters the result back), and the
-// entries of position p are oval/pci[s0[p] .. s1[p]) with pci the
-// positions of their columns.  The rows of a colour are then one contiguous
-// run of t, and the entries of a row point into the other colours' runs
-// near the row's own relative place, so every access streams.  G lanes per
-// row; one lane per row subtracts the products in the row's column order.
-// In place: t entries of earlier colours (forward) or later ones (backward)
-// are final.
-template <bool kForward, int G>
+// One colour of the forward solve L t = in or of the backward solve U t = t
+// (result also to out, the caller's vector type), on a work vector in the
+// colour order: t[p] belongs to row order[p], and the entries of position p
+// are oval/pci[s0[p] .. s1[p]) with pci the positions of their columns.  The
+// rows of a colour are then one contiguous run of t, and the entries of a
+// row point into the other colours' runs near the row's own relative place,
+// so the t accesses stream; only in and out are reached through order.  G
+// lanes per row; one lane per row subtracts the products in the row's
+// column order.  In place: t entries of earlier colours (forward) or later
+// ones (backward) are final.
+template <typename VT, bool kForward, int G>
 __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
+    const int32_t* __restrict__ order, const VT* __restrict__ in, VT* __restrict__ out,
     int32_t begin, int32_t end, const int32_t* __restrict__ s0, const int32_t* __restrict__ s1,
     const int32_t* __restrict__ pci, const double* __restrict__ oval,
     const double* __restrict__ udiag, double* t, const DevCtl* ctl) {
@@ -459,7 +460,7 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
   const int qa = s0[pos], qb = s1[pos];
   double acc;
   if constexpr (G == 1) {
-    acc = t[pos];
+    acc = kForward ? static_cast<double>(in[order[pos]]) : t[pos];
     // (four entries' loads in flight at once, subtracted in order)
     for (int q = qa; q < qb; q += 4) {
       const int m = qb - q;
@@ -483,31 +484,16 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
     for (int q = qa + sub; q < qb; q += G) part += oval[q] * t[pci[q]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, G);
-    acc = t[pos] - part;
+    acc = (kForward ? static_cast<double>(in[order[pos]]) : t[pos]) - part;
   }
   if (sub != 0) return;
-  t[pos] = kForward ? acc : acc / udiag[pos];
-}
-
-// t in the colour order from the input, and the result back to A's order.
-template <typename VT>
-__global__ void k_ilu_gather(int64_t n, const int32_t* __restrict__ order,
-                             const VT* __restrict__ in, double* __restrict__ t,
-                             const DevCtl* ctl) {
-  if (ctl && ctl->stop_k != 0) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
-    t[p] = static_cast<double>(in[order[p]]);
-}
-
-template <typename VT>
-__global__ void k_ilu_scatter(int64_t n, const int32_t* __restrict__ order,
-                              const double* __restrict__ t, VT* __restrict__ out,
-                              const DevCtl* ctl) {
-  if (ctl && ctl->stop_k != 0) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride)
-    out[order[p]] = static_cast<VT>(t[p]);
+  if (kForward) {
+    t[pos] = acc;
+  } else {
+    const double z = acc / udiag[pos];
+    t[pos] = z;
+    out[order[pos]] = static_cast<VT>(z);
+  }
 }
 
 // pos[order[p]] = p, then the solve copies' column indices (entries [0,
@@ -630,48 +616,44 @@ int ilu_group(int64_t rows, int64_t entries) {
   return g == 2 ? 1 : g;
 }
 
-template <bool kForward, int G>
+template <typename VT, bool kForward, int G>
 static void ilu_solve_launch(const IluFactors& f, int b, int e, const int32_t* s0,
-                             const int32_t* s1, double* t, hipStream_t st, const DevCtl* ctl) {
+                             const int32_t* s1, const VT* in, double* t, VT* out, hipStream_t st,
+                             const DevCtl* ctl) {
   const int64_t threads = (int64_t)(e - b) * G;
   const int grid = (int)((threads + kIluThreads - 1) / kIluThreads);
-  hipLaunchKernelGGL((k_ilu_solve<kForward, G>), dim3(grid), dim3(kIluThreads), 0, st, b, e, s0,
-                     s1, f.oci, f.oval, f.udiag, t, ctl);
+  hipLaunchKernelGGL((k_ilu_solve<VT, kForward, G>), dim3(grid), dim3(kIluThreads), 0, st,
+                     f.order, in, out, b, e, s0, s1, f.oci, f.oval, f.udiag, t, ctl);
 }
 
-template <bool kForward>
-static void ilu_solve_colour(const IluFactors& f, int c, double* t, hipStream_t st,
-                             const DevCtl* ctl) {
+template <typename VT, bool kForward>
+static void ilu_solve_colour(const IluFactors& f, int c, const VT* in, double* t, VT* out,
+                             hipStream_t st, const DevCtl* ctl) {
   const int b = f.level[c], e = f.level[c + 1];
   if (e <= b) return;
   const int32_t* s0 = kForward ? f.orp : f.omid;
   const int32_t* s1 = kForward ? f.omid : f.orp + 1;
   switch (f.group[2 * c + (kForward ? 0 : 1)]) {
     case 1:
-      return ilu_solve_launch<kForward, 1>(f, b, e, s0, s1, t, st, ctl);
+      return ilu_solve_launch<VT, kForward, 1>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 4:
-      return ilu_solve_launch<kForward, 4>(f, b, e, s0, s1, t, st, ctl);
+      return ilu_solve_launch<VT, kForward, 4>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 8:
-      return ilu_solve_launch<kForward, 8>(f, b, e, s0, s1, t, st, ctl);
+      return ilu_solve_launch<VT, kForward, 8>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 16:
-      return ilu_solve_launch<kForward, 16>(f, b, e, s0, s1, t, st, ctl);
+      return ilu_solve_launch<VT, kForward, 16>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 32:
-      return ilu_solve_launch<kForward, 32>(f, b, e, s0, s1, t, st, ctl);
+      return ilu_solve_launch<VT, kForward, 32>(f, b, e, s0, s1, in, t, out, st, ctl);
     default:
-      return ilu_solve_launch<kForward, 64>(f, b, e, s0, s1, t, st, ctl);
+      return ilu_solve_launch<VT, kForward, 64>(f, b, e, s0, s1, in, t, out, st, ctl);
   }
 }
 
 template <typename VT>
 static hipError_t ilu_apply_vt(const IluFactors& f, const VT* in, double* t, VT* out,
                                hipStream_t st, const DevCtl* ctl) {
-  const int64_t n = f.n;
-  hipLaunchKernelGGL((k_ilu_gather<VT>), dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n, f.order,
-                     in, t, ctl);
-  for (int c = 0; c < f.ncolors; ++c) ilu_solve_colour<true>(f, c, t, st, ctl);
-  for (int c = f.ncolors - 1; c >= 0; --c) ilu_solve_colour<false>(f, c, t, st, ctl);
-  hipLaunchKernelGGL((k_ilu_scatter<VT>), dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n, f.order,
-                     t, out, ctl);
+  for (int c = 0; c < f.ncolors; ++c) ilu_solve_colour<VT, true>(f, c, in, t, out, st, ctl);
+  for (int c = f.ncolors - 1; c >= 0; --c) ilu_solve_colour<VT, false>(f, c, in, t, out, st, ctl);
   return hipGetLastError();
 }
 

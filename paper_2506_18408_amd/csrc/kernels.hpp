@@ -255,7 +255,6 @@ inline int64_t ilu_chunks(int64_t n) { return (n + kIluChunk - 1) / kIluChunk; }
 // position in the colour order too (the solves run on a work vector in that
 // order).
 struct IluFactors {
-  int64_t n;
   const int32_t* order;      // rows by colour, increasing within a colour
   const int32_t* orp;        // n+1
   const int32_t* omid;       // n

@@ -497,7 +497,6 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
     host->group[2 * c] = (int8_t)ilu_group(rows, sums[c]);
     host->group[2 * c + 1] = (int8_t)ilu_group(rows, sums[(kIluMaxColors + 1) + c]);
   }
-  F->n = n;
   F->order = order;
   F->orp = orp;
   F->omid = omid;
