@@ -145,3 +145,45 @@ def test_ilu_option_errors():
     with warnings.catch_warnings():
         warnings.simplefilter("ignore")
         P.solve(*to_dev(B), tvec(b), **prm)
+
+
+@pytest.mark.parametrize("n", [1, 777])
+def test_ilu_of_a_diagonal_matrix_is_the_matrix(n):
+    """No off-diagonal entries: one colour, empty L and U, the factor is A
+    itself, and M^{-1} = A^{-1} solves in one inner step."""
+    d = np.random.default_rng([40, n]).uniform(1.0, 3.0, n)
+    A = W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), d)
+    lu, color = P.ilu0(*to_dev(A))
+    assert np.array_equal(color.cpu().numpy(), np.zeros(n, np.int32))
+    assert np.array_equal(lu.cpu().numpy(), d)
+    if n < 60:
+        return
+    b = np.random.default_rng([41, n]).uniform(-1.0, 1.0, n)
+    x, info = P.solve(*to_dev(A), tvec(b), precond="ilu0", m=20, t=2, s=60, zeta=8, tol=1e-12,
+                      seed=5, max_outer=5)
+    assert info["converged"] and info["outer_iters"] == 1 and list(info["inner_k"]) == [1]
+    assert np.linalg.norm(x.cpu().numpy() - b / d) <= 1e-14 * np.linalg.norm(b / d)
+
+
+def test_ilu_of_a_block_diagonal_matrix_is_exact():
+    """Independent 2 x 2 blocks: two colours, and ILU(0) without fill is
+    the exact LU, so the preconditioned solve takes one inner step."""
+    nb = 400
+    rng = np.random.default_rng(42)
+    blocks = [np.array([[rng.uniform(3, 4), rng.uniform(-1, 1)],
+                        [rng.uniform(-1, 1), rng.uniform(3, 4)]]) for _ in range(nb)]
+    S = sp.csr_matrix(sp.block_diag(blocks))
+    S.sort_indices()
+    A = W.CSR(S.shape[0], S.indptr.astype(np.int32), S.indices.astype(np.int32),
+              S.data.astype(np.float64))
+    lu, color = P.ilu0(*to_dev(A))
+    M = OI.ILU0(A.to_scipy(), "multicolor")
+    assert np.array_equal(color.cpu().numpy(), M.color)
+    assert set(np.unique(M.color)) == {0, 1}
+    assert np.allclose(lu.cpu().numpy(), M.lu, rtol=1e-14, atol=0.0)
+    b = rng.uniform(-1.0, 1.0, A.n)
+    x, info = P.solve(*to_dev(A), tvec(b), precond="ilu0", m=20, t=2, s=60, zeta=8, tol=1e-12,
+                      seed=5, max_outer=5)
+    assert info["converged"] and info["outer_iters"] == 1 and list(info["inner_k"]) == [1]
+    xe = np.linalg.solve(S.toarray(), b)
+    assert np.linalg.norm(x.cpu().numpy() - xe) <= 1e-13 * np.linalg.norm(xe)
