@@ -29,9 +29,12 @@
 // the updates from one row k spread over the lanes) that owns it.
 //
 // Triangular solves: a copy of the factors in the colour order, with the L
-// and U entries of each row contiguous, so the rows of a colour are read as
-// one stream; a group of 1..64 lanes per row, by the colour's mean row
-// length.  Vectors stay in A's numbering.
+// and U entries of each row contiguous and their columns given as positions
+// in that order, so the rows of a colour are read as one stream; a group of
+// 1..64 lanes per row, by the colour's mean row length.  They run on an FP64
+// work vector in the colour order (the rows of a colour are one contiguous
+// run of it); the caller's vectors stay in A's numbering, read by the
+// forward solve and written by the backward one through the row order.
 #include "kernels.hpp"
 
 namespace sfg {
@@ -78,12 +81,17 @@ __global__ void k_ilu_init(int64_t n, const int32_t* __restrict__ rp,
 }
 
 // One Jones-Plassmann round r: neighbours are the columns of row i of A and
-// of A^T (CSR of the transpose), the diagonal excluded.
-__global__ void k_ilu_jp_round(int64_t n, const int32_t* __restrict__ rp,
-                               const int32_t* __restrict__ ci, const int32_t* __restrict__ rpt,
-                               const int32_t* __restrict__ cit, int32_t* state, int32_t r,
-                               int32_t* colored, int32_t* err) {
+// of A^T (CSR of the transpose), the diagonal excluded.  A row's neighbour
+// states are read eight at a time (independent loads in flight together):
+// a thread per row otherwise waits one memory round trip per neighbour, and
+// the longest rows set the time of the round.
+__global__ __launch_bounds__(kIluThreads) void k_ilu_jp_round(
+    int64_t n, const int32_t* __restrict__ rp, const int32_t* __restrict__ ci,
+    const int32_t* __restrict__ rpt, const int32_t* __restrict__ cit, int32_t* state, int32_t r,
+    int32_t* colored, int32_t* err) {
+  constexpr int kB = 8;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int mine = 0;  // rows this thread coloured
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
     if (state[i] != -1) continue;
     const uint32_t pi = ilu_priority(i);
@@ -94,31 +102,40 @@ __global__ void k_ilu_jp_round(int64_t n, const int32_t* __restrict__ rp,
     for (int pass = 0; pass < 2 && is_max; ++pass) {
       const int32_t* P = pass ? rpt : rp;
       const int32_t* C = pass ? cit : ci;
-      for (int q = P[i]; q < P[i + 1]; ++q) {
-        const int j = C[q];
-        if (j == (int)i) continue;
-        if (open_at_start(state[j]) && ilu_priority(j) > pi) {
-          is_max = false;
-          break;
-        }
+      const int q1 = P[i + 1];
+      for (int q = P[i]; q < q1 && is_max; q += kB) {
+        int j[kB];
+        int32_t sj[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) j[k] = q + k < q1 ? C[q + k] : (int)i;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) sj[k] = state[j[k]];
+#pragma unroll
+        for (int k = 0; k < kB; ++k)
+          if (j[k] != (int)i && open_at_start(sj[k]) && ilu_priority(j[k]) > pi) is_max = false;
       }
     }
     if (!is_max) continue;
     // smallest colour not held by a neighbour coloured in an earlier round:
     // colours below 64 through a bit mask, then a scan per candidate
     uint64_t low = 0;
-    int cmax = -1;
     for (int pass = 0; pass < 2; ++pass) {
       const int32_t* P = pass ? rpt : rp;
       const int32_t* C = pass ? cit : ci;
-      for (int q = P[i]; q < P[i + 1]; ++q) {
-        const int j = C[q];
-        if (j == (int)i) continue;
-        const int32_t st = state[j];
-        if (open_at_start(st)) continue;
-        const int c = st & 0xFFF;
-        if (c < 64) low |= 1ull << c;
-        cmax = c > cmax ? c : cmax;
+      const int q1 = P[i + 1];
+      for (int q = P[i]; q < q1; q += kB) {
+        int j[kB];
+        int32_t sj[kB];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) j[k] = q + k < q1 ? C[q + k] : (int)i;
+#pragma unroll
+        for (int k = 0; k < kB; ++k) sj[k] = state[j[k]];
+#pragma unroll
+        for (int k = 0; k < kB; ++k) {
+          if (j[k] == (int)i || open_at_start(sj[k])) continue;
+          const int c = sj[k] & 0xFFF;
+          if (c < 64) low |= 1ull << c;
+        }
       }
     }
     int c = 0;
@@ -148,8 +165,12 @@ __global__ void k_ilu_jp_round(int64_t n, const int32_t* __restrict__ rp,
       c = kIluMaxColors - 1;
     }
     state[i] = (r << 12) | c;
-    atomicAdd(colored, 1);
+    ++mine;
   }
+  // (one atomic per wave)
+#pragma unroll
+  for (int off = kWave / 2; off > 0; off >>= 1) mine += __shfl_xor(mine, off, kWave);
+  if ((threadIdx.x & (kWave - 1)) == 0 && mine > 0) atomicAdd(colored, mine);
 }
 
 // Rows per colour: a histogram per workgroup in LDS, added to cnt once.
@@ -533,8 +554,10 @@ hipError_t launch_ilu_init(int64_t n, const int32_t* rp, const int32_t* ci, cons
 hipError_t launch_ilu_jp_round(int64_t n, const int32_t* rp, const int32_t* ci,
                                const int32_t* rpt, const int32_t* cit, int32_t* state,
                                int32_t round, int32_t* colored, int32_t* err, hipStream_t st) {
-  hipLaunchKernelGGL(k_ilu_jp_round, dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n, rp, ci, rpt,
-                     cit, state, round, colored, err);
+  // (a thread per row: the rows of a round wait on memory, not on issue)
+  const int64_t g = (n + kIluThreads - 1) / kIluThreads;
+  hipLaunchKernelGGL(k_ilu_jp_round, dim3((int)(g < 65535 ? (g > 0 ? g : 1) : 65535)),
+                     dim3(kIluThreads), 0, st, n, rp, ci, rpt, cit, state, round, colored, err);
   return hipGetLastError();
 }
 

@@ -451,11 +451,15 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
   // (the globally highest-priority uncoloured vertex colours itself in every
   // round, so at most n rounds; the round number sits above the 12 colour bits)
   const int64_t max_rounds = std::min<int64_t>(n + 1, (int64_t)1 << 19);
+  // (four rounds per look at the counters: a round after the last one
+  // changes nothing)
   int64_t r = 0;
-  for (;; ++r) {
+  for (;;) {
     if (r >= max_rounds) return fail(h, SFGMRES_ERR_INVALID, "ILU colouring did not finish");
-    SFG_HIP(launch_ilu_jp_round(n, A->row_ptr, A->col_idx, trp, tci, state, (int32_t)r, colored,
-                                err, st));
+    const int64_t burst = std::min<int64_t>(4, max_rounds - r);
+    for (int64_t k = 0; k < burst; ++k, ++r)
+      SFG_HIP(launch_ilu_jp_round(n, A->row_ptr, A->col_idx, trp, tci, state, (int32_t)r,
+                                  colored, err, st));
     SFG_HIP(hipMemcpyAsync(hv, err, 2 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     SFG_HIP(hipStreamSynchronize(st));
     if (hv[1] >= n || hv[0]) break;
