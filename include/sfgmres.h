@@ -151,7 +151,10 @@ typedef struct sfgmres_options {
                                    level per colour); the inner cycle works on A M^{-1} and
                                    z_j = M^{-1} B_k y_k, so residuals stay b - A x.  Built on
                                    the device at the start of every solve (of A^T for the
-                                   adjoint).  SFGMRES_ERR_INVALID for unsorted columns or a
+                                   adjoint), factored in float64; with precision MIXED the
+                                   triangular solves read a float32 copy of the factor values
+                                   (products and sums in float64), like the matrix in the
+                                   inner SpMV.  SFGMRES_ERR_INVALID for unsorted columns or a
                                    missing diagonal entry, SFGMRES_ERR_BREAKDOWN for a zero
                                    pivot                                                          */
   int32_t mid_outer;            /* 0 (default): one sGMRES cycle per outer step.  N > 0: two-level

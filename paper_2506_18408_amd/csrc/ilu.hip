@@ -396,13 +396,14 @@ __global__ void k_ilu_split_count(int64_t n, const int32_t* __restrict__ rp,
   }
 }
 
+template <typename FT>
 __global__ void k_ilu_split_fill(int64_t n, const int32_t* __restrict__ rp,
                                  const int32_t* __restrict__ ci, const int8_t* __restrict__ kind,
                                  const int32_t* __restrict__ diag, const double* __restrict__ lu,
                                  const int32_t* __restrict__ order,
                                  const int32_t* __restrict__ orp, int32_t* __restrict__ omid,
-                                 int32_t* __restrict__ oci, double* __restrict__ oval,
-                                 double* __restrict__ udiag) {
+                                 int32_t* __restrict__ oci, FT* __restrict__ oval,
+                                 FT* __restrict__ udiag) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; p < n; p += stride) {
     const int i = order[p];
@@ -411,17 +412,17 @@ __global__ void k_ilu_split_fill(int64_t n, const int32_t* __restrict__ rp,
     for (int q = q0; q < q1; ++q)
       if (kind[q] == -1) {
         oci[o] = ci[q];
-        oval[o] = lu[q];
+        oval[o] = static_cast<FT>(lu[q]);
         ++o;
       }
     omid[p] = o;
     for (int q = q0; q < q1; ++q)
       if (kind[q] == 1) {
         oci[o] = ci[q];
-        oval[o] = lu[q];
+        oval[o] = static_cast<FT>(lu[q]);
         ++o;
       }
-    udiag[p] = lu[diag[i]];
+    udiag[p] = static_cast<FT>(lu[diag[i]]);
   }
 }
 
@@ -466,13 +467,14 @@ __global__ void k_ilu_level_usum(int32_t nc, const int32_t* __restrict__ start,
 // so the t accesses stream; only in and out are reached through order.  G
 // lanes per row; one lane per row subtracts the products in the row's
 // column order.  In place: t entries of earlier colours (forward) or later
-// ones (backward) are final.
-template <typename VT, bool kForward, int G>
+// ones (backward) are final.  Factor values of type FT (FP32 copies in mixed
+// precision), every product and sum in FP64.
+template <typename VT, typename FT, bool kForward, int G>
 __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
     const int32_t* __restrict__ order, const VT* __restrict__ in, VT* __restrict__ out,
     int32_t begin, int32_t end, const int32_t* __restrict__ s0, const int32_t* __restrict__ s1,
-    const int32_t* __restrict__ pci, const double* __restrict__ oval,
-    const double* __restrict__ udiag, double* t, const DevCtl* ctl) {
+    const int32_t* __restrict__ pci, const FT* __restrict__ oval,
+    const FT* __restrict__ udiag, double* t, const DevCtl* ctl) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t pos = begin + gid / G;
   const int sub = (int)(gid % G);
@@ -486,7 +488,8 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
     for (int q = qa; q < qb; q += 4) {
       const int m = qb - q;
       int c[4];
-      double v[4], tv[4];
+      FT v[4];
+      double tv[4];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k < m) {
@@ -498,11 +501,11 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
         if (k < m) tv[k] = t[c[k]];
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (k < m) acc -= v[k] * tv[k];
+        if (k < m) acc -= static_cast<double>(v[k]) * tv[k];
     }
   } else {
     double part = 0.0;
-    for (int q = qa + sub; q < qb; q += G) part += oval[q] * t[pci[q]];
+    for (int q = qa + sub; q < qb; q += G) part += static_cast<double>(oval[q]) * t[pci[q]];
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, G);
     acc = (kForward ? static_cast<double>(in[order[pos]]) : t[pos]) - part;
@@ -511,7 +514,7 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
   if (kForward) {
     t[pos] = acc;
   } else {
-    const double z = acc / udiag[pos];
+    const double z = acc / static_cast<double>(udiag[pos]);
     t[pos] = z;
     out[order[pos]] = static_cast<VT>(z);
   }
@@ -608,15 +611,21 @@ hipError_t launch_ilu_factor(const int32_t* order, int32_t begin, int32_t end, c
 hipError_t launch_ilu_split(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
                             const int8_t* kind, const int32_t* diag, const double* lu,
                             const int32_t* order, int32_t nc, const int32_t* start, int32_t* orp,
-                            int32_t* omid, int32_t* oci, double* oval, double* udiag,
-                            int32_t* lsum, int32_t* usum, int32_t* pos, int32_t* scan_tmp,
-                            hipStream_t st) {
+                            int32_t* omid, int32_t* oci, void* oval, void* udiag,
+                            bool fp32_factors, int32_t* lsum, int32_t* usum, int32_t* pos,
+                            int32_t* scan_tmp, hipStream_t st) {
   hipLaunchKernelGGL(k_ilu_split_count, dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n, rp, order,
                      orp);
   const hipError_t e = launch_exclusive_scan(orp, n, scan_tmp, st);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_ilu_split_fill, dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n, rp, ci,
-                     kind, diag, lu, order, orp, omid, oci, oval, udiag);
+  if (fp32_factors)
+    hipLaunchKernelGGL(k_ilu_split_fill<float>, dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n,
+                       rp, ci, kind, diag, lu, order, orp, omid, oci, static_cast<float*>(oval),
+                       static_cast<float*>(udiag));
+  else
+    hipLaunchKernelGGL(k_ilu_split_fill<double>, dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n,
+                       rp, ci, kind, diag, lu, order, orp, omid, oci, static_cast<double*>(oval),
+                       static_cast<double*>(udiag));
   // (every row holds its diagonal: nnz - n off-diagonal entries)
   hipLaunchKernelGGL(k_ilu_pos, dim3(ilu_grid(n)), dim3(kIluThreads), 0, st, n, order, pos);
   hipLaunchKernelGGL(k_ilu_pci, dim3(ilu_grid(nnz - n)), dim3(kIluThreads), 0, st, nnz - n, pos,
@@ -639,17 +648,18 @@ int ilu_group(int64_t rows, int64_t entries) {
   return g == 2 ? 1 : g;
 }
 
-template <typename VT, bool kForward, int G>
+template <typename VT, typename FT, bool kForward, int G>
 static void ilu_solve_launch(const IluFactors& f, int b, int e, const int32_t* s0,
                              const int32_t* s1, const VT* in, double* t, VT* out, hipStream_t st,
                              const DevCtl* ctl) {
   const int64_t threads = (int64_t)(e - b) * G;
   const int grid = (int)((threads + kIluThreads - 1) / kIluThreads);
-  hipLaunchKernelGGL((k_ilu_solve<VT, kForward, G>), dim3(grid), dim3(kIluThreads), 0, st,
-                     f.order, in, out, b, e, s0, s1, f.oci, f.oval, f.udiag, t, ctl);
+  hipLaunchKernelGGL((k_ilu_solve<VT, FT, kForward, G>), dim3(grid), dim3(kIluThreads), 0, st,
+                     f.order, in, out, b, e, s0, s1, f.oci, static_cast<const FT*>(f.oval),
+                     static_cast<const FT*>(f.udiag), t, ctl);
 }
 
-template <typename VT, bool kForward>
+template <typename VT, typename FT, bool kForward>
 static void ilu_solve_colour(const IluFactors& f, int c, const VT* in, double* t, VT* out,
                              hipStream_t st, const DevCtl* ctl) {
   const int b = f.level[c], e = f.level[c + 1];
@@ -658,35 +668,41 @@ static void ilu_solve_colour(const IluFactors& f, int c, const VT* in, double* t
   const int32_t* s1 = kForward ? f.omid : f.orp + 1;
   switch (f.group[2 * c + (kForward ? 0 : 1)]) {
     case 1:
-      return ilu_solve_launch<VT, kForward, 1>(f, b, e, s0, s1, in, t, out, st, ctl);
+      return ilu_solve_launch<VT, FT, kForward, 1>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 4:
-      return ilu_solve_launch<VT, kForward, 4>(f, b, e, s0, s1, in, t, out, st, ctl);
+      return ilu_solve_launch<VT, FT, kForward, 4>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 8:
-      return ilu_solve_launch<VT, kForward, 8>(f, b, e, s0, s1, in, t, out, st, ctl);
+      return ilu_solve_launch<VT, FT, kForward, 8>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 16:
-      return ilu_solve_launch<VT, kForward, 16>(f, b, e, s0, s1, in, t, out, st, ctl);
+      return ilu_solve_launch<VT, FT, kForward, 16>(f, b, e, s0, s1, in, t, out, st, ctl);
     case 32:
-      return ilu_solve_launch<VT, kForward, 32>(f, b, e, s0, s1, in, t, out, st, ctl);
+      return ilu_solve_launch<VT, FT, kForward, 32>(f, b, e, s0, s1, in, t, out, st, ctl);
     default:
-      return ilu_solve_launch<VT, kForward, 64>(f, b, e, s0, s1, in, t, out, st, ctl);
+      return ilu_solve_launch<VT, FT, kForward, 64>(f, b, e, s0, s1, in, t, out, st, ctl);
   }
 }
 
-template <typename VT>
+template <typename VT, typename FT>
 static hipError_t ilu_apply_vt(const IluFactors& f, const VT* in, double* t, VT* out,
                                hipStream_t st, const DevCtl* ctl) {
-  for (int c = 0; c < f.ncolors; ++c) ilu_solve_colour<VT, true>(f, c, in, t, out, st, ctl);
-  for (int c = f.ncolors - 1; c >= 0; --c) ilu_solve_colour<VT, false>(f, c, in, t, out, st, ctl);
+  for (int c = 0; c < f.ncolors; ++c) ilu_solve_colour<VT, FT, true>(f, c, in, t, out, st, ctl);
+  for (int c = f.ncolors - 1; c >= 0; --c)
+    ilu_solve_colour<VT, FT, false>(f, c, in, t, out, st, ctl);
   return hipGetLastError();
 }
 
 hipError_t launch_ilu_apply(bool fp32, const IluFactors& f, const void* in, double* t, void* out,
                             hipStream_t st, const DevCtl* ctl) {
-  if (fp32)
-    return ilu_apply_vt<float>(f, static_cast<const float*>(in), t, static_cast<float*>(out), st,
-                               ctl);
-  return ilu_apply_vt<double>(f, static_cast<const double*>(in), t, static_cast<double*>(out), st,
-                              ctl);
+  const float* fi = static_cast<const float*>(in);
+  const double* di = static_cast<const double*>(in);
+  float* fo = static_cast<float*>(out);
+  double* dout = static_cast<double*>(out);
+  if (f.fp32)
+    return fp32 ? ilu_apply_vt<float, float>(f, fi, t, fo, st, ctl)
+                : ilu_apply_vt<double, float>(f, di, t, dout, st, ctl);
+  // (FP64 factors serve FP64 vectors only)
+  if (fp32) return hipErrorInvalidValue;
+  return ilu_apply_vt<double, double>(f, di, t, dout, st, ctl);
 }
 
 }  // namespace sfg

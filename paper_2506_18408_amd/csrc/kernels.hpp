@@ -259,11 +259,12 @@ struct IluFactors {
   const int32_t* orp;        // n+1
   const int32_t* omid;       // n
   const int32_t* oci;
-  const double* oval;
-  const double* udiag;
+  const void* oval;          // FP32 when fp32, else FP64
+  const void* udiag;
   const int32_t* level;      // host: order[level[c] .. level[c+1]) has colour c
   const int8_t* group;       // host: lanes per row in colour c, [2c] for L and [2c+1] for U
   int32_t ncolors;
+  bool fp32;                 // FP32 copies of the values (mixed precision)
 };
 hipError_t launch_ilu_init(int64_t n, const int32_t* rp, const int32_t* ci, const double* val,
                            double* lu, int32_t* diag, int32_t* state, int32_t* err,
@@ -290,14 +291,14 @@ hipError_t launch_ilu_factor(const int32_t* order, int32_t begin, int32_t end, c
 hipError_t launch_ilu_split(int64_t n, int64_t nnz, const int32_t* rp, const int32_t* ci,
                             const int8_t* kind, const int32_t* diag, const double* lu,
                             const int32_t* order, int32_t nc, const int32_t* start, int32_t* orp,
-                            int32_t* omid, int32_t* oci, double* oval, double* udiag,
-                            int32_t* lsum, int32_t* usum, int32_t* pos, int32_t* scan_tmp,
-                            hipStream_t st);
+                            int32_t* omid, int32_t* oci, void* oval, void* udiag,
+                            bool fp32_factors, int32_t* lsum, int32_t* usum, int32_t* pos,
+                            int32_t* scan_tmp, hipStream_t st);
 // Lanes per row for a colour whose rows hold `entries` off-diagonal entries
 // of the solved factor in all.
 int ilu_group(int64_t rows, int64_t entries);
 // out = M^{-1} in (VT = float when fp32), through the FP64 work vector t
-// (n doubles, in the colour order);
+// (n doubles, in the colour order); FP32 vectors need the FP32 factors;
 // with ctl, every launch does nothing once the inner cycle has stopped.
 hipError_t launch_ilu_apply(bool fp32, const IluFactors& f, const void* in, double* t, void* out,
                             hipStream_t st, const DevCtl* ctl = nullptr);

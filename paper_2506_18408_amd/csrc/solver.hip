@@ -417,9 +417,10 @@ struct IluHost {
 // pattern, the transposed pattern, Jones-Plassmann rounds until every row
 // is coloured, rows grouped by colour (level starts read back to the
 // host), the factorisation one colour at a time, and the copies of the
-// factors in the colour order for the triangular solves.
+// factors in the colour order for the triangular solves (their values in
+// FP32 when fp32: the mixed-precision solves read those).
 int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L,
-              hipStream_t st, IluFactors* F, IluHost* host) {
+              hipStream_t st, IluFactors* F, IluHost* host, bool fp32) {
   const int64_t n = A->n, nnz = A->nnz;
   double* lu = reinterpret_cast<double*>(base + L.lu);
   int8_t* kind = reinterpret_cast<int8_t*>(base + L.kind);
@@ -484,11 +485,11 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
   int32_t* orp = reinterpret_cast<int32_t*>(base + L.orp);
   int32_t* omid = reinterpret_cast<int32_t*>(base + L.omid);
   int32_t* oci = reinterpret_cast<int32_t*>(base + L.oci);
-  double* oval = reinterpret_cast<double*>(base + L.oval);
-  double* udiag = reinterpret_cast<double*>(base + L.udiag);
+  void* oval = base + L.oval;
+  void* udiag = base + L.udiag;
   // (the transpose's cursor array is free again and holds the positions)
   SFG_HIP(launch_ilu_split(n, nnz, A->row_ptr, A->col_idx, kind, diag, lu, order, nc, start, orp,
-                           omid, oci, oval, udiag, lsum, usum,
+                           omid, oci, oval, udiag, fp32, lsum, usum,
                            reinterpret_cast<int32_t*>(base + L.t_cursor), scan_tmp, st));
   std::vector<int32_t> sums(2 * (size_t)(kIluMaxColors + 1));
   SFG_HIP(hipMemcpyAsync(hv, err, sizeof(int32_t), hipMemcpyDeviceToHost, st));
@@ -510,6 +511,7 @@ int ilu_setup(sfgmres_handle h, const sfgmres_csr* A, char* base, const IluWs& L
   F->level = lev.data();
   F->group = host->group.data();
   F->ncolors = nc;
+  F->fp32 = fp32;
   return SFGMRES_OK;
 }
 
@@ -634,7 +636,7 @@ int solve_impl(sfgmres_handle h, const sfgmres_csr* A, const double* b, const do
     if (shared_ilu) {
       F = *shared_ilu;
     } else {
-      rc = ilu_setup(h, A, base, ilu_regions(n, nnz, L.ilu), st, &F, &ilu_host);
+      rc = ilu_setup(h, A, base, ilu_regions(n, nnz, L.ilu), st, &F, &ilu_host, f32);
       if (rc) return rc;
     }
   }
@@ -1549,7 +1551,7 @@ int sfgmres_ilu0(sfgmres_handle h, const sfgmres_csr* A, double* lu, int32_t* co
   const IluWs W = ilu_regions(A->n, A->nnz, 0);
   IluFactors F{};
   IluHost host;
-  const int rc = ilu_setup(h, A, base, W, st, &F, &host);
+  const int rc = ilu_setup(h, A, base, W, st, &F, &host, false);
   if (rc) return rc;
   SFG_HIP(hipMemcpyAsync(lu, base + W.lu, (size_t)A->nnz * 8, hipMemcpyDeviceToDevice, st));
   SFG_HIP(launch_ilu_colors(A->n, reinterpret_cast<const int32_t*>(base + W.state), color, st));
