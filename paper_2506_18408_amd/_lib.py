@@ -165,7 +165,7 @@ def load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build the HIP library first "
-            "(python -c 'import __graft_entry__ as g; g.build()')")
+            "(python -m paper_2506_18408_amd.build)")
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
