@@ -187,3 +187,34 @@ def test_ilu_of_a_block_diagonal_matrix_is_exact():
     assert info["converged"] and info["outer_iters"] == 1 and list(info["inner_k"]) == [1]
     xe = np.linalg.solve(S.toarray(), b)
     assert np.linalg.norm(x.cpu().numpy() - xe) <= 1e-13 * np.linalg.norm(xe)
+
+
+def test_ilu_zero_pivot_is_a_breakdown():
+    """A zero pivot, met as a divisor or left on U's diagonal, is reported as
+    a breakdown by the factorisation and by a preconditioned solve (the
+    oracle's factorisation stops on the same pivot)."""
+    rng = np.random.default_rng(43)
+    good = [np.array([[4.0, rng.uniform(-1, 1)], [rng.uniform(-1, 1), 4.0]]) for _ in range(50)]
+    S = sp.csr_matrix(sp.block_diag(good[:20] + [np.ones((2, 2))] + good[20:]))
+    S.sort_indices()
+    n = 100
+    d = np.r_[np.full(40, 2.0), 0.0, np.full(59, 2.0)]
+    cases = {
+        # rows (40, 41) = [[1, 1], [1, 1]]: u = 1 - 1 * 1 = 0 on the second one
+        "eliminated_to_zero": W.CSR(S.shape[0], S.indptr.astype(np.int32),
+                                    S.indices.astype(np.int32), S.data.astype(np.float64)),
+        # an explicit zero on the diagonal of a row nothing depends on
+        "zero_diagonal": W.CSR(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32),
+                               d),
+    }
+    for name, A in cases.items():
+        with pytest.raises(ZeroDivisionError):
+            OI.ILU0(A.to_scipy(), "multicolor")
+        with pytest.raises(P.SFGMRESError) as e:
+            P.ilu0(*to_dev(A))
+        assert e.value.code == L.ERR_BREAKDOWN, name
+        b = np.ones(A.n)
+        with pytest.raises(P.SFGMRESError) as e:
+            P.solve(*to_dev(A), tvec(b), precond="ilu0", m=20, t=2, s=60, zeta=8, tol=1e-8,
+                    seed=5, max_outer=5)
+        assert e.value.code == L.ERR_BREAKDOWN, name
