@@ -60,3 +60,23 @@ def test_two_level_with_ilu_matches_the_oracle():
     assert list(info["inner_k"]) == ref.inner_k
     hist_close(info["residual_history"], ref.residual_history)
     assert np.linalg.norm(x.cpu().numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
+
+
+def test_two_level_with_ilu_mixed_precision_reaches_tol():
+    """The mixed-precision lower levels share the top level's factors (their
+    FP32 copy for the cycles' FP32 vectors, the same copy for the FP64
+    inner solutions)."""
+    A, b = _sys()
+    prm = dict(m=12, t=2, s=48, zeta=8, tol=1e-8, seed=21, max_outer=60)
+    rp, ci, va = to_dev(A)
+    x64, i64 = P.solve(rp, ci, va, tvec(b), mid_outer=3, precond="ilu0", **prm)
+    xm, im = P.solve(rp, ci, va, tvec(b), mid_outer=3, precond="ilu0", precision="mixed", **prm)
+    assert i64["converged"] and im["converged"]
+    assert im["true_rel_residual"] <= 1e-8 * (1 + 1e-6)
+    # both within their residuals of the solution: ||x_m - x_64|| / ||x|| is at
+    # most cond(A) (r_m + r_64) / (1 - cond(A) r_64) in relative terms
+    kappa = np.linalg.cond(A.to_scipy().toarray())
+    rm, r64 = im["true_rel_residual"], i64["true_rel_residual"]
+    xs, xr = xm.cpu().numpy(), x64.cpu().numpy()
+    bound = kappa * (rm + r64) / (1.0 - kappa * r64)
+    assert np.linalg.norm(xs - xr) <= bound * np.linalg.norm(xr)
