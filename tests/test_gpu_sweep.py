@@ -91,3 +91,30 @@ def test_random_case_matches_the_oracle(case):
     hist_close(info["residual_history"], ref.residual_history)
     xs = x.cpu().numpy()
     assert np.linalg.norm(xs - ref.x) <= 1e-9 * np.linalg.norm(ref.x), what
+
+
+@pytest.mark.filterwarnings("ignore:sfgmres")
+@pytest.mark.parametrize("case", range(0, NCASES, 2))
+def test_random_case_adjoint_matches_the_oracle(case):
+    """The adjoint solve A^T lam = g of the same cases (the transpose built
+    on the device, its own ILU(0) when preconditioned), against the oracle
+    on A^T with the same forced dimensions; dL/dA from the GPU's lam and x
+    equals the product formula exactly."""
+    rng = np.random.default_rng([2506, 18408, case])
+    A, b, kind = _random_system(rng)
+    prm, forced, precond, src, fmt = _random_options(rng)
+    g = np.random.default_rng([2506, 18409, case]).uniform(-1.0, 1.0, A.n)
+    xv = np.random.default_rng([2506, 18410, case]).uniform(-1.0, 1.0, A.n)
+    lam, gv, info = P.solve_adjoint(*to_dev(A), tvec(g), tvec(xv), forced_k=forced,
+                                    precond=precond, sketch_source=src, matrix_format=fmt, **prm)
+    rpT, ciT, vT, _ = oracle.transpose_csr(A.row_ptr, A.col_idx, A.val, A.n)
+    AT = sp.csr_matrix((vT, ciT, rpT), shape=(A.n, A.n))
+    M = OI.ILU0(AT, "multicolor") if precond == "ilu0" else None
+    ref = oracle.sfgmres(AT, g, forced_k=forced, precond=M, **prm)
+    what = (case, A.n, kind, prm, forced, precond, src, fmt)
+    assert list(info["inner_k"]) == list(ref.inner_k), what
+    hist_close(info["residual_history"], ref.residual_history)
+    lr = lam.cpu().numpy()
+    assert np.linalg.norm(lr - ref.x) <= 1e-9 * np.linalg.norm(ref.x), what
+    want = oracle.adjoint_gradient(A.row_ptr, A.col_idx, lr, xv)
+    assert np.array_equal(gv.cpu().numpy(), want), what
