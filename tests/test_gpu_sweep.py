@@ -118,3 +118,26 @@ def test_random_case_adjoint_matches_the_oracle(case):
     assert np.linalg.norm(lr - ref.x) <= 1e-9 * np.linalg.norm(ref.x), what
     want = oracle.adjoint_gradient(A.row_ptr, A.col_idx, lr, xv)
     assert np.array_equal(gv.cpu().numpy(), want), what
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precond", ["none", "ilu0"])
+@pytest.mark.parametrize("fmt", ["auto", "csr"])
+@pytest.mark.parametrize("n", [1, 2, 3])
+def test_smallest_systems_solve(n, fmt, precond, precision):
+    """Systems of one to three unknowns: one tile with most lanes idle, a
+    matrix by diagonal of one to three diagonals, a one- or two-colour ILU;
+    the Krylov space is exhausted within the first cycle (an exact breakdown
+    of the Arnoldi recurrence at the latest after n steps)."""
+    rng = np.random.default_rng([77, n])
+    D = np.diag(rng.uniform(2.0, 3.0, n)) + (np.triu(rng.uniform(-0.5, 0.5, (n, n)), 1)
+                                             + np.tril(rng.uniform(-0.5, 0.5, (n, n)), -1))
+    S = sp.csr_matrix(D)
+    A = W.CSR(n, S.indptr.astype(np.int32), S.indices.astype(np.int32), S.data.astype(np.float64))
+    b = rng.uniform(-1.0, 1.0, n)
+    m = n + 1
+    x, info = P.solve(*to_dev(A), tvec(b), m=m, t=1, s=m + 2, zeta=1, tol=1e-12, seed=3,
+                      max_outer=10, precond=precond, matrix_format=fmt, precision=precision)
+    assert info["converged"], info
+    xe = np.linalg.solve(D, b)
+    assert np.linalg.norm(x.cpu().numpy() - xe) <= 1e-10 * np.linalg.norm(xe)
