@@ -153,7 +153,8 @@ typedef struct sfgmres_options {
                                    the device at the start of every solve (of A^T for the
                                    adjoint), factored in float64; with precision MIXED the
                                    triangular solves read a float32 copy of the factor values
-                                   (products and sums in float64), like the matrix in the
+                                   and keep their intermediate vector in float32 (products and
+                                   sums in float64), like the matrix and the vectors of the
                                    inner SpMV.  SFGMRES_ERR_INVALID for unsorted columns or a
                                    missing diagonal entry, SFGMRES_ERR_BREAKDOWN for a zero
                                    pivot                                                          */

@@ -31,10 +31,11 @@
 // Triangular solves: a copy of the factors in the colour order, with the L
 // and U entries of each row contiguous and their columns given as positions
 // in that order, so the rows of a colour are read as one stream; a group of
-// 1..64 lanes per row, by the colour's mean row length.  They run on an FP64
-// work vector in the colour order (the rows of a colour are one contiguous
-// run of it); the caller's vectors stay in A's numbering, read by the
-// forward solve and written by the backward one through the row order.
+// 1..64 lanes per row, by the colour's mean row length.  They run on a work
+// vector in the colour order, of the caller's vector type (the rows of a
+// colour are one contiguous run of it); the caller's vectors stay in A's
+// numbering, read by the forward solve and written by the backward one
+// through the row order.
 #include "kernels.hpp"
 
 namespace sfg {
@@ -459,8 +460,8 @@ __global__ void k_ilu_level_usum(int32_t nc, const int32_t* __restrict__ start,
 }
 
 // One colour of the forward solve L t = in or of the backward solve U t = t
-// (result also to out, the caller's vector type), on a work vector in the
-// colour order: t[p] belongs to row order[p], and the entries of position p
+// (result also to out), on a work vector of the caller's vector type VT in
+// the colour order: t[p] belongs to row order[p], and the entries of position p
 // are oval/pci[s0[p] .. s1[p]) with pci the positions of their columns.  The
 // rows of a colour are then one contiguous run of t, and the entries of a
 // row point into the other colours' runs near the row's own relative place,
@@ -468,13 +469,14 @@ __global__ void k_ilu_level_usum(int32_t nc, const int32_t* __restrict__ start,
 // lanes per row; one lane per row subtracts the products in the row's
 // column order.  In place: t entries of earlier colours (forward) or later
 // ones (backward) are final.  Factor values of type FT (FP32 copies in mixed
-// precision), every product and sum in FP64.
+// precision), every product and sum in FP64; each row's result is stored
+// rounded to VT, as the inner SpMV stores its output.
 template <typename VT, typename FT, bool kForward, int G>
 __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
     const int32_t* __restrict__ order, const VT* __restrict__ in, VT* __restrict__ out,
     int32_t begin, int32_t end, const int32_t* __restrict__ s0, const int32_t* __restrict__ s1,
     const int32_t* __restrict__ pci, const FT* __restrict__ oval,
-    const FT* __restrict__ udiag, double* t, const DevCtl* ctl) {
+    const FT* __restrict__ udiag, VT* t, const DevCtl* ctl) {
   const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t pos = begin + gid / G;
   const int sub = (int)(gid % G);
@@ -483,7 +485,7 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
   const int qa = s0[pos], qb = s1[pos];
   double acc;
   if constexpr (G == 1) {
-    acc = kForward ? static_cast<double>(in[order[pos]]) : t[pos];
+    acc = kForward ? static_cast<double>(in[order[pos]]) : static_cast<double>(t[pos]);
     // (four entries' loads in flight at once, subtracted in order)
     for (int q = qa; q < qb; q += 4) {
       const int m = qb - q;
@@ -498,24 +500,24 @@ __global__ __launch_bounds__(kIluThreads) void k_ilu_solve(
         }
 #pragma unroll
       for (int k = 0; k < 4; ++k)
-        if (k < m) tv[k] = t[c[k]];
+        if (k < m) tv[k] = static_cast<double>(t[c[k]]);
 #pragma unroll
       for (int k = 0; k < 4; ++k)
         if (k < m) acc -= static_cast<double>(v[k]) * tv[k];
     }
   } else {
     double part = 0.0;
-    for (int q = qa + sub; q < qb; q += G) part += static_cast<double>(oval[q]) * t[pci[q]];
+    for (int q = qa + sub; q < qb; q += G) part += static_cast<double>(oval[q]) * static_cast<double>(t[pci[q]]);
 #pragma unroll
     for (int off = G / 2; off > 0; off >>= 1) part += __shfl_xor(part, off, G);
-    acc = (kForward ? static_cast<double>(in[order[pos]]) : t[pos]) - part;
+    acc = (kForward ? static_cast<double>(in[order[pos]]) : static_cast<double>(t[pos])) - part;
   }
   if (sub != 0) return;
   if (kForward) {
-    t[pos] = acc;
+    t[pos] = static_cast<VT>(acc);
   } else {
     const double z = acc / static_cast<double>(udiag[pos]);
-    t[pos] = z;
+    t[pos] = static_cast<VT>(z);
     out[order[pos]] = static_cast<VT>(z);
   }
 }
@@ -656,7 +658,7 @@ static void ilu_solve_launch(const IluFactors& f, int b, int e, const int32_t* s
   const int grid = (int)((threads + kIluThreads - 1) / kIluThreads);
   hipLaunchKernelGGL((k_ilu_solve<VT, FT, kForward, G>), dim3(grid), dim3(kIluThreads), 0, st,
                      f.order, in, out, b, e, s0, s1, f.oci, static_cast<const FT*>(f.oval),
-                     static_cast<const FT*>(f.udiag), t, ctl);
+                     static_cast<const FT*>(f.udiag), reinterpret_cast<VT*>(t), ctl);
 }
 
 template <typename VT, typename FT, bool kForward>

@@ -297,8 +297,9 @@ hipError_t launch_ilu_split(int64_t n, int64_t nnz, const int32_t* rp, const int
 // Lanes per row for a colour whose rows hold `entries` off-diagonal entries
 // of the solved factor in all.
 int ilu_group(int64_t rows, int64_t entries);
-// out = M^{-1} in (VT = float when fp32), through the FP64 work vector t
-// (n doubles, in the colour order); FP32 vectors need the FP32 factors;
+// out = M^{-1} in (VT = float when fp32), through the work vector t (room
+// for n doubles, used as n values of VT, in the colour order); FP32 vectors
+// need the FP32 factors;
 // with ctl, every launch does nothing once the inner cycle has stopped.
 hipError_t launch_ilu_apply(bool fp32, const IluFactors& f, const void* in, double* t, void* out,
                             hipStream_t st, const DevCtl* ctl = nullptr);
